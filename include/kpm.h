@@ -1,0 +1,217 @@
+/*
+ * kpm.h -- C ABI of the MI355X (gfx950) kernel polynomial method library.
+ *
+ * The library estimates the density of states (DOS) of a real symmetric
+ * sparse matrix A with the kernel polynomial method (KPM) as described by
+ * Lin, Saad & Yang, "Approximating spectral densities of large matrices"
+ * (SIAM Review 58(1), 2016; arXiv:1308.5467), section 3.1.1 and Appendix A.
+ * The problem statement is that of Algorithm 1: given A, evaluation points
+ * and a degree M, return the approximate DOS at those points.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - All functions return a kpm_status; nothing is thrown across the ABI.
+ *    On failure a message is available from kpm_last_error(ctx).
+ *  - Small arrays (moments, damping factors, points, outputs) are HOST
+ *    pointers owned by the caller.  The call copies what it needs and has
+ *    written every output when it returns (it synchronises its stream).
+ *  - The sparse matrix is passed as a borrowed kpm_csr.  With on_device = 1
+ *    its arrays are device pointers on the context's device and are used in
+ *    place for the duration of the call; with on_device = 0 they are host
+ *    pointers and are copied into context-owned device memory.
+ *  - A context owns a HIP stream reference, grow-only device workspace and
+ *    the damping network's weights.  One context must not be used from two
+ *    threads at once.
+ *  - Moments are normalised:  mu[k] = zeta_k / n  with
+ *    zeta_k = (1/nvec) sum_l v_l^T T_k(B) v_l   (eqs. (nuk), (muEst)),
+ *    B = (A - cI)/d, c = (lb+ub)/2, d = (ub-lb)/2  (eq. (cd)).  Hence
+ *    mu[0] = 1, and the (2 - delta_k0)/pi factor of eq. (expmu) is applied
+ *    inside kpm_dos / kpm_dos_bins.
+ *  - Probe vectors are Rademacher vectors: entry i of probe vector l is -1
+ *    when the top bit of output number ((l << 32) | i) + 1 of the SplitMix64
+ *    sequence started from `seed` is set, +1 otherwise.  They satisfy the
+ *    condition E[v] = 0, E[v v^T] = I of Theorem 1.
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KPM_OK = 0,
+    KPM_ERR_ARG = -1,         /* invalid argument or malformed CSR            */
+    KPM_ERR_ALLOC = -2,       /* device allocation failed                     */
+    KPM_ERR_HIP = -3,         /* a HIP runtime call failed                    */
+    KPM_ERR_SPECTRUM = -4,    /* spectrum escaped [lb, ub]: |zeta_k| > n or non-finite */
+    KPM_ERR_NOCONV = -5,      /* eigen-solver of the Lanczos matrix did not converge */
+    KPM_ERR_UNSUPPORTED = -6, /* option combination not supported             */
+    KPM_ERR_NOMODEL = -7      /* learned damping requested but no weights set  */
+} kpm_status;
+
+typedef struct kpm_ctx kpm_ctx;
+
+/* Borrowed CSR matrix.  Columns must be sorted and unique within a row;
+ * the matrix must be symmetric (not checked on the hot path). */
+typedef struct {
+    int64_t n;               /* rows = columns, 1 <= n < 2^31                */
+    int64_t nnz;             /* stored entries, row_ptr[n]                    */
+    const int32_t* row_ptr;  /* [n + 1], row_ptr[0] = 0, non-decreasing       */
+    const int32_t* col_idx;  /* [nnz], 0 <= col < n                           */
+    const void* val;         /* [nnz] float (val_is_f64 = 0) or double (= 1) */
+    int32_t val_is_f64;
+    int32_t on_device;       /* 1: device pointers; 0: host pointers          */
+} kpm_csr;
+
+enum {
+    KPM_FP32 = 0, /* FP32 matrix values and vectors, FP32 SpMM products,
+                     FP64 recurrence combination and FP64 dot products      */
+    KPM_FP64 = 1  /* FP64 everywhere                                       */
+};
+
+typedef struct {
+    int32_t M;          /* degree: moments mu_0 .. mu_M are returned, M >= 0   */
+    int32_t nvec;       /* number of probe vectors, >= 1                       */
+    int32_t block;      /* probe vectors per device block, 0 = library choice;
+                           at most 256 (FP32) or 128 (FP64)                    */
+    int32_t precision;  /* KPM_FP32 or KPM_FP64                                */
+    uint64_t seed;      /* probe-vector seed                                   */
+    int32_t validate;   /* 1: check the CSR structure and values first          */
+    int32_t rows_per_block; /* row-panel height per workgroup, 0 = library choice */
+} kpm_moment_opts;
+
+typedef enum {
+    KPM_DAMP_NONE = 0,    /* g_k = 1                                            */
+    KPM_DAMP_JACKSON = 1, /* Jackson factors, Appendix A eq. (jackson)          */
+    KPM_DAMP_LEARNED = 2  /* damping network (requires weights, M = 127)        */
+} kpm_damping;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+kpm_status kpm_create(int device, void* hip_stream, kpm_ctx** out);
+kpm_status kpm_destroy(kpm_ctx* ctx);
+/* Change the stream later calls enqueue on. */
+kpm_status kpm_set_stream(kpm_ctx* ctx, void* hip_stream);
+/* Message of the last failure on this context ("" if none); valid until the next call. */
+const char* kpm_last_error(const kpm_ctx* ctx);
+
+/*
+ * kpm_bounds -- lower and upper bounds of the spectrum of A (section 3.1.1,
+ * the paragraph after eq. (cd)).  Runs `steps` Lanczos steps in FP64 on the
+ * device (start vector: probe vector 2^31 - 1 of `seed`, normalised; two
+ * passes of full re-orthogonalisation per step), takes the extreme Ritz
+ * values theta_1, theta_k of the tridiagonal matrix and widens each by its
+ * residual norm beta_k |z_{k,j}|.  On breakdown the Gershgorin hull is merged
+ * in.  The interval [lb0, ub0] is finally widened so that it maps into
+ * [-(1 - margin), 1 - margin]:  c = (lb0+ub0)/2,  d = (ub0-lb0)/(2(1-margin)),
+ * d >= margin * max(|c|, 1);  *lb = c - d,  *ub = c + d.
+ * steps in [1, 32] (capped at n); margin in [0, 0.5).
+ */
+kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_t seed,
+                      double margin, double* lb, double* ub);
+
+/*
+ * kpm_moments -- normalised stochastic Chebyshev moments mu[0..M] of
+ * B = (A - cI)/d (Algorithm 1; eqs. (nuk), (3term), (muEst)), using the
+ * product identity T_{p+q} = 2 T_p T_q - T_{|p-q|} (Appendix A) so that
+ * ceil(M/2) sparse products per probe block give all M+1 moments:
+ *   zeta_{2k}   = 2 v_k^T v_k     - zeta_0,
+ *   zeta_{2k+1} = 2 v_{k+1}^T v_k - zeta_1.
+ * mu:          host [M+1], written.
+ * mu_per_vec:  host [nvec * (M+1)] or NULL; row l holds v_l^T T_k(B) v_l / n.
+ * Returns KPM_ERR_SPECTRUM (after writing the outputs) when a per-vector
+ * moment is non-finite or exceeds 1 in magnitude beyond rounding, i.e. the
+ * spectrum of A is not inside [lb, ub].
+ */
+kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
+                       const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
+
+/*
+ * kpm_moments_batched -- the same for nmat independent matrices of uneven
+ * size in one persistent launch per call (work queue over all matrices,
+ * vector blocks and row panels, with per-matrix step ordering), optionally
+ * replayed from a captured HIP graph.  lb, ub: host [nmat].  All matrices
+ * share opts (M, nvec, block, precision, seed); matrix m uses probe vectors
+ * of seed opts->seed + m.  mu: host [nmat * (M+1)].
+ * A[m].on_device must be 1 for every m.
+ */
+kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
+                               const double* ub, const kpm_moment_opts* opts, double* mu);
+
+/*
+ * kpm_damping_factors -- damping factors g[0..M] (host, written).
+ * KPM_DAMP_NONE: all ones.  KPM_DAMP_JACKSON: eq. (jackson) of Appendix A.
+ * KPM_DAMP_LEARNED: the damping network applied to mu[0..127] (host, M must
+ * be 127); g[0] = 1.
+ */
+kpm_status kpm_damping_factors(kpm_ctx* ctx, kpm_damping kind, int M, const double* mu, double* g);
+
+/*
+ * kpm_dos -- approximate DOS of A at npts points x (host) into phi (host):
+ *   phi(x) = [g_0 mu_0 + 2 sum_{k>=1} g_k mu_k T_k(t)] / (pi d sqrt(1 - t^2)),
+ *   t = (x - c)/d   (eq. (tdosFinal) with eq. (expmu)'s factor and the damping
+ * of Appendix A; the 1/d converts the density of B into that of A).
+ * phi = 0 where |t| >= 1.
+ */
+kpm_status kpm_dos(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb, double ub,
+                   const double* x, int npts, double* phi);
+
+/*
+ * kpm_dos_bins -- mass of the same density over [edges[i], edges[i+1]],
+ * i < nbins (edges host [nbins+1], increasing), integrated exactly term by
+ * term in theta = arccos t.  A histogram estimate of eq. (DOS1) / n.
+ */
+kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb,
+                        double ub, const double* edges, int nbins, double* mass);
+
+/*
+ * kpm_rademacher -- fill a device block out[i * ld + j] (i < n, j < nvec)
+ * with probe vectors vec0 .. vec0+nvec-1 of `seed` as float (precision
+ * KPM_FP32) or double (KPM_FP64).  Columns nvec .. ld-1 are left untouched.
+ */
+kpm_status kpm_rademacher(kpm_ctx* ctx, uint64_t seed, int64_t vec0, int nvec, int64_t n,
+                          int64_t ld, int precision, void* out_device);
+
+/* ---- learned damping network (128 -> 256 -> 256 -> 128, GELU, sigmoid) ----
+ * Parameters are one FP32 array in the order W1[128x256], b1[256],
+ * W2[256x256], b2[256], W3[256x128], b3[128] (row-major, input index first):
+ * kpm_mlp_param_count() floats in total. */
+int64_t kpm_mlp_param_count(void);
+kpm_status kpm_mlp_set_params(kpm_ctx* ctx, const float* params);
+kpm_status kpm_mlp_get_params(kpm_ctx* ctx, float* params);
+/* Forward pass: x host [N x 128] (moments) -> g host [N x 128]. */
+kpm_status kpm_mlp_forward(kpm_ctx* ctx, int N, const float* x, float* g);
+/* Loss (mean over the batch of the L1 distance between the blurred damped
+ * KPM density and `target` on npts = 200 midpoints of [-1, 1], Gaussian
+ * width sigma in B's units) and its gradient with respect to every
+ * parameter, in the parameter order above.  grads host [param_count]. */
+kpm_status kpm_mlp_loss_grad(kpm_ctx* ctx, int N, const float* x, const float* target,
+                             float sigma, float* loss, float* grads);
+/* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `epochs` passes of
+ * minibatches of `batch` samples in a seeded order; loss_per_epoch host
+ * [epochs] or NULL.  Starts from the current parameters (kpm_mlp_init first
+ * for a fresh network). */
+kpm_status kpm_mlp_train(kpm_ctx* ctx, int N, const float* x, const float* target, float sigma,
+                         int epochs, int batch, float lr, uint64_t seed, float* loss_per_epoch);
+/* Fresh parameters: fan-in scaled Rademacher-signed weights, zero biases. */
+kpm_status kpm_mlp_init(kpm_ctx* ctx, uint64_t seed);
+/* Save / load the parameters as raw little-endian FP32 behind a 16-byte header. */
+kpm_status kpm_mlp_save(kpm_ctx* ctx, const char* path);
+kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path);
+
+/* ---- device timing of the library's own kernels ----
+ * When enabled, every launch of the listed kernels is bracketed by HIP
+ * events on the context's stream.  kernel: "cheb_step" (fused recurrence
+ * step, the dominant kernel), "cheb_first", "lanczos", "batched". */
+kpm_status kpm_profile_enable(kpm_ctx* ctx, int enable);
+kpm_status kpm_profile_query(kpm_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
+kpm_status kpm_profile_reset(kpm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPM_H */

@@ -1,0 +1,359 @@
+"""Python binding of libkpm.so, the MI355X kernel polynomial method library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libkpm.so``.  PyTorch is used for device memory (matrices
+uploaded with :class:`DeviceCSR`) and for the HIP stream handle.  If the
+library is not built this module raises on first use; there is no fallback.
+
+The functions carry the C names of ``include/kpm.h`` (``kpm_bounds``,
+``kpm_moments``, ``kpm_dos`` ...) and take a :class:`Context`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpm.so")
+
+KPM_FP32, KPM_FP64 = 0, 1
+KPM_DAMP_NONE, KPM_DAMP_JACKSON, KPM_DAMP_LEARNED = 0, 1, 2
+STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP",
+          -4: "KPM_ERR_SPECTRUM", -5: "KPM_ERR_NOCONV", -6: "KPM_ERR_UNSUPPORTED",
+          -7: "KPM_ERR_NOMODEL"}
+
+# Every symbol include/kpm.h declares.
+EXPORTS = [
+    "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
+    "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
+    "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
+    "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
+    "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset",
+]
+
+
+class KpmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class kpm_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("val_is_f64", ctypes.c_int32),
+                ("on_device", ctypes.c_int32)]
+
+
+class kpm_moment_opts(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("nvec", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("validate", ctypes.c_int32),
+                ("rows_per_block", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1308_5467_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "kpm_create": ([I32, P, P], I32),
+        "kpm_destroy": ([P], I32),
+        "kpm_set_stream": ([P, P], I32),
+        "kpm_last_error": ([P], ctypes.c_char_p),
+        "kpm_bounds": ([P, P, I32, U64, D, P, P], I32),
+        "kpm_moments": ([P, P, D, D, P, P, P], I32),
+        "kpm_moments_batched": ([P, I32, P, P, P, P, P], I32),
+        "kpm_damping_factors": ([P, I32, I32, P, P], I32),
+        "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_rademacher": ([P, U64, I64, I32, I64, I64, I32, P], I32),
+        "kpm_mlp_param_count": ([], I64),
+        "kpm_mlp_set_params": ([P, P], I32),
+        "kpm_mlp_get_params": ([P, P], I32),
+        "kpm_mlp_forward": ([P, I32, P, P], I32),
+        "kpm_mlp_loss_grad": ([P, I32, P, P, ctypes.c_float, P, P], I32),
+        "kpm_mlp_train": ([P, I32, P, P, ctypes.c_float, I32, I32, ctypes.c_float, U64, P], I32),
+        "kpm_mlp_init": ([P, U64], I32),
+        "kpm_mlp_save": ([P, ctypes.c_char_p], I32),
+        "kpm_mlp_load": ([P, ctypes.c_char_p], I32),
+        "kpm_profile_enable": ([P, I32], I32),
+        "kpm_profile_query": ([P, ctypes.c_char_p, P, P], I32),
+        "kpm_profile_reset": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Matrices
+# --------------------------------------------------------------------------
+@dataclass
+class DeviceCSR:
+    """CSR matrix in device memory (torch tensors own the storage)."""
+
+    n: int
+    row_ptr: "object"
+    col_idx: "object"
+    val: "object"
+
+    @classmethod
+    def from_host(cls, n, row_ptr, col_idx, val, dtype="f32", device="cuda:0") -> "DeviceCSR":
+        import torch
+        tdt = torch.float32 if dtype in ("f32", "float32", KPM_FP32) else torch.float64
+        rp = torch.as_tensor(np.ascontiguousarray(row_ptr, dtype=np.int32)).to(device)
+        ci = torch.as_tensor(np.ascontiguousarray(col_idx, dtype=np.int32)).to(device)
+        va = torch.as_tensor(np.ascontiguousarray(val)).to(device=device, dtype=tdt)
+        return cls(int(n), rp, ci, va)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def as_c(self) -> kpm_csr:
+        import torch
+        return kpm_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                       self.val.data_ptr(), 1 if self.val.dtype == torch.float64 else 0, 1)
+
+
+@dataclass
+class HostCSR:
+    """CSR matrix in host memory (copied into the context on each call)."""
+
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    val: np.ndarray
+
+    def __post_init__(self):
+        self.row_ptr = np.ascontiguousarray(self.row_ptr, dtype=np.int32)
+        self.col_idx = np.ascontiguousarray(self.col_idx, dtype=np.int32)
+        if self.val.dtype not in (np.float32, np.float64):
+            self.val = self.val.astype(np.float64)
+        self.val = np.ascontiguousarray(self.val)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.size)
+
+    def as_c(self) -> kpm_csr:
+        return kpm_csr(self.n, self.nnz, _p(self.row_ptr), _p(self.col_idx), _p(self.val),
+                       1 if self.val.dtype == np.float64 else 0, 0)
+
+
+# --------------------------------------------------------------------------
+# Context and entry points
+# --------------------------------------------------------------------------
+class Context:
+    """A library context on one device, enqueueing on one HIP stream."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.lib = load_library()
+        if stream is None:
+            import torch
+            torch.cuda.set_device(device)
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.handle = ctypes.c_void_p()
+        st = self.lib.kpm_create(device, ctypes.c_void_p(stream), ctypes.byref(self.handle))
+        if st != 0:
+            raise KpmError(st, "kpm_create failed")
+
+    def check(self, st: int):
+        if st != 0:
+            raise KpmError(st, self.lib.kpm_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            self.lib.kpm_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kpm_create(device: int = 0, stream: int | None = None) -> Context:
+    return Context(device, stream)
+
+
+def kpm_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def kpm_set_stream(ctx: Context, stream: int) -> None:
+    ctx.check(ctx.lib.kpm_set_stream(ctx.handle, ctypes.c_void_p(stream)))
+
+
+def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 0.01):
+    lb, ub = ctypes.c_double(), ctypes.c_double()
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_bounds(ctx.handle, ctypes.byref(c), steps, seed, margin,
+                                 ctypes.byref(lb), ctypes.byref(ub)))
+    return lb.value, ub.value
+
+
+def _opts(M, nvec, seed, precision, block, validate, rows_per_block) -> kpm_moment_opts:
+    prec = KPM_FP64 if precision in ("f64", "float64", KPM_FP64) else KPM_FP32
+    return kpm_moment_opts(M, nvec, block, prec, seed & (2**64 - 1), 1 if validate else 0, rows_per_block)
+
+
+def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
+                precision="f32", block: int = 0, validate: bool = True, per_vector: bool = False,
+                rows_per_block: int = 0):
+    """Normalised moments mu[0..M]; with per_vector=True also [nvec, M+1] per-probe moments."""
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block)
+    mu = np.zeros(M + 1)
+    pv = np.zeros((nvec, M + 1)) if per_vector else None
+    c = A.as_c()
+    st = ctx.lib.kpm_moments(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), _p(mu),
+                             _p(pv) if pv is not None else None)
+    ctx.check(st)
+    return (mu, pv) if per_vector else mu
+
+
+def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",
+                        block: int = 0, validate: bool = False):
+    o = _opts(M, nvec, seed, precision, block, validate, 0)
+    arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+    lbv, ubv = _f64(lb), _f64(ub)
+    mu = np.zeros((len(mats), M + 1))
+    ctx.check(ctx.lib.kpm_moments_batched(ctx.handle, len(mats), arr, _p(lbv), _p(ubv),
+                                          ctypes.byref(o), _p(mu)))
+    return mu
+
+
+def kpm_damping_factors(ctx: Context, kind: int, M: int, mu=None) -> np.ndarray:
+    g = np.zeros(M + 1)
+    mu_a = _f64(mu) if mu is not None else None
+    ctx.check(ctx.lib.kpm_damping_factors(ctx.handle, kind, M, _p(mu_a) if mu_a is not None else None, _p(g)))
+    return g
+
+
+def kpm_dos(ctx: Context, mu, g, lb: float, ub: float, x) -> np.ndarray:
+    mu, g, x = _f64(mu), _f64(g), _f64(x)
+    phi = np.zeros(x.size)
+    ctx.check(ctx.lib.kpm_dos(ctx.handle, _p(mu), _p(g), mu.size - 1, lb, ub, _p(x), x.size, _p(phi)))
+    return phi
+
+
+def kpm_dos_bins(ctx: Context, mu, g, lb: float, ub: float, edges) -> np.ndarray:
+    mu, g, e = _f64(mu), _f64(g), _f64(edges)
+    mass = np.zeros(max(e.size - 1, 0))
+    ctx.check(ctx.lib.kpm_dos_bins(ctx.handle, _p(mu), _p(g), mu.size - 1, lb, ub, _p(e), mass.size, _p(mass)))
+    return mass
+
+
+def kpm_rademacher(ctx: Context, seed: int, vec0: int, nvec: int, n: int, ld: int, precision, out) -> None:
+    """Fill device tensor ``out`` ([n, ld] row-major) with probe vectors."""
+    prec = KPM_FP64 if precision in ("f64", "float64", KPM_FP64) else KPM_FP32
+    ctx.check(ctx.lib.kpm_rademacher(ctx.handle, seed, vec0, nvec, n, ld, prec, ctypes.c_void_p(out.data_ptr())))
+
+
+# ---- damping network -------------------------------------------------------
+def kpm_mlp_param_count() -> int:
+    return int(load_library().kpm_mlp_param_count())
+
+
+def kpm_mlp_set_params(ctx: Context, params) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == kpm_mlp_param_count()
+    ctx.check(ctx.lib.kpm_mlp_set_params(ctx.handle, _p(p)))
+
+
+def kpm_mlp_get_params(ctx: Context) -> np.ndarray:
+    p = np.zeros(kpm_mlp_param_count(), dtype=np.float32)
+    ctx.check(ctx.lib.kpm_mlp_get_params(ctx.handle, _p(p)))
+    return p
+
+
+def kpm_mlp_init(ctx: Context, seed: int) -> None:
+    ctx.check(ctx.lib.kpm_mlp_init(ctx.handle, seed))
+
+
+def kpm_mlp_forward(ctx: Context, x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    g = np.zeros_like(x)
+    ctx.check(ctx.lib.kpm_mlp_forward(ctx.handle, x.shape[0], _p(x), _p(g)))
+    return g
+
+
+def kpm_mlp_loss_grad(ctx: Context, x, target, sigma: float):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(target, dtype=np.float32)
+    loss = ctypes.c_float()
+    grads = np.zeros(kpm_mlp_param_count(), dtype=np.float32)
+    ctx.check(ctx.lib.kpm_mlp_loss_grad(ctx.handle, x.shape[0], _p(x), _p(t), sigma, ctypes.byref(loss), _p(grads)))
+    return loss.value, grads
+
+
+def kpm_mlp_train(ctx: Context, x, target, sigma: float, epochs: int, batch: int, lr: float, seed: int):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(target, dtype=np.float32)
+    losses = np.zeros(epochs, dtype=np.float32)
+    ctx.check(ctx.lib.kpm_mlp_train(ctx.handle, x.shape[0], _p(x), _p(t), sigma, epochs, batch, lr, seed, _p(losses)))
+    return losses
+
+
+def kpm_mlp_save(ctx: Context, path: str) -> None:
+    ctx.check(ctx.lib.kpm_mlp_save(ctx.handle, path.encode()))
+
+
+def kpm_mlp_load(ctx: Context, path: str) -> None:
+    ctx.check(ctx.lib.kpm_mlp_load(ctx.handle, path.encode()))
+
+
+# ---- device timing -------------------------------------------------------
+def kpm_profile_enable(ctx: Context, enable: bool = True) -> None:
+    ctx.check(ctx.lib.kpm_profile_enable(ctx.handle, 1 if enable else 0))
+
+
+def kpm_profile_query(ctx: Context, kernel: str):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    ctx.check(ctx.lib.kpm_profile_query(ctx.handle, kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+def kpm_profile_reset(ctx: Context) -> None:
+    ctx.check(ctx.lib.kpm_profile_reset(ctx.handle))
+
+
+# MLP parameter layout (matches include/kpm.h)
+MLP_SHAPES = [("W1", (128, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+              ("W3", (256, 128)), ("b3", (128,))]
+
+
+def mlp_pack(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).reshape(-1) for k, _ in MLP_SHAPES])
+
+
+def mlp_unpack(flat) -> dict:
+    out, off = {}, 0
+    for k, shp in MLP_SHAPES:
+        sz = int(np.prod(shp))
+        out[k] = np.asarray(flat[off:off + sz]).reshape(shp)
+        off += sz
+    return out

@@ -1,0 +1,545 @@
+// C ABI of the KPM library: context, workspace, argument checking and the
+// host side of each entry point.  Every numerical step runs in the device
+// kernels of this library; the host only orders launches, moves small
+// arrays and solves the Lanczos tridiagonal eigenproblem (at most 32 x 32).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "kpm_internal.h"
+
+using namespace kpm;
+
+// ---------------------------------------------------------------- context helpers
+kpm_status kpm_fail(kpm_ctx* ctx, kpm_status st, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+kpm_status kpm_hip_fail(kpm_ctx* ctx, hipError_t e, const char* what) {
+    std::string m = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+    return kpm_fail(ctx, KPM_ERR_HIP, m);
+}
+
+kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out) {
+    kpm_dev_buf& b = ctx->bufs[role];
+    if (bytes == 0) bytes = 256;
+    if (b.cap < bytes) {
+        if (b.p) {
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return kpm_hip_fail(ctx, e, "hipStreamSynchronize (workspace)");
+            hipFree(b.p);
+            b.p = nullptr;
+            b.cap = 0;
+        }
+        size_t cap = (bytes + 4095) / 4096 * 4096;
+        hipError_t e = hipMalloc(&b.p, cap);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            return kpm_fail(ctx, KPM_ERR_ALLOC,
+                            std::string("hipMalloc of ") + std::to_string(cap) + " bytes for " + role + " failed");
+        }
+        b.cap = cap;
+    }
+    *out = b.p;
+    return KPM_OK;
+}
+
+void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) {
+    if (!ctx->prof) return;
+    kpm_prof_entry& e = ctx->prof_map[kernel];
+    if (e.used + 2 > e.ev.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) return;
+            e.ev.push_back(ev);
+        }
+    }
+    hipEventRecord(e.ev[e.used], ctx->stream);
+}
+
+void kpm_prof_end(kpm_ctx* ctx, const char* kernel) {
+    if (!ctx->prof) return;
+    kpm_prof_entry& e = ctx->prof_map[kernel];
+    if (e.used + 2 > e.ev.size()) return;
+    hipEventRecord(e.ev[e.used + 1], ctx->stream);
+    e.used += 2;
+}
+
+void kpm_prof_collect(kpm_ctx* ctx) {
+    for (auto& kv : ctx->prof_map) {
+        kpm_prof_entry& e = kv.second;
+        for (size_t i = 0; i + 1 < e.used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.ev[i], e.ev[i + 1]) == hipSuccess) {
+                e.total_ms += ms;
+                e.launches += 1;
+            }
+        }
+        e.used = 0;
+    }
+}
+
+static kpm_status sync(kpm_ctx* ctx) {
+    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    kpm_prof_collect(ctx);
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- CSR intake
+static kpm_status check_csr_args(kpm_ctx* ctx, const kpm_csr* A) {
+    if (!A) return kpm_fail(ctx, KPM_ERR_ARG, "matrix is NULL");
+    if (A->n < 1 || A->n >= ((int64_t)1 << 31))
+        return kpm_fail(ctx, KPM_ERR_ARG, "n must be in [1, 2^31)");
+    if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31))
+        return kpm_fail(ctx, KPM_ERR_ARG, "nnz must be in [0, 2^31)");
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+        return kpm_fail(ctx, KPM_ERR_ARG, "CSR array pointer is NULL");
+    return KPM_OK;
+}
+
+// Device view of A; host arrays are copied into the context, FP64 values are
+// rounded to FP32 when the FP32 path is requested.
+static kpm_status prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, CsrDev* out,
+                              const char* tag = "") {
+    kpm_status st = check_csr_args(ctx, A);
+    if (st != KPM_OK) return st;
+    CsrDev D;
+    D.n = (int32_t)A->n;
+    D.nnz = (int32_t)A->nnz;
+    D.val_f64 = A->val_is_f64 ? 1 : 0;
+    const size_t vbytes = (size_t)A->nnz * (A->val_is_f64 ? 8 : 4);
+    if (A->on_device) {
+        D.rp = A->row_ptr;
+        D.ci = A->col_idx;
+        D.val = A->val;
+    } else {
+        void *rp, *ci, *va;
+        std::string t(tag);
+        if ((st = kpm_ws(ctx, ("csr_rp" + t).c_str(), (size_t)(A->n + 1) * 4, &rp)) != KPM_OK) return st;
+        if ((st = kpm_ws(ctx, ("csr_ci" + t).c_str(), (size_t)A->nnz * 4, &ci)) != KPM_OK) return st;
+        if ((st = kpm_ws(ctx, ("csr_val" + t).c_str(), vbytes, &va)) != KPM_OK) return st;
+        KPM_HIP(ctx, hipMemcpyAsync(rp, A->row_ptr, (size_t)(A->n + 1) * 4, hipMemcpyHostToDevice, ctx->stream));
+        if (A->nnz > 0) {
+            KPM_HIP(ctx, hipMemcpyAsync(ci, A->col_idx, (size_t)A->nnz * 4, hipMemcpyHostToDevice, ctx->stream));
+            KPM_HIP(ctx, hipMemcpyAsync(va, A->val, vbytes, hipMemcpyHostToDevice, ctx->stream));
+        }
+        D.rp = (const int32_t*)rp;
+        D.ci = (const int32_t*)ci;
+        D.val = va;
+    }
+    if (precision == KPM_FP32 && D.val_f64) {
+        void* v32;
+        if ((st = kpm_ws(ctx, (std::string("csr_val32") + tag).c_str(), (size_t)A->nnz * 4, &v32)) != KPM_OK)
+            return st;
+        if (A->nnz > 0) KPM_HIP(ctx, launch_convert_f64_to_f32(ctx->stream, (const double*)D.val, (float*)v32, A->nnz));
+        D.val = v32;
+        D.val_f64 = 0;
+    }
+    *out = D;
+    return KPM_OK;
+}
+
+static kpm_status validate_csr(kpm_ctx* ctx, const CsrDev& D) {
+    void* f;
+    kpm_status st = kpm_ws(ctx, "flags", 64, &f);
+    if (st != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemsetAsync(f, 0, 16, ctx->stream));
+    KPM_HIP(ctx, launch_validate_csr(ctx->stream, D, (int*)f));
+    int flags[4] = {0, 0, 0, 0};
+    KPM_HIP(ctx, hipMemcpyAsync(flags, f, 16, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    if (flags[0]) return kpm_fail(ctx, KPM_ERR_ARG, "row_ptr is not a valid CSR row pointer");
+    if (flags[1]) return kpm_fail(ctx, KPM_ERR_ARG, "col_idx out of range or not strictly increasing within a row");
+    if (flags[2]) return kpm_fail(ctx, KPM_ERR_ARG, "matrix values are not all finite");
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- create / destroy
+extern "C" kpm_status kpm_create(int device, void* hip_stream, kpm_ctx** out) {
+    if (!out) return KPM_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return KPM_ERR_HIP;
+    if (device < 0 || device >= count) return KPM_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return KPM_ERR_HIP;
+    kpm_ctx* ctx = new kpm_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    *out = ctx;
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
+    if (!ctx) return KPM_ERR_ARG;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->bufs)
+        if (kv.second.p) hipFree(kv.second.p);
+    if (ctx->mlp_params.p) hipFree(ctx->mlp_params.p);
+    for (auto& kv : ctx->prof_map)
+        for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
+    delete ctx;
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_set_stream(kpm_ctx* ctx, void* hip_stream) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return KPM_OK;
+}
+
+extern "C" const char* kpm_last_error(const kpm_ctx* ctx) {
+    if (!ctx) return "context is NULL";
+    return ctx->err.c_str();
+}
+
+// ---------------------------------------------------------------- tridiagonal eigenproblem
+// Cyclic Jacobi rotations on the dense symmetric m x m matrix (m <= 32):
+// eigenvalues in w (ascending) and eigenvectors as columns of Z (row-major).
+static bool jacobi_eigen(int m, std::vector<double> A, std::vector<double>& w, std::vector<double>& Z) {
+    Z.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+    double norm = 0.0;
+    for (double x : A) norm += x * x;
+    bool converged = false;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) off += A[(size_t)p * m + q] * A[(size_t)p * m + q];
+        if (off <= 1e-34 * norm || off == 0.0) {
+            converged = true;
+            break;
+        }
+        for (int p = 0; p < m; ++p) {
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = A[(size_t)p * m + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < m; ++k) {  // columns p, q
+                    const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - s * akq;
+                    A[(size_t)k * m + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < m; ++k) {  // rows p, q
+                    const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - s * aqk;
+                    A[(size_t)q * m + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double zkp = Z[(size_t)k * m + p], zkq = Z[(size_t)k * m + q];
+                    Z[(size_t)k * m + p] = c * zkp - s * zkq;
+                    Z[(size_t)k * m + q] = s * zkp + c * zkq;
+                }
+            }
+        }
+    }
+    w.resize(m);
+    for (int i = 0; i < m; ++i) w[i] = A[(size_t)i * m + i];
+    // sort ascending, permuting eigenvector columns
+    std::vector<int> idx(m);
+    for (int i = 0; i < m; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] < w[b]; });
+    std::vector<double> w2(m), Z2((size_t)m * m);
+    for (int j = 0; j < m; ++j) {
+        w2[j] = w[idx[j]];
+        for (int k = 0; k < m; ++k) Z2[(size_t)k * m + j] = Z[(size_t)k * m + idx[j]];
+    }
+    w.swap(w2);
+    Z.swap(Z2);
+    return converged;
+}
+
+// ---------------------------------------------------------------- bounds
+extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed,
+                                 double margin, double* lb, double* ub) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!lb || !ub) return kpm_fail(ctx, KPM_ERR_ARG, "lb/ub output is NULL");
+    if (steps < 1 || steps > 32) return kpm_fail(ctx, KPM_ERR_ARG, "steps must be in [1, 32]");
+    if (!(margin >= 0.0 && margin < 0.5)) return kpm_fail(ctx, KPM_ERR_ARG, "margin must be in [0, 0.5)");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    CsrDev A;
+    kpm_status st = prepare_csr(ctx, Ain, KPM_FP64, &A);
+    if (st != KPM_OK) return st;
+    const int n = A.n;
+    const int m = std::min(steps, n);
+    LanczosWork W;
+    W.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
+    void *Q, *w, *coef, *part;
+    if ((st = kpm_ws(ctx, "lz_Q", (size_t)m * n * 8, &Q)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lz_w", (size_t)n * 8, &w)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lz_coef", 256 * 8, &coef)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lz_part", (size_t)W.nblk * 32 * 8 + 2 * 8 * 1024, &part)) != KPM_OK) return st;
+    W.Q = (double*)Q;
+    W.w = (double*)w;
+    W.coef = (double*)coef;
+    W.partial = (double*)part;
+    KPM_HIP(ctx, hipMemsetAsync(coef, 0, 256 * 8, ctx->stream));
+    kpm_prof_begin(ctx, "lanczos");
+    KPM_HIP(ctx, launch_lanczos(ctx->stream, A, m, seed, W));
+    kpm_prof_end(ctx, "lanczos");
+    std::vector<double> hc(256);
+    KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    // Breakdown test in step order: stop at the first residual below 1e-12 of
+    // the largest coefficient seen so far.
+    double scale = 0.0, beta_last = 0.0;
+    int k = m;
+    bool breakdown = false;
+    for (int j = 0; j < m; ++j) {
+        const double a = hc[j], b = hc[64 + j];
+        if (!isfinite(a) || !isfinite(b))
+            return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
+        scale = std::max(scale, std::max(fabs(a), b));
+        if (j == m - 1) {
+            beta_last = b;
+            break;
+        }
+        if (b <= 1e-12 * scale) {
+            breakdown = true;
+            beta_last = b;
+            k = j + 1;
+            break;
+        }
+    }
+    std::vector<double> T((size_t)k * k, 0.0), theta, Z;
+    for (int j = 0; j < k; ++j) {
+        T[(size_t)j * k + j] = hc[j];
+        if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = hc[64 + j];
+    }
+    if (!jacobi_eigen(k, T, theta, Z))
+        return kpm_fail(ctx, KPM_ERR_NOCONV, "Jacobi iteration on the Lanczos matrix did not converge");
+    const double rlo = beta_last * fabs(Z[(size_t)(k - 1) * k + 0]);
+    const double rhi = beta_last * fabs(Z[(size_t)(k - 1) * k + (k - 1)]);
+    double lb0 = theta[0] - rlo, ub0 = theta[k - 1] + rhi;
+    if (breakdown) {
+        const int gb = W.nblk;
+        double* gout = (double*)part + (size_t)W.nblk * 32;
+        KPM_HIP(ctx, launch_gershgorin(ctx->stream, A, gout, gb));
+        std::vector<double> hg(2 * gb);
+        KPM_HIP(ctx, hipMemcpyAsync(hg.data(), gout, 2 * gb * 8, hipMemcpyDeviceToHost, ctx->stream));
+        if ((st = sync(ctx)) != KPM_OK) return st;
+        for (int b = 0; b < gb; ++b) {
+            lb0 = std::min(lb0, hg[2 * b]);
+            ub0 = std::max(ub0, hg[2 * b + 1]);
+        }
+    }
+    const double c = 0.5 * (lb0 + ub0);
+    double d = 0.5 * (ub0 - lb0) / (1.0 - margin);
+    d = std::max(d, margin * std::max(fabs(c), 1.0));
+    if (!(d > 0.0)) d = 1e-300 > d ? 1.0 : d;
+    *lb = c - d;
+    *ub = c + d;
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- moments
+static int default_block(int nvec, int precision) {
+    const int maxb = precision == KPM_FP64 ? 128 : 256;
+    return std::min(nvec, std::min(maxb, 64));
+}
+
+extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
+                                  const kpm_moment_opts* o, double* mu, double* mu_per_vec) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!o || !mu) return kpm_fail(ctx, KPM_ERR_ARG, "opts or mu is NULL");
+    if (o->M < 0 || o->M > (1 << 20)) return kpm_fail(ctx, KPM_ERR_ARG, "M must be in [0, 2^20]");
+    if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
+    if (o->precision != KPM_FP32 && o->precision != KPM_FP64)
+        return kpm_fail(ctx, KPM_ERR_ARG, "precision must be KPM_FP32 or KPM_FP64");
+    const int maxb = o->precision == KPM_FP64 ? 128 : 256;
+    if (o->block < 0 || o->block > maxb) return kpm_fail(ctx, KPM_ERR_ARG, "block out of range");
+    if (o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
+        return kpm_fail(ctx, KPM_ERR_ARG, "rows_per_block out of range");
+    if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    CsrDev A;
+    kpm_status st = prepare_csr(ctx, Ain, o->precision, &A);
+    if (st != KPM_OK) return st;
+    if (o->validate && (st = validate_csr(ctx, A)) != KPM_OK) return st;
+
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    const double alpha = 2.0 / d, beta = -2.0 * c / d;
+    const int M = o->M, nvec = o->nvec;
+    const int b = o->block > 0 ? std::min(o->block, nvec) : default_block(nvec, o->precision);
+    const int K = (M + 1) / 2;  // ceil(M/2) sparse products per block
+    const int esz = o->precision == KPM_FP64 ? 8 : 4;
+    BlockGeom g = make_geom(A.n, b, o->precision, o->rows_per_block);
+
+    void *X0, *X1, *part, *dots, *zeta, *mud;
+    const size_t vbytes = (size_t)A.n * g.ld * esz;
+    if ((st = kpm_ws(ctx, "X0", vbytes, &X0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X1", vbytes, &X1)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "partial", (size_t)std::max(K, 1) * g.nblocks * 2 * g.ld * 8, &part)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dots", (size_t)std::max(K, 1) * 2 * g.ld * 8, &dots)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "zeta", (size_t)nvec * (M + 1) * 8, &zeta)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "mu", (size_t)(M + 1) * 8, &mud)) != KPM_OK) return st;
+
+    const int nblk_vec = (nvec + b - 1) / b;
+    for (int blk = 0; blk < nblk_vec; ++blk) {
+        const int ncols = std::min(b, nvec - blk * b);
+        const BlockGeom gb = ncols == b ? g : make_geom(A.n, ncols, o->precision, o->rows_per_block);
+        const int64_t vec0 = (int64_t)blk * b;
+        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
+        void* X[2] = {X0, X1};
+        for (int s = 0; s < K; ++s) {
+            double* ps = (double*)part + (size_t)s * gb.nblocks * 2 * gb.ld;
+            const char* tag = s == 0 ? "cheb_first" : "cheb_step";
+            kpm_prof_begin(ctx, tag);
+            KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, X[s & 1], X[(s + 1) & 1],
+                                          alpha, beta, ps));
+            kpm_prof_end(ctx, tag);
+        }
+        KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gb.nblocks, 2 * gb.ld, K, (double*)dots));
+        KPM_HIP(ctx, launch_assemble(ctx->stream, (double*)dots, K, gb.ld, ncols, M, (double)A.n, vec0,
+                                     (double*)zeta));
+    }
+    KPM_HIP(ctx, launch_mean_moments(ctx->stream, (double*)zeta, nvec, M, (double*)mud));
+    KPM_HIP(ctx, hipMemcpyAsync(mu, mud, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<double>& hz = ctx->host_scratch;
+    hz.resize((size_t)nvec * (M + 1));
+    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), zeta, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    if (mu_per_vec) memcpy(mu_per_vec, hz.data(), hz.size() * 8);
+    // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1].
+    const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
+    for (size_t i = 0; i < hz.size(); ++i) {
+        if (!isfinite(hz[i]) || fabs(hz[i]) > 1.0 + tol) {
+            char msg[200];
+            snprintf(msg, sizeof msg,
+                     "spectrum escaped [lb, ub]: probe %zu moment %zu = %g (|mu_k| must stay <= 1)",
+                     i / (M + 1), i % (M + 1), hz[i]);
+            return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
+        }
+    }
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- damping / density
+extern "C" kpm_status kpm_damping_factors(kpm_ctx* ctx, kpm_damping kind, int M, const double* mu,
+                                          double* g) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!g || M < 0 || M > (1 << 20)) return kpm_fail(ctx, KPM_ERR_ARG, "bad M or g is NULL");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    void* gd;
+    kpm_status st = kpm_ws(ctx, "damp_g", (size_t)(M + 1) * 8, &gd);
+    if (st != KPM_OK) return st;
+    if (kind == KPM_DAMP_NONE) {
+        for (int k = 0; k <= M; ++k) g[k] = 1.0;
+        return KPM_OK;
+    } else if (kind == KPM_DAMP_JACKSON) {
+        KPM_HIP(ctx, launch_jackson(ctx->stream, M, (double*)gd));
+    } else if (kind == KPM_DAMP_LEARNED) {
+        if (!mu) return kpm_fail(ctx, KPM_ERR_ARG, "learned damping needs the moments");
+        return kpm_learned_damping(ctx, M, mu, g);
+    } else {
+        return kpm_fail(ctx, KPM_ERR_ARG, "unknown damping kind");
+    }
+    KPM_HIP(ctx, hipMemcpyAsync(g, gd, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
+    return sync(ctx);
+}
+
+static kpm_status upload_series(kpm_ctx* ctx, const double* mu, const double* g, int M, void** mud,
+                                void** gd) {
+    kpm_status st;
+    if ((st = kpm_ws(ctx, "dos_mu", (size_t)(M + 1) * 8, mud)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_g", (size_t)(M + 1) * 8, gd)) != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemcpyAsync(*mud, mu, (size_t)(M + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(*gd, g, (size_t)(M + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_dos(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb,
+                              double ub, const double* x, int npts, double* phi) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!mu || !g || !x || !phi || M < 0 || npts < 0) return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
+    if (npts == 0) return KPM_OK;
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    void *mud, *gd, *xd, *pd;
+    kpm_status st = upload_series(ctx, mu, g, M, &mud, &gd);
+    if (st != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_x", (size_t)npts * 8, &xd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_phi", (size_t)npts * 8, &pd)) != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemcpyAsync(xd, x, (size_t)npts * 8, hipMemcpyHostToDevice, ctx->stream));
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    KPM_HIP(ctx, launch_dos(ctx->stream, (double*)mud, (double*)gd, M, c, d, (double*)xd, npts, (double*)pd));
+    KPM_HIP(ctx, hipMemcpyAsync(phi, pd, (size_t)npts * 8, hipMemcpyDeviceToHost, ctx->stream));
+    return sync(ctx);
+}
+
+extern "C" kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb,
+                                   double ub, const double* edges, int nbins, double* mass) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!mu || !g || !edges || !mass || M < 0 || nbins < 0) return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
+    for (int i = 0; i < nbins; ++i)
+        if (!(edges[i + 1] >= edges[i])) return kpm_fail(ctx, KPM_ERR_ARG, "edges must be non-decreasing");
+    if (nbins == 0) return KPM_OK;
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    void *mud, *gd, *ed, *md;
+    kpm_status st = upload_series(ctx, mu, g, M, &mud, &gd);
+    if (st != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "bins_e", (size_t)(nbins + 1) * 8, &ed)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "bins_m", (size_t)nbins * 8, &md)) != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemcpyAsync(ed, edges, (size_t)(nbins + 1) * 8, hipMemcpyHostToDevice, ctx->stream));
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    KPM_HIP(ctx, launch_dos_bins(ctx->stream, (double*)mud, (double*)gd, M, c, d, (double*)ed, nbins, (double*)md));
+    KPM_HIP(ctx, hipMemcpyAsync(mass, md, (size_t)nbins * 8, hipMemcpyDeviceToHost, ctx->stream));
+    return sync(ctx);
+}
+
+extern "C" kpm_status kpm_rademacher(kpm_ctx* ctx, uint64_t seed, int64_t vec0, int nvec, int64_t n,
+                                     int64_t ld, int precision, void* out_device) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!out_device || nvec < 0 || n < 0 || ld < nvec || vec0 < 0 || vec0 + nvec > ((int64_t)1 << 32) ||
+        n > ((int64_t)1 << 32) || (precision != KPM_FP32 && precision != KPM_FP64))
+        return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (n == 0 || nvec == 0) return KPM_OK;
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    KPM_HIP(ctx, launch_rademacher(ctx->stream, seed, vec0, nvec, ld, n, precision, 0, out_device));
+    return sync(ctx);
+}
+
+// ---------------------------------------------------------------- profiling
+extern "C" kpm_status kpm_profile_enable(kpm_ctx* ctx, int enable) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->prof = enable != 0;
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_profile_query(kpm_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms) {
+    if (!ctx || !kernel || !launches || !total_ms) return KPM_ERR_ARG;
+    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    kpm_prof_collect(ctx);
+    auto it = ctx->prof_map.find(kernel);
+    *launches = it == ctx->prof_map.end() ? 0 : it->second.launches;
+    *total_ms = it == ctx->prof_map.end() ? 0.0 : it->second.total_ms;
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_profile_reset(kpm_ctx* ctx) {
+    if (!ctx) return KPM_ERR_ARG;
+    hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->prof_map) {
+        kv.second.used = 0;
+        kv.second.launches = 0;
+        kv.second.total_ms = 0.0;
+    }
+    return KPM_OK;
+}

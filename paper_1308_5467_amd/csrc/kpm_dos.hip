@@ -1,0 +1,81 @@
+// Damping factors and density evaluation (Lin, Saad & Yang, eq. (tdosFinal),
+// eq. (expmu) and Appendix A eq. (jackson)).  All FP64.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// g_k = [(1 - k/(M+2)) sin(a) cos(k a) + (1/(M+2)) cos(a) sin(k a)] / sin(a),
+// a = pi/(M+2).
+__global__ void jackson_kernel(int M, double* __restrict__ g) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > M) return;
+    const double a = M_PI / (double)(M + 2);
+    const double sa = sin(a), ca = cos(a);
+    g[k] = ((1.0 - (double)k / (double)(M + 2)) * sa * cos(k * a) +
+            (1.0 / (double)(M + 2)) * ca * sin(k * a)) / sa;
+}
+
+hipError_t launch_jackson(hipStream_t s, int M, double* g) {
+    jackson_kernel<<<(M + 1 + 127) / 128, 128, 0, s>>>(M, g);
+    return hipGetLastError();
+}
+
+// phi(x) = [g_0 mu_0 + 2 sum_{k>=1} g_k mu_k T_k(t)] / (pi d sqrt(1 - t^2)),
+// t = (x - c)/d, the Chebyshev sum evaluated by Clenshaw's recurrence.
+__global__ void dos_kernel(const double* __restrict__ mu, const double* __restrict__ g, int M,
+                           double c, double d, const double* __restrict__ x, int npts,
+                           double* __restrict__ phi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const double t = (x[i] - c) / d;
+    if (!(fabs(t) < 1.0)) {
+        phi[i] = 0.0;
+        return;
+    }
+    double b1 = 0.0, b2 = 0.0;
+    for (int k = M; k >= 1; --k) {
+        const double b0 = 2.0 * g[k] * mu[k] + 2.0 * t * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    const double sum = g[0] * mu[0] + t * b1 - b2;
+    phi[i] = sum / (M_PI * d * sqrt(1.0 - t * t));
+}
+
+hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, double c, double d,
+                      const double* x, int npts, double* phi) {
+    dos_kernel<<<(npts + 127) / 128, 128, 0, s>>>(mu, g, M, c, d, x, npts, phi);
+    return hipGetLastError();
+}
+
+// Antiderivative of the density in t, written in theta = arccos t:
+// F(t) = -(1/pi) [g_0 mu_0 theta + 2 sum_k g_k mu_k sin(k theta)/k];
+// mass[i] = F(t_{i+1}) - F(t_i) with t clamped to [-1, 1].
+__device__ double dos_antiderivative(const double* mu, const double* g, int M, double t) {
+    t = fmin(1.0, fmax(-1.0, t));
+    const double th = acos(t);
+    double s = g[0] * mu[0] * th;
+    for (int k = 1; k <= M; ++k) s += 2.0 * g[k] * mu[k] * sin(k * th) / (double)k;
+    return -s / M_PI;
+}
+
+__global__ void dos_bins_kernel(const double* __restrict__ mu, const double* __restrict__ g, int M,
+                                double c, double d, const double* __restrict__ edges, int nbins,
+                                double* __restrict__ mass) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbins) return;
+    const double fa = dos_antiderivative(mu, g, M, (edges[i] - c) / d);
+    const double fb = dos_antiderivative(mu, g, M, (edges[i + 1] - c) / d);
+    mass[i] = fb - fa;
+}
+
+hipError_t launch_dos_bins(hipStream_t s, const double* mu, const double* g, int M, double c,
+                           double d, const double* edges, int nbins, double* mass) {
+    dos_bins_kernel<<<(nbins + 127) / 128, 128, 0, s>>>(mu, g, M, c, d, edges, nbins, mass);
+    return hipGetLastError();
+}
+
+}  // namespace kpm

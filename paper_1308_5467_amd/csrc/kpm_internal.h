@@ -1,0 +1,161 @@
+// Internal declarations of the KPM library: context, workspace and the
+// launch wrappers of the device kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kpm.h"
+
+namespace kpm {
+
+// Device view of a CSR matrix (int32 indices).
+struct CsrDev {
+    const int32_t* rp = nullptr;
+    const int32_t* ci = nullptr;
+    const void* val = nullptr;
+    int val_f64 = 0;
+    int32_t n = 0;
+    int32_t nnz = 0;
+};
+
+// Geometry of one vector block on the device: `ld` values per row
+// (a multiple of the per-lane pack width), `lpr` lanes per row, `rpw` rows
+// per 64-wide wavefront, `rows_per_block` rows per workgroup (a multiple of
+// the 4 * rpw rows one workgroup pass covers), `nblocks` workgroups.
+struct BlockGeom {
+    int ld = 0, lpr = 0, rpw = 0, rows_per_block = 0, nblocks = 0;
+};
+
+constexpr int kWaves = 4;        // wavefronts per workgroup of the step kernels
+constexpr int kThreads = 64 * kWaves;
+
+BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint);
+
+// ---------------------------------------------------------------- moments
+hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
+                             int64_t n, int precision, int zero_pad, void* out);
+hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
+                            const BlockGeom& g, const void* V, void* U, double alpha, double beta,
+                            double* partial);
+hipError_t launch_reduce_partials(hipStream_t s, const double* partial, int nblocks, int width,
+                                  int K, double* dots);
+hipError_t launch_assemble(hipStream_t s, const double* dots, int K, int ld, int ncols, int M,
+                           double n, int64_t vec0, double* zeta_norm);
+hipError_t launch_mean_moments(hipStream_t s, const double* zeta_norm, int nvec, int M, double* mu);
+hipError_t launch_convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t count);
+hipError_t launch_validate_csr(hipStream_t s, const CsrDev& A, int* flags);
+
+// ---------------------------------------------------------------- bounds
+struct LanczosWork {
+    double* Q = nullptr;        // [(m+1) x n]
+    double* w = nullptr;        // [n]
+    double* coef = nullptr;     // alpha[64], beta[64], h[64], scratch[64]
+    double* partial = nullptr;  // [nblk x 64]
+    int nblk = 0;
+};
+hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, LanczosWork& W);
+hipError_t launch_gershgorin(hipStream_t s, const CsrDev& A, double* out /* [2 * nblk] */, int nblk);
+
+// ---------------------------------------------------------------- damping / density
+hipError_t launch_jackson(hipStream_t s, int M, double* g);
+hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, double c, double d,
+                      const double* x, int npts, double* phi);
+hipError_t launch_dos_bins(hipStream_t s, const double* mu, const double* g, int M, double c,
+                           double d, const double* edges, int nbins, double* mass);
+
+// ---------------------------------------------------------------- batched
+struct BatchTile {       // one row panel of one matrix
+    int32_t mat;         // matrix index
+    int32_t panel;       // panel index within the matrix
+};
+struct BatchMat {        // per-matrix data for the persistent kernel
+    const int32_t* rp;
+    const int32_t* ci;
+    const float* val;
+    float* X0;           // v_{even} buffer [n x ld]
+    float* X1;           // v_{odd}  buffer [n x ld]
+    double alpha, beta;  // 2B = alpha A + beta I
+    int32_t n;
+    int32_t npanels;
+    int32_t tile0;       // first tile of this matrix within one step's tile list
+    int32_t part0;       // first partial slot of this matrix within one step
+};
+hipError_t launch_batched_persistent(hipStream_t s, const BatchMat* mats, int nmat,
+                                     const BatchTile* tiles, int ntiles_per_step, int K,
+                                     const BlockGeom& g, int nparts_per_step, double* partial,
+                                     uint32_t* counters, uint32_t* queue, int* status,
+                                     int grid, uint32_t spin_limit);
+hipError_t launch_batched_fill(hipStream_t s, const BatchMat* mats, int nmat, int ld, int ncols,
+                               uint64_t seed, int64_t max_n);
+hipError_t launch_batched_assemble(hipStream_t s, const double* dots, int nmat, int K, int ld,
+                                   int ncols, int M, const int32_t* n_of, double* zeta_norm,
+                                   int nparts_per_step, const int32_t* part0,
+                                   const int32_t* npanels, double* dots_out);
+hipError_t launch_clear_u32(hipStream_t s, uint32_t* p, int64_t count);
+int batched_max_resident_blocks(int precision);
+
+// ---------------------------------------------------------------- MLP
+hipError_t mlp_forward_dev(hipStream_t s, int N, const float* x, const float* params,
+                           float* z1, float* h1, float* z2, float* h2, float* g);
+hipError_t mlp_loss_grad_dev(hipStream_t s, int N, const float* x, const float* target,
+                             const float* K, const float* params, float* act, float* grads,
+                             float* loss_parts, float* dwork);
+hipError_t mlp_blur_operator_dev(hipStream_t s, int nmom, int npts, float sigma, float* K);
+hipError_t mlp_adam_dev(hipStream_t s, int64_t P, float* params, const float* grads, float* m,
+                        float* v, float lr, float b1, float b2, float eps, int t);
+hipError_t mlp_init_dev(hipStream_t s, uint64_t seed, float* params);
+hipError_t mlp_gather_rows_dev(hipStream_t s, const float* src, int cols, const int32_t* idx,
+                               int nrows, float* dst);
+
+}  // namespace kpm
+
+// ---------------------------------------------------------------- context
+struct kpm_dev_buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct kpm_prof_entry {
+    std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded but not yet read
+    size_t used = 0;             // number of events in use
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+struct kpm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<std::string, kpm_dev_buf> bufs;  // grow-only device workspace by role
+    std::vector<double> host_scratch;
+    // damping network
+    bool mlp_ready = false;
+    kpm_dev_buf mlp_params;
+    // profiling
+    bool prof = false;
+    std::map<std::string, kpm_prof_entry> prof_map;
+};
+
+// Learned damping (damping network on the device); host mu/g arrays.
+kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g);
+
+// Grow-only workspace allocation by role name.
+kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out);
+kpm_status kpm_fail(kpm_ctx* ctx, kpm_status st, const std::string& msg);
+kpm_status kpm_hip_fail(kpm_ctx* ctx, hipError_t e, const char* what);
+// Profiling helpers: bracket a launch with events when profiling is on.
+void kpm_prof_begin(kpm_ctx* ctx, const char* kernel);
+void kpm_prof_end(kpm_ctx* ctx, const char* kernel);
+// Fold recorded events into the totals (call after a stream sync).
+void kpm_prof_collect(kpm_ctx* ctx);
+
+#define KPM_HIP(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return kpm_hip_fail(ctx, e_, #call); \
+    } while (0)

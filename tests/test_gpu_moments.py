@@ -1,0 +1,260 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances (stated per test): FP64 path 1e-12 absolute on every normalised
+moment; FP32 path (FP32 vectors and sparse products, FP64 dots) 1e-5
+absolute.  Both sides get identical lb/ub and probe seeds.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1308_5467_amd as kpm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = kpm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(A, dtype):
+    vals = A.val if dtype == "f64" else A.val.astype(np.float32)
+    return kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, dtype)
+
+
+def oracle_per_vec(A, lb, ub, M, nvec, seed, vec0=0, dtype="f64"):
+    Ao = A if dtype == "f64" else A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    z = oracle.moments_per_vector(Ao, c, d, M, nvec, seed, vec0=vec0)
+    return z / A.n
+
+
+# ---------------------------------------------------------------- probe vectors
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_rademacher_bit_exact(ctx, prec):
+    import torch
+    n, nvec, ld = 1000, 7, 9
+    out = torch.full((n, ld), 5.0, dtype=torch.float32 if prec == "f32" else torch.float64, device="cuda")
+    kpm.kpm_rademacher(ctx, 12345, 3, nvec, n, ld, prec, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.rademacher_block(12345, 3, nvec, n)
+    assert np.array_equal(got[:, :nvec], ref)
+    assert np.all(got[:, nvec:] == 5.0)
+
+
+# ---------------------------------------------------------------- moments, small cases
+def test_c1_fp64_parity(ctx):
+    """c1: 2D Dirichlet Laplacian 32x32, FP64, M = 100, 20 probes."""
+    _say("c1 fp64")
+    A = synth.laplacian2d_dirichlet(32)
+    lb, ub = oracle.lanczos_bounds(A, 20, 3001)["lb"], oracle.lanczos_bounds(A, 20, 3001)["ub"]
+    D = dev(A, "f64")
+    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 100, 20, 2001, precision="f64", per_vector=True)
+    ref = oracle_per_vec(A, lb, ub, 100, 20, 2001)
+    assert np.max(np.abs(pv - ref)) < TOL64
+    assert np.max(np.abs(mu - ref.mean(axis=0))) < TOL64
+    assert mu[0] == 1.0
+
+
+@pytest.mark.parametrize("L,nvec,block,M", [(16, 64, 64, 256), (13, 40, 16, 31), (11, 5, 0, 2),
+                                            (9, 3, 3, 1), (10, 17, 8, 0)])
+def test_anderson3d_fp32_parity_ragged(ctx, L, nvec, block, M):
+    """3D Anderson model, FP32 path: several workgroups, ragged row tail,
+    ragged last probe block, odd/even/tiny M."""
+    _say(f"anderson3d fp32 L={L} nvec={nvec} block={block} M={M}")
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(L), 16.0, 7 + L)
+    b = oracle.lanczos_bounds(A.rounded_f32(), 20, 3)
+    D = dev(A, "f32")
+    mu, pv = kpm.kpm_moments(ctx, D, b["lb"], b["ub"], M, nvec, 99, precision="f32", block=block,
+                             per_vector=True, rows_per_block=32)
+    ref = oracle_per_vec(A, b["lb"], b["ub"], M, nvec, 99, dtype="f32")
+    assert np.max(np.abs(pv - ref)) < TOL32
+    assert np.max(np.abs(mu - ref.mean(axis=0))) < TOL32
+    assert mu[0] == 1.0
+
+
+@pytest.mark.parametrize("block", [0, 4, 6, 128])
+def test_random_sparse_fp64_parity(ctx, block):
+    _say(f"random sparse fp64 block={block}")
+    A = synth.random_sparse_symmetric(3001, 4.5, 17)
+    b = oracle.lanczos_bounds(A, 20, 4)
+    D = dev(A, "f64")
+    mu, pv = kpm.kpm_moments(ctx, D, b["lb"], b["ub"], 67, 10, 5, precision="f64", block=block, per_vector=True)
+    ref = oracle_per_vec(A, b["lb"], b["ub"], 67, 10, 5)
+    assert np.max(np.abs(pv - ref)) < TOL64
+
+
+def test_fp64_values_fp32_path_rounds_values(ctx):
+    """FP64 values on the FP32 path are rounded to FP32 first."""
+    A = synth.random_sparse_symmetric(1500, 3.0, 3)
+    b = oracle.lanczos_bounds(A, 20, 4)
+    D = dev(A, "f64")
+    mu = kpm.kpm_moments(ctx, D, b["lb"], b["ub"], 40, 8, 5, precision="f32")
+    ref = oracle_per_vec(A, b["lb"], b["ub"], 40, 8, 5, dtype="f32").mean(axis=0)
+    assert np.max(np.abs(mu - ref)) < TOL32
+
+
+def test_host_csr_input(ctx):
+    A = synth.laplacian2d_dirichlet(20)
+    H = kpm.HostCSR(A.n, A.row_ptr, A.col_idx, A.val)
+    mu = kpm.kpm_moments(ctx, H, -0.1, 8.1, 30, 4, 9, precision="f64")
+    ref = oracle_per_vec(A, -0.1, 8.1, 30, 4, 9).mean(axis=0)
+    assert np.max(np.abs(mu - ref)) < TOL64
+
+
+def test_diagonal_and_one_by_one(ctx):
+    d = np.random.default_rng(1).uniform(-2, 3, 333)
+    A = synth.diagonal_matrix(d)
+    mu = kpm.kpm_moments(ctx, dev(A, "f64"), -2.5, 3.5, 50, 3, 8, precision="f64")
+    c, dd = oracle.rescale(-2.5, 3.5)
+    exact = np.array([np.mean(np.cos(k * np.arccos((d - c) / dd))) for k in range(51)])
+    assert np.max(np.abs(mu - exact)) < TOL64
+    one = synth.diagonal_matrix(np.array([0.0]))
+    mu1 = kpm.kpm_moments(ctx, dev(one, "f64"), -1.0, 1.0, 40, 1, 0, precision="f64")
+    assert np.max(np.abs(mu1 - np.array([[1.0, 0.0, -1.0, 0.0][k % 4] for k in range(41)]))) < 1e-15
+
+
+def test_deterministic_bitwise(ctx):
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(20), 8.0, 2)
+    D = dev(A, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 1, 0.01)
+    r1 = kpm.kpm_moments(ctx, D, lb, ub, 64, 64, 3)
+    r2 = kpm.kpm_moments(ctx, D, lb, ub, 64, 64, 3)
+    assert np.array_equal(r1, r2)
+
+
+# ---------------------------------------------------------------- errors
+def test_narrow_bounds_report_spectrum_escape(ctx):
+    A = synth.laplacian2d_dirichlet(16)
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_moments(ctx, dev(A, "f64"), 1.0, 5.0, 120, 4, 1, precision="f64")
+    assert e.value.status == -4
+
+
+def test_malformed_csr_is_rejected(ctx):
+    A = synth.laplacian2d_dirichlet(8)
+    ci = A.col_idx.copy()
+    ci[5] = A.n + 3          # out of range
+    H = kpm.HostCSR(A.n, A.row_ptr, ci, A.val)
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_moments(ctx, H, -0.1, 8.1, 10, 2, 1, precision="f64", validate=True)
+    assert e.value.status == -1
+    ci = A.col_idx.copy()
+    ci[0], ci[1] = ci[1], ci[0]  # unsorted
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_moments(ctx, kpm.HostCSR(A.n, A.row_ptr, ci, A.val), -0.1, 8.1, 10, 2, 1,
+                        precision="f64", validate=True)
+    v = A.val.copy()
+    v[3] = np.nan
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_moments(ctx, kpm.HostCSR(A.n, A.row_ptr, A.col_idx, v), -0.1, 8.1, 10, 2, 1,
+                        precision="f64", validate=True)
+
+
+def test_bad_arguments(ctx):
+    A = synth.laplacian2d_dirichlet(8)
+    D = dev(A, "f64")
+    for kw in (dict(M=-1), dict(nvec=0), dict(block=300)):
+        args = dict(M=10, nvec=2, block=0)
+        args.update(kw)
+        with pytest.raises(kpm.KpmError) as e:
+            kpm.kpm_moments(ctx, D, -0.1, 8.1, args["M"], args["nvec"], 1, precision="f64", block=args["block"])
+        assert e.value.status == -1
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_moments(ctx, D, 2.0, 1.0, 10, 2, 1)
+
+
+# ---------------------------------------------------------------- bounds
+@pytest.mark.parametrize("which", ["lap2d", "anderson3d", "random", "diag_breakdown", "tiny"])
+def test_bounds_parity_and_enclosure(ctx, which):
+    _say(f"bounds {which}")
+    if which == "lap2d":
+        A = synth.laplacian2d_dirichlet(32)
+    elif which == "anderson3d":
+        A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(12), 16.0, 5)
+    elif which == "random":
+        A = synth.random_sparse_symmetric(2000, 4.5, 8)
+    elif which == "diag_breakdown":
+        A = synth.diagonal_matrix(np.array([1.0, 1.0, 1.0, 2.0, 2.0]))
+    else:
+        A = synth.random_sparse_symmetric(7, 2.0, 3)
+    for prec in ("f64", "f32"):
+        Ao = A if prec == "f64" else A.rounded_f32()
+        ref = oracle.lanczos_bounds(Ao, 20, 3001)
+        lb, ub = kpm.kpm_bounds(ctx, dev(A, prec), 20, 3001, 0.01)
+        scale = max(abs(ref["lb"]), abs(ref["ub"]), 1.0)
+        assert abs(lb - ref["lb"]) < 1e-9 * scale and abs(ub - ref["ub"]) < 1e-9 * scale
+        if A.n <= 4096:
+            lam = np.linalg.eigvalsh(Ao.dense())
+            assert lb < lam[0] and ub > lam[-1]
+
+
+# ---------------------------------------------------------------- damping and density
+def test_jackson_and_dos_parity(ctx):
+    for M in (1, 2, 3, 40, 100, 1000):
+        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
+        assert np.max(np.abs(g - oracle.jackson(M))) < 1e-14
+    g1 = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_NONE, 5)
+    assert np.all(g1 == 1.0)
+    rng = np.random.default_rng(2)
+    M = 100
+    mu = np.concatenate([[1.0], rng.normal(0, 0.3, M) / np.arange(1, M + 1)])
+    g = oracle.jackson(M)
+    x = np.linspace(-3.5, 9.5, 401)
+    phi = kpm.kpm_dos(ctx, mu, g, -2.0, 8.0, x)
+    ref = oracle.dos(mu, g, -2.0, 8.0, x)
+    assert np.max(np.abs(phi - ref)) < 1e-11
+    edges = np.linspace(-3, 9, 61)
+    mass = kpm.kpm_dos_bins(ctx, mu, g, -2.0, 8.0, edges)
+    assert np.max(np.abs(mass - oracle.dos_bins(mu, g, -2.0, 8.0, edges))) < 1e-12
+    assert abs(mass.sum() - 1.0) < 1e-12
+
+
+def test_delta_function_example(ctx):
+    """The paper's degree-40 delta-function expansion: 41/pi at 0 undamped."""
+    M = 40
+    mu = kpm.kpm_moments(ctx, dev(synth.diagonal_matrix(np.array([0.0])), "f64"), -1.0, 1.0, M, 1, 0,
+                         precision="f64")
+    phi = kpm.kpm_dos(ctx, mu, np.ones(M + 1), -1.0, 1.0, np.array([0.0]))
+    assert abs(phi[0] - 41 / math.pi) < 1e-12
+    t = np.linspace(-0.999, 0.999, 4001)
+    assert kpm.kpm_dos(ctx, mu, np.ones(M + 1), -1.0, 1.0, t).min() < -1.0
+    gj = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
+    assert kpm.kpm_dos(ctx, mu, gj, -1.0, 1.0, t).min() > -1e-12
+
+
+# ---------------------------------------------------------------- full-size workloads, sampled
+def test_c2_full_size_sampled(ctx):
+    """c2 at full size (64^3 Anderson, M = 256, 64 probes, FP32), in the
+    launch configuration the benchmark times; the oracle recomputes probes
+    0, 31 and 63 one by one."""
+    _say("c2 full size")
+    A = synth.config_matrix("c2")
+    D = dev(A, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
+    # 7-point periodic Laplacian spectrum [0, 12] shifted by disorder in [-8, 8]
+    assert -8.0 - 1.0 < lb < 0.0 and 12.0 < ub < 20.0 + 1.0
+    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 256, 64, 2002, precision="f32", validate=False, per_vector=True)
+    Ao = A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    for l in (0, 31, 63):
+        z = oracle.moments_per_vector(Ao, c, d, 256, 1, 2002, vec0=l)[0] / A.n
+        assert np.max(np.abs(pv[l] - z)) < TOL32, l
+    assert mu[0] == 1.0 and np.all(np.abs(pv) <= 1 + 1e-5)
