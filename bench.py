@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--grid", type=int, default=64, help="side of the periodic cubic grid")
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="only run the streaming-copy bandwidth probe (counter calibration)")
     ap.add_argument("--cpu-sample-vectors", type=int, default=0,
                     help="probes in the oracle sample (0 = all cores' worth)")
     return ap.parse_args()
@@ -61,6 +63,12 @@ def main():
     import torch
     import paper_1308_5467_amd as kpm
     import synth
+
+    if args.copy_probe_only:
+        ctx = kpm.Context(0)
+        out = {f"copy_gbs_{sz >> 20}MiB": kpm.kpm_hbm_copy_probe(ctx, sz, 5) for sz in (1 << 30, 1 << 26)}
+        print(json.dumps(out))
+        return
 
     A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(args.grid), 16.0, 1002)
     vals = A.val.astype(np.float32) if args.precision == "f32" else A.val
@@ -91,6 +99,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kpm.kpm_profile_enable(ctx, False)
+    copy_gbs = kpm.kpm_hbm_copy_probe(ctx, 1 << 30, 10)
     nl, step_ms_total = kpm.kpm_profile_query(ctx, "cheb_step")
     nf, first_ms_total = kpm.kpm_profile_query(ctx, "cheb_first")
     nlz, lz_ms_total = kpm.kpm_profile_query(ctx, "lanczos")
@@ -109,7 +118,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": MEASURED_TRAFFIC_BYTES,
             "kernel": "cheb_step_kernel", "avg_launch_us": round(avg_ms * 1000, 2),
-            "launches": nl, "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+            "launches": nl, "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy_probe": round(achieved / copy_gbs, 4)}
 
     out = {
         "metric": "Chebyshev moment nnz*deg*vec/s",

@@ -202,6 +202,15 @@ kpm_status kpm_mlp_init(kpm_ctx* ctx, uint64_t seed);
 kpm_status kpm_mlp_save(kpm_ctx* ctx, const char* path);
 kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path);
 
+/*
+ * kpm_hbm_copy_probe -- achievable device-memory bandwidth: a plain
+ * streaming copy of `bytes` bytes (16-byte loads/stores) run `iters` times
+ * between two context-owned buffers; *gbs = 2 * bytes * iters / time / 1e9.
+ * The practical denominator beside the HBM specification peak and the
+ * calibration kernel for hardware byte counters.
+ */
+kpm_status kpm_hbm_copy_probe(kpm_ctx* ctx, int64_t bytes, int iters, double* gbs);
+
 /* ---- device timing of the library's own kernels ----
  * When enabled, every launch of the listed kernels is bracketed by HIP
  * events on the context's stream.  kernel: "cheb_step" (fused recurrence

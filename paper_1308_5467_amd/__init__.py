@@ -31,7 +31,7 @@ EXPORTS = [
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
-    "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset",
+    "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
 ]
 
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_profile_enable": ([P, I32], I32),
         "kpm_profile_query": ([P, ctypes.c_char_p, P, P], I32),
         "kpm_profile_reset": ([P], I32),
+        "kpm_hbm_copy_probe": ([P, I64, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -339,6 +340,13 @@ def kpm_profile_query(ctx: Context, kernel: str):
 
 def kpm_profile_reset(ctx: Context) -> None:
     ctx.check(ctx.lib.kpm_profile_reset(ctx.handle))
+
+
+def kpm_hbm_copy_probe(ctx: Context, nbytes: int = 1 << 30, iters: int = 20) -> float:
+    """Achievable copy bandwidth in GB/s (read + write bytes)."""
+    g = ctypes.c_double()
+    ctx.check(ctx.lib.kpm_hbm_copy_probe(ctx.handle, nbytes, iters, ctypes.byref(g)))
+    return g.value
 
 
 # MLP parameter layout (matches include/kpm.h)

@@ -64,11 +64,12 @@ void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) {
     hipEventRecord(e.ev[e.used], ctx->stream);
 }
 
-void kpm_prof_end(kpm_ctx* ctx, const char* kernel) {
+void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches) {
     if (!ctx->prof) return;
     kpm_prof_entry& e = ctx->prof_map[kernel];
     if (e.used + 2 > e.ev.size()) return;
     hipEventRecord(e.ev[e.used + 1], ctx->stream);
+    e.counts.push_back(launches);
     e.used += 2;
 }
 
@@ -79,10 +80,11 @@ void kpm_prof_collect(kpm_ctx* ctx) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, e.ev[i], e.ev[i + 1]) == hipSuccess) {
                 e.total_ms += ms;
-                e.launches += 1;
+                e.launches += e.counts[i / 2];
             }
         }
         e.used = 0;
+        e.counts.clear();
     }
 }
 
@@ -274,12 +276,18 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     const int n = A.n;
     const int m = std::min(steps, n);
     LanczosWork W;
-    W.nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
+    W.nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
+    W.chunk = (int)(((int64_t)n + W.nblk - 1) / W.nblk);
+    if (W.chunk > 8192) {
+        W.chunk = 8192;
+        W.nblk = (int)(((int64_t)n + 8191) / 8192);
+    }
     void *Q, *w, *coef, *part;
     if ((st = kpm_ws(ctx, "lz_Q", (size_t)m * n * 8, &Q)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "lz_w", (size_t)n * 8, &w)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lz_w", (size_t)2 * n * 8, &w)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "lz_coef", 256 * 8, &coef)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "lz_part", (size_t)W.nblk * 32 * 8 + 2 * 8 * 1024, &part)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lz_part", (size_t)4 * W.nblk * 32 * 8 + (size_t)2 * 8 * W.nblk, &part)) != KPM_OK)
+        return st;
     W.Q = (double*)Q;
     W.w = (double*)w;
     W.coef = (double*)coef;
@@ -287,7 +295,7 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     KPM_HIP(ctx, hipMemsetAsync(coef, 0, 256 * 8, ctx->stream));
     kpm_prof_begin(ctx, "lanczos");
     KPM_HIP(ctx, launch_lanczos(ctx->stream, A, m, seed, W));
-    kpm_prof_end(ctx, "lanczos");
+    kpm_prof_end(ctx, "lanczos", 1);
     std::vector<double> hc(256);
     KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;
@@ -324,7 +332,7 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     double lb0 = theta[0] - rlo, ub0 = theta[k - 1] + rhi;
     if (breakdown) {
         const int gb = W.nblk;
-        double* gout = (double*)part + (size_t)W.nblk * 32;
+        double* gout = (double*)part + (size_t)4 * W.nblk * 32;
         KPM_HIP(ctx, launch_gershgorin(ctx->stream, A, gout, gb));
         std::vector<double> hg(2 * gb);
         KPM_HIP(ctx, hipMemcpyAsync(hg.data(), gout, 2 * gb * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -378,10 +386,11 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     BlockGeom g = make_geom(A.n, b, o->precision, o->rows_per_block);
 
     void *X0, *X1, *part, *dots, *zeta, *mud;
+    const int grid = cheb_step_grid(A, o->precision, g);
     const size_t vbytes = (size_t)A.n * g.ld * esz;
     if ((st = kpm_ws(ctx, "X0", vbytes, &X0)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "X1", vbytes, &X1)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "partial", (size_t)std::max(K, 1) * g.nblocks * 2 * g.ld * 8, &part)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "partial", (size_t)std::max(K, 1) * grid * 2 * g.ld * 8, &part)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "dots", (size_t)std::max(K, 1) * 2 * g.ld * 8, &dots)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "zeta", (size_t)nvec * (M + 1) * 8, &zeta)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "mu", (size_t)(M + 1) * 8, &mud)) != KPM_OK) return st;
@@ -390,18 +399,22 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     for (int blk = 0; blk < nblk_vec; ++blk) {
         const int ncols = std::min(b, nvec - blk * b);
         const BlockGeom gb = ncols == b ? g : make_geom(A.n, ncols, o->precision, o->rows_per_block);
+        const int gridb = ncols == b ? grid : cheb_step_grid(A, o->precision, gb);
         const int64_t vec0 = (int64_t)blk * b;
         KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
         void* X[2] = {X0, X1};
         for (int s = 0; s < K; ++s) {
-            double* ps = (double*)part + (size_t)s * gb.nblocks * 2 * gb.ld;
-            const char* tag = s == 0 ? "cheb_first" : "cheb_step";
-            kpm_prof_begin(ctx, tag);
-            KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, X[s & 1], X[(s + 1) & 1],
-                                          alpha, beta, ps));
-            kpm_prof_end(ctx, tag);
+            double* ps = (double*)part + (size_t)s * gridb * 2 * gb.ld;
+            // One event pair brackets the first step and one the run of the
+            // remaining steps (events between launches would add gaps).
+            if (s == 0) kpm_prof_begin(ctx, "cheb_first");
+            if (s == 1) kpm_prof_begin(ctx, "cheb_step");
+            KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, gridb, X[s & 1],
+                                          X[(s + 1) & 1], alpha, beta, ps));
+            if (s == 0) kpm_prof_end(ctx, "cheb_first", 1);
+            if (s == K - 1 && K > 1) kpm_prof_end(ctx, "cheb_step", K - 1);
         }
-        KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gb.nblocks, 2 * gb.ld, K, (double*)dots));
+        KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gridb, 2 * gb.ld, K, (double*)dots));
         KPM_HIP(ctx, launch_assemble(ctx->stream, (double*)dots, K, gb.ld, ncols, M, (double)A.n, vec0,
                                      (double*)zeta));
     }
@@ -538,6 +551,7 @@ extern "C" kpm_status kpm_profile_reset(kpm_ctx* ctx) {
     hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->prof_map) {
         kv.second.used = 0;
+        kv.second.counts.clear();
         kv.second.launches = 0;
         kv.second.total_ms = 0.0;
     }

@@ -39,9 +39,11 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
 // ---------------------------------------------------------------- moments
 hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
                              int64_t n, int precision, int zero_pad, void* out);
+// Workgroups every step launch of this geometry uses (= partial rows per step).
+int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g);
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
-                            const BlockGeom& g, const void* V, void* U, double alpha, double beta,
-                            double* partial);
+                            const BlockGeom& g, int grid, const void* V, void* U, double alpha,
+                            double beta, double* partial);
 hipError_t launch_reduce_partials(hipStream_t s, const double* partial, int nblocks, int width,
                                   int K, double* dots);
 hipError_t launch_assemble(hipStream_t s, const double* dots, int K, int ld, int ncols, int M,
@@ -52,11 +54,12 @@ hipError_t launch_validate_csr(hipStream_t s, const CsrDev& A, int* flags);
 
 // ---------------------------------------------------------------- bounds
 struct LanczosWork {
-    double* Q = nullptr;        // [(m+1) x n]
-    double* w = nullptr;        // [n]
-    double* coef = nullptr;     // alpha[64], beta[64], h[64], scratch[64]
-    double* partial = nullptr;  // [nblk x 64]
-    int nblk = 0;
+    double* Q = nullptr;        // [m x n] Lanczos vectors
+    double* w = nullptr;        // [2 x n] residual ping-pong buffers
+    double* coef = nullptr;     // alpha[64], beta[64]
+    double* partial = nullptr;  // [4 x nblk x 32] per-workgroup partial sums
+    int nblk = 0;               // workgroups
+    int chunk = 0;              // rows per workgroup (<= 8192)
 };
 hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, LanczosWork& W);
 hipError_t launch_gershgorin(hipStream_t s, const CsrDev& A, double* out /* [2 * nblk] */, int nblk);
@@ -123,6 +126,7 @@ struct kpm_dev_buf {
 struct kpm_prof_entry {
     std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded but not yet read
     size_t used = 0;             // number of events in use
+    std::vector<int> counts;     // launches covered by each recorded pair
     int64_t launches = 0;
     double total_ms = 0.0;
 };
@@ -148,9 +152,10 @@ kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g)
 kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out);
 kpm_status kpm_fail(kpm_ctx* ctx, kpm_status st, const std::string& msg);
 kpm_status kpm_hip_fail(kpm_ctx* ctx, hipError_t e, const char* what);
-// Profiling helpers: bracket a launch with events when profiling is on.
+// Profiling helpers: bracket a run of `launches` back-to-back launches of
+// one kernel with an event pair when profiling is on.
 void kpm_prof_begin(kpm_ctx* ctx, const char* kernel);
-void kpm_prof_end(kpm_ctx* ctx, const char* kernel);
+void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches);
 // Fold recorded events into the totals (call after a stream sync).
 void kpm_prof_collect(kpm_ctx* ctx);
 

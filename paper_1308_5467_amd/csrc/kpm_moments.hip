@@ -23,6 +23,10 @@
 // products are exact FP32 x FP32 products accumulated in FP64.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
 
 #include "kpm_internal.h"
 
@@ -88,12 +92,15 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
     if (rows_per_block_hint > 0) {
         rows = (rows_per_block_hint + rows_per_pass - 1) / rows_per_pass * rows_per_pass;
     } else {
-        // Aim for about 2048 workgroups (8 per CU) and at most 64 passes each.
-        int64_t passes = (n + (int64_t)rows_per_pass * 2048 - 1) / ((int64_t)rows_per_pass * 2048);
+        // About 8 KB of vector rows per panel (32 rows at 64 FP32 columns):
+        // the panels the resident workgroups of one XCD work on at a time
+        // then span ~2 MB of the gathered block, which keeps most gathers of
+        // 3D-stencil neighbours (a plane apart) in that XCD's L2; the grid
+        // is sized to the resident workgroups.
+        const int row_bytes = g.ld * (precision == KPM_FP64 ? 8 : 4);
+        int passes = (8192 / row_bytes + rows_per_pass / 2) / rows_per_pass;
         if (passes < 1) passes = 1;
-        if (passes > 64) passes = 64;
-        rows = (int)passes * rows_per_pass;
-    }
+        rows = passes * rows_per_pass;
     g.rows_per_block = rows;
     g.nblocks = (int)((n + rows - 1) / rows);
     return g;
@@ -139,89 +146,185 @@ struct StepParams {
     void* U;          // in: v_{k-1} (unless FIRST), out: v_{k+1}
     double* partial;  // [nblocks][2][ld]: <U_new, V>, <U_new, U_new> per panel
     double alpha, beta;
-    int32_t n, ld, lpr, rpw, rows_per_block;
+    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
 };
 
-template <typename TA, typename TV, bool FIRST>
+// Byte offset of element (row, column group) in a vector block.  With
+// OFF32 the block is known to be smaller than 4 GiB and the offset is an
+// unsigned 32-bit value added to a uniform base (one address register per
+// load instead of two).
+template <bool OFF32>
+__device__ __forceinline__ uint64_t voff(uint32_t row, uint32_t ldb, uint32_t coffb) {
+    if (OFF32) return (uint32_t)(row * ldb + coffb);
+    return (uint64_t)row * ldb + coffb;
+}
+
+// One matrix row of the fused step for the lanes of one row group: gather
+// the CSR row in predicated batches of G entries (one memory round trip
+// for rows of up to G entries), combine, store, and accumulate the two
+// dot products.
+//
+// EARLY (indices in LDS): the own-row and U loads go out first and overlap
+// the gathers.  Without staging the index loads share the in-order vector
+// memory counter with them, so the own-row and U loads are issued after the
+// gathers instead.
+template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G>
+__device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t* __restrict__ cidx,
+                                         const TA* __restrict__ cval, const char* __restrict__ Vb,
+                                         char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
+                                         double alpha, double beta, double (&sx)[Pack<TV>::N],
+                                         double (&ss)[Pack<TV>::N]) {
+    constexpr int N = Pack<TV>::N;
+    const uint64_t orow = voff<OFF32>(row, ldb, coffb);
+    TV own[N], u[N];
+    if (EARLY) {
+        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
+        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+    }
+    TV acc[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) acc[e] = (TV)0;
+    for (int k = kb; k < ke; k += G) {
+        TV x[G][N];
+        TV a[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (k + i < ke) {
+                const int j = cidx[k + i];
+                a[i] = (TV)cval[k + i];
+                Pack<TV>::load(reinterpret_cast<const TV*>(Vb + voff<OFF32>(j, ldb, coffb)), x[i]);
+            } else {
+                a[i] = (TV)0;
+#pragma unroll
+                for (int e = 0; e < N; ++e) x[i][e] = (TV)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+#pragma unroll
+            for (int e = 0; e < N; ++e) acc[e] = fma(a[i], x[i][e], acc[e]);
+    }
+    if (!EARLY) {
+        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
+        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+    }
+    TV out[N];
+    if (FIRST) {
+        // v1 = B v0 = (alpha/2) A v0 + (beta/2) v0
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = (TV)fma(0.5 * alpha, (double)acc[e], 0.5 * beta * (double)own[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], -(double)u[e]));
+    }
+    Pack<TV>::store(reinterpret_cast<TV*>(Ub + orow), out);
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const double o = (double)out[e];
+        sx[e] = fma(o, (double)own[e], sx[e]);
+        ss[e] = fma(o, o, ss[e]);
+    }
+}
+
+// Fused step.  The grid is sized to the number of workgroups that fit on
+// the device at once; workgroups running on XCD x (hardware round-robin
+// b % 8) walk the x-th contiguous eighth of the row panels, so neighbouring
+// rows -- and the gathered rows of banded matrices -- share that XCD's L2.
+// With `stage` set, a panel's slice of the CSR arrays (row offsets, column
+// indices, values) is first copied to LDS with coalesced loads when it fits
+// (rows of up to ~15 entries at the default panel height), so each row costs
+// one round of independent gathers.  Each workgroup accumulates its dot
+// products over all the rows it processes and writes one partial pair per
+// probe column at the end; the grid size and the panel-to-workgroup map are
+// fixed for a device, so results are bitwise reproducible run to run.
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
 __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     constexpr int N = Pack<TV>::N;
-    __shared__ double red[kWaves * 64 * 2 * N];
+    constexpr int kLdsDoubles = kWaves * 64 * 2 * N;
+    __shared__ double smem[kLdsDoubles];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rw = lane / p.lpr;
     const int cg = lane - rw * p.lpr;
     const bool lane_on = rw < p.rpw;
-    const int panel = xcd_panel(blockIdx.x, gridDim.x);
-    const int r0 = panel * p.rows_per_block;
-    const int r1 = min(p.n, r0 + p.rows_per_block);
     const TA* __restrict__ val = static_cast<const TA*>(p.val);
-    const TV* __restrict__ V = static_cast<const TV*>(p.V);
-    TV* __restrict__ U = static_cast<TV*>(p.U);
+    const char* __restrict__ Vb = static_cast<const char*>(p.V);
+    char* __restrict__ Ub = static_cast<char*>(p.U);
     const int32_t* __restrict__ rp = p.rp;
     const int32_t* __restrict__ ci = p.ci;
-    const int64_t ld = p.ld;
+    const uint32_t ldb = (uint32_t)p.ld * (uint32_t)sizeof(TV);
     const int coff = cg * N;
+    const uint32_t coffb = (uint32_t)coff * (uint32_t)sizeof(TV);
+    const int pass_rows = kWaves * p.rpw;
+    const int nslots = kWaves * p.rpw;
+
+    // Panel range of this workgroup.
+    const int nb = gridDim.x;
+    int p_begin, p_end, p_stride, first;
+    if (nb >= 8) {
+        const int x = blockIdx.x & 7, li = blockIdx.x >> 3;
+        const int gx = nb / 8 + (x < (nb & 7) ? 1 : 0);
+        p_begin = (int)((int64_t)p.npanels * x / 8);
+        p_end = (int)((int64_t)p.npanels * (x + 1) / 8);
+        first = p_begin + li;
+        p_stride = gx;
+    } else {
+        p_begin = 0;
+        p_end = p.npanels;
+        first = blockIdx.x;
+        p_stride = nb;
+    }
+    (void)p_begin;
 
     double sx[N], ss[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) sx[e] = ss[e] = 0.0;
 
-    if (lane_on) {
-        const int pass_rows = kWaves * p.rpw;
-        for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows) {
-            const int kb = rp[row];
-            const int ke = rp[row + 1];
-            TV acc[N];
-#pragma unroll
-            for (int e = 0; e < N; ++e) acc[e] = (TV)0;
-            int k = kb;
-            for (; k + 4 <= ke; k += 4) {
-                const int j0 = ci[k], j1 = ci[k + 1], j2 = ci[k + 2], j3 = ci[k + 3];
-                const TV a0 = (TV)val[k], a1 = (TV)val[k + 1], a2 = (TV)val[k + 2], a3 = (TV)val[k + 3];
-                TV x0[N], x1[N], x2[N], x3[N];
-                Pack<TV>::load(V + j0 * ld + coff, x0);
-                Pack<TV>::load(V + j1 * ld + coff, x1);
-                Pack<TV>::load(V + j2 * ld + coff, x2);
-                Pack<TV>::load(V + j3 * ld + coff, x3);
-#pragma unroll
-                for (int e = 0; e < N; ++e) {
-                    acc[e] = fma(a0, x0[e], acc[e]);
-                    acc[e] = fma(a1, x1[e], acc[e]);
-                    acc[e] = fma(a2, x2[e], acc[e]);
-                    acc[e] = fma(a3, x3[e], acc[e]);
+    for (int panel = first; panel < p_end; panel += p_stride) {
+        const int r0 = panel * p.rows_per_block;
+        const int r1 = min(p.n, r0 + p.rows_per_block);
+
+        // Staging layout in LDS (bytes): [row offsets (R+1) x 4, padded to 8]
+        // [values pnnz x sizeof(TA)] [column indices pnnz x 4].
+        const int R = r1 - r0;
+        const int kbase = rp[r0];
+        const int pnnz = rp[r1] - kbase;
+        const int off_val = ((R + 1) * 4 + 7) & ~7;
+        const int off_ci = off_val + pnnz * (int)sizeof(TA);
+        const bool staged = p.stage && off_ci + pnnz * 4 <= (int)sizeof(smem);
+        if (staged) {
+            char* base = reinterpret_cast<char*>(smem);
+            int32_t* s_rp = reinterpret_cast<int32_t*>(base);
+            TA* s_val = reinterpret_cast<TA*>(base + off_val);
+            int32_t* s_ci = reinterpret_cast<int32_t*>(base + off_ci);
+            for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = rp[r0 + t] - kbase;
+            for (int t = threadIdx.x; t < pnnz; t += kThreads) {
+                s_val[t] = val[kbase + t];
+                s_ci[t] = ci[kbase + t];
+            }
+            __syncthreads();
+            if (lane_on) {
+                for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows) {
+                    const int lr = row - r0;
+                    step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], s_ci, s_val, Vb, Ub, ldb,
+                                                            coffb, p.alpha, p.beta, sx, ss);
                 }
             }
-            for (; k < ke; ++k) {
-                const int j = ci[k];
-                const TV a = (TV)val[k];
-                TV x[N];
-                Pack<TV>::load(V + j * ld + coff, x);
-#pragma unroll
-                for (int e = 0; e < N; ++e) acc[e] = fma(a, x[e], acc[e]);
-            }
-            TV own[N], out[N];
-            Pack<TV>::load(V + row * ld + coff, own);
-            if (FIRST) {
-                // v1 = B v0 = (alpha/2) A v0 + (beta/2) v0
-#pragma unroll
-                for (int e = 0; e < N; ++e)
-                    out[e] = (TV)fma(0.5 * p.alpha, (double)acc[e], 0.5 * p.beta * (double)own[e]);
-            } else {
-                TV u[N];
-                Pack<TV>::load(U + row * ld + coff, u);
-#pragma unroll
-                for (int e = 0; e < N; ++e)
-                    out[e] = (TV)fma(p.alpha, (double)acc[e], fma(p.beta, (double)own[e], -(double)u[e]));
-            }
-            Pack<TV>::store(U + row * ld + coff, out);
-#pragma unroll
-            for (int e = 0; e < N; ++e) {
-                const double o = (double)out[e];
-                sx[e] = fma(o, (double)own[e], sx[e]);
-                ss[e] = fma(o, o, ss[e]);
-            }
+            __syncthreads();  // before the LDS is restaged or reused below
+        } else if (lane_on) {
+            for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows)
+                step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], ci, val, Vb, Ub, ldb, coffb,
+                                                         p.alpha, p.beta, sx, ss);
         }
+    }
+
+    // One partial per workgroup: the lanes' sums over every row they
+    // processed, combined over row slots in a fixed order.
+    double* red = smem;
+    if (lane_on) {
         const int slot = wave * p.rpw + rw;
 #pragma unroll
         for (int e = 0; e < N; ++e) {
@@ -230,8 +333,7 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
         }
     }
     __syncthreads();
-    const int nslots = kWaves * p.rpw;
-    double* __restrict__ outp = p.partial + (int64_t)panel * 2 * p.ld;
+    double* __restrict__ outp = p.partial + (int64_t)blockIdx.x * 2 * p.ld;
     for (int t = threadIdx.x; t < 2 * p.ld; t += kThreads) {
         const int d = t / p.ld;
         const int c = t - d * p.ld;
@@ -241,9 +343,81 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     }
 }
 
+// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8").
+struct StepTune {
+    int stage = 1;
+    int persist = 1;
+    int gather = 8;
+};
+static StepTune read_tune() {
+    StepTune t;
+    const char* e = getenv("KPM_TUNE");
+    if (e) {
+        const char* s;
+        if ((s = strstr(e, "stage="))) t.stage = atoi(s + 6);
+        if ((s = strstr(e, "persist="))) t.persist = atoi(s + 8);
+        if ((s = strstr(e, "gather="))) t.gather = atoi(s + 7) == 4 ? 4 : 8;
+    }
+    return t;
+}
+static const StepTune& tune() {
+    static StepTune t = read_tune();
+    return t;
+}
+
+// Workgroups of `kernel` that fit on the current device at once (0 if unknown).
+static int resident_blocks(const void* kernel) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
+}
+
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
+static int resident_of() {
+    static const int r = resident_blocks(reinterpret_cast<const void*>(cheb_step_kernel<TA, TV, FIRST, OFF32, G>));
+    return r;
+}
+
+template <typename TA, typename TV, bool OFF32, int G>
+static int grid_of(int npanels) {
+    int grid = npanels;
+    if (tune().persist) {
+        const int r = std::min(resident_of<TA, TV, true, OFF32, G>(), resident_of<TA, TV, false, OFF32, G>());
+        if (r > 0 && r < grid) grid = r;
+    }
+    return grid;
+}
+
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
+static hipError_t launch_step_variant(hipStream_t s, const StepParams& p, int grid) {
+    cheb_step_kernel<TA, TV, FIRST, OFF32, G><<<grid, kThreads, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+static bool step_off32(const CsrDev& A, const BlockGeom& g, int precision) {
+    const int esz = precision == KPM_FP64 ? 8 : 4;
+    return (uint64_t)A.n * (uint64_t)g.ld * (uint64_t)esz < (1ull << 32);
+}
+
+int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
+    const bool off32 = step_off32(A, g, precision);
+    const bool g4 = tune().gather == 4;
+#define KPM_GRID(TA, TV)                                                                     \
+    return off32 ? (g4 ? grid_of<TA, TV, true, 4>(g.nblocks) : grid_of<TA, TV, true, 8>(g.nblocks)) \
+                 : (g4 ? grid_of<TA, TV, false, 4>(g.nblocks) : grid_of<TA, TV, false, 8>(g.nblocks))
+    if (precision == KPM_FP64) {
+        if (A.val_f64) KPM_GRID(double, double);
+        KPM_GRID(float, double);
+    }
+    KPM_GRID(float, float);
+#undef KPM_GRID
+}
+
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
-                            const BlockGeom& g, const void* V, void* U, double alpha, double beta,
-                            double* partial) {
+                            const BlockGeom& g, int grid, const void* V, void* U, double alpha,
+                            double beta, double* partial) {
     StepParams p;
     p.rp = A.rp;
     p.ci = A.ci;
@@ -258,21 +432,29 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.lpr = g.lpr;
     p.rpw = g.rpw;
     p.rows_per_block = g.rows_per_block;
-    dim3 grid(g.nblocks), block(kThreads);
-    if (precision == KPM_FP64) {
-        if (A.val_f64) {
-            if (first) cheb_step_kernel<double, double, true><<<grid, block, 0, s>>>(p);
-            else cheb_step_kernel<double, double, false><<<grid, block, 0, s>>>(p);
-        } else {
-            if (first) cheb_step_kernel<float, double, true><<<grid, block, 0, s>>>(p);
-            else cheb_step_kernel<float, double, false><<<grid, block, 0, s>>>(p);
-        }
-    } else {
-        if (A.val_f64) return hipErrorInvalidValue;  // FP32 path takes FP32 values
-        if (first) cheb_step_kernel<float, float, true><<<grid, block, 0, s>>>(p);
-        else cheb_step_kernel<float, float, false><<<grid, block, 0, s>>>(p);
+    p.npanels = g.nblocks;
+    p.stage = tune().stage;
+    const bool off32 = step_off32(A, g, precision);
+    const bool g4 = tune().gather == 4;
+#define KPM_STEP_G(TA, TV, GG)                                                                   \
+    return off32 ? (first ? launch_step_variant<TA, TV, true, true, GG>(s, p, grid)              \
+                          : launch_step_variant<TA, TV, false, true, GG>(s, p, grid))            \
+                 : (first ? launch_step_variant<TA, TV, true, false, GG>(s, p, grid)             \
+                          : launch_step_variant<TA, TV, false, false, GG>(s, p, grid))
+#define KPM_STEP_DISPATCH(TA, TV) \
+    if (g4) {                     \
+        KPM_STEP_G(TA, TV, 4);    \
+    } else {                      \
+        KPM_STEP_G(TA, TV, 8);    \
     }
-    return hipGetLastError();
+    if (precision == KPM_FP64) {
+        if (A.val_f64) KPM_STEP_DISPATCH(double, double);
+        KPM_STEP_DISPATCH(float, double);
+    }
+    if (A.val_f64) return hipErrorInvalidValue;  // the FP32 path takes FP32 values
+    KPM_STEP_DISPATCH(float, float);
+#undef KPM_STEP_DISPATCH
+#undef KPM_STEP_G
 }
 
 // ---------------------------------------------------------------- reductions
