@@ -1,22 +1,21 @@
 // Spectral bounds (Lin, Saad & Yang, section 3.1.1, the paragraph after
-// eq. (cd)): a k-step Lanczos run in FP64 on the device with two passes of
-// full re-orthogonalisation per step.  It leaves alpha[0..m-1] and
-// beta[0..m-1] (beta[j] = norm of the residual after step j) in device
-// memory; the host part of kpm_bounds solves the m x m tridiagonal
-// eigenproblem and widens the extreme Ritz values by their residuals.
+// eq. (cd)): a k-step Lanczos run in FP64 on the device with full
+// re-orthogonalisation (classical Gram-Schmidt applied twice).  It leaves
+// alpha[0..m-1] and beta[0..m-1] (beta[j] = norm of the residual after step
+// j) in device memory; the host part of kpm_bounds solves the m x m
+// tridiagonal eigenproblem and widens the extreme Ritz values by their
+// residuals.
 //
-// Work split: workgroup b owns the contiguous row chunk [b*C, (b+1)*C).
-// Each Lanczos step j is four launches, enqueued without any host sync:
-//   A spmv    q_j = r_{j-1} / beta_{j-1} (beta reduced from the previous
-//             norm partials; q_0 = start probe / sqrt(n)), row j of Q
-//             stored, w = A q_j into the other residual buffer, partial
-//             sums of q_j . w
-//   B axpy    w -= alpha_j q_j + beta_{j-1} q_{j-1}; partials of Q^T w
-//   C reorth  w -= Q h (h reduced from B's partials); partials of Q^T w
-//   D reorth  w -= Q h (from C's partials); partials of w . w
-// Every consumer reduces the per-workgroup partials itself with one fixed
-// summation tree, so all workgroups see bit-identical coefficients and
-// results are deterministic run to run.
+// Step j is three data-parallel launches, each followed by a small
+// reduction launch, all enqueued without any host sync:
+//   A  q_j = r_{j-1} / beta_{j-1} (q_0 = start probe / sqrt(n)), stored as
+//      row j of Q;  w = A q_j;  partials of h = Q^T w    (alpha_j = h_j)
+//   B  w -= Q h;  partials of h' = Q^T w                  (second pass)
+//   C  w -= Q h';  partial of ||w||^2                      (-> beta_j)
+// Every workgroup owns a contiguous chunk of rows (R rows per thread, held
+// in registers) and writes one partial per coefficient; the reduction
+// launch adds them in a fixed order (one workgroup per coefficient), so
+// results are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,7 +24,7 @@
 namespace kpm {
 
 constexpr int LZ_THREADS = 256;
-constexpr int LZ_SLOTS = 32;  // partial slots per workgroup (max Lanczos steps)
+constexpr int LZ_SLOTS = 32;  // max Lanczos steps
 
 __device__ __forceinline__ uint64_t lz_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -39,10 +38,7 @@ __device__ __forceinline__ double lz_start_entry(uint64_t seed, int64_t i, doubl
     return ((lz_mix(seed + k * 0x9e3779b97f4a7c15ull) >> 63) ? -1.0 : 1.0) * inv_sqrt_n;
 }
 
-// coef layout: alpha[0..63], beta[64..127]
-#define ALPHA(j) coef[(j)]
-#define BETA(j) coef[64 + (j)]
-
+// coef layout (doubles): alpha[0..63], beta[64..127], h1[128..159], h2[160..191]
 struct LzArgs {
     const int32_t* rp;
     const int32_t* ci;
@@ -50,140 +46,182 @@ struct LzArgs {
     double* Q;       // [m][n]
     double* W[2];    // residual buffers
     double* coef;
-    double* part;    // [4 kinds][nblk][LZ_SLOTS]
+    double* part;    // [3 kinds][LZ_SLOTS][nblk]
     uint64_t seed;
     int32_t n, nblk, chunk;
 };
 
-__device__ __forceinline__ double* part_of(const LzArgs& a, int kind, int b) {
-    return a.part + ((int64_t)kind * a.nblk + b) * LZ_SLOTS;
+__device__ __forceinline__ double* part_slot(const LzArgs& a, int kind, int t) {
+    return a.part + ((int64_t)kind * LZ_SLOTS + t) * a.nblk;
 }
 
-// Sum of slot t over all workgroups of `kind`, by one wavefront: lane l adds
-// workgroups l, l+64, ... in order, then a fixed butterfly combines the
-// lanes.  Every workgroup that calls this gets the same bits.
-__device__ __forceinline__ double lz_wave_sum_partials(const LzArgs& a, int kind, int t) {
-    const int lane = threadIdx.x & 63;
-    double s = 0.0;
-    for (int b = lane; b < a.nblk; b += 64) s += part_of(a, kind, b)[t];
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    return s;
-}
-
-// Reduce slots [0, J) of `kind` into hs[]: wavefront w handles t = w, w+4, ...
-__device__ __forceinline__ void lz_reduce_into(const LzArgs& a, int kind, int J, double* hs) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < J; t += LZ_THREADS / 64) {
-        const double v = lz_wave_sum_partials(a, kind, t);
-        if (lane == 0) hs[t] = v;
-    }
-    __syncthreads();
-}
-
-// Workgroup sum of one value per thread: butterfly per wavefront, then the
-// four wavefront sums in order.  Every thread returns the total.
-__device__ __forceinline__ double lz_block_sum(double v, double* sh4) {
+__device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh4[wave] = v;
-    __syncthreads();
-    return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+    return v;
 }
 
-template <typename TA>
-__global__ __launch_bounds__(LZ_THREADS) void lz_spmv(LzArgs a, int j) {
-    __shared__ double sh4[4];
-    __shared__ double s_inv;
-    const int b = blockIdx.x;
+// Store this workgroup's J partial sums (wavefront sums in sh[wave][t]).
+__device__ __forceinline__ void lz_store_partials(const LzArgs& a, int kind, int J, double (*sh)[LZ_SLOTS]) {
+    __syncthreads();
+    if ((int)threadIdx.x < J) {
+        const int t = threadIdx.x;
+        part_slot(a, kind, t)[blockIdx.x] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+    }
+}
+
+// out[t] = sum over workgroups of partial slot t of `kind` (square root when
+// MODE == 2; MODE == 0 also copies slot j to alpha_j).  Workgroup t: each
+// thread adds workgroups tid, tid+256, ... in order, then a fixed tree.
+template <int MODE>
+__global__ __launch_bounds__(LZ_THREADS) void lz_reduce(LzArgs a, int kind, int j, double* out) {
+    __shared__ double sh[LZ_THREADS / 64];
+    const int t = blockIdx.x;
+    const double* p = part_slot(a, kind, t);
+    double s = 0.0;
+    for (int b = threadIdx.x; b < a.nblk; b += LZ_THREADS) s += p[b];
+    s = wave_sum(s);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        if (MODE == 2) {
+            out[t] = sqrt(r > 0.0 ? r : 0.0);
+        } else {
+            out[t] = r;
+            if (MODE == 0 && t == j) a.coef[j] = r;  // alpha_j = q_j^T A q_j
+        }
+    }
+}
+
+// A: normalise, w = A q_j, first projection h = Q^T w.
+template <typename TA, int R>
+__global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double* __restrict__ wr = a.W[(j + 1) & 1];
     double* __restrict__ ww = a.W[j & 1];
     const TA* __restrict__ val = static_cast<const TA*>(a.val);
     const double inv_sqrt_n = 1.0 / sqrt((double)a.n);
-    if (threadIdx.x < 64) {
-        double inv = 0.0;
-        if (j > 0) {
-            const double nrm2 = lz_wave_sum_partials(a, 3, 0);
-            const double beta = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
-            inv = beta > 0.0 ? 1.0 / beta : 0.0;
-            if (b == 0 && threadIdx.x == 0) a.coef[64 + j - 1] = beta;
-        }
-        if (threadIdx.x == 0) s_inv = inv;
+    double inv = 0.0;
+    if (j > 0) {
+        const double beta = a.coef[64 + j - 1];
+        inv = beta > 0.0 ? 1.0 / beta : 0.0;
     }
-    __syncthreads();
-    const double inv = s_inv;
-    double* __restrict__ qj = a.Q + (int64_t)j * a.n;
-    const int64_t i0 = (int64_t)b * a.chunk;
-    const int64_t i1 = min((int64_t)a.n, i0 + a.chunk);
-    double acc = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += LZ_THREADS) {
-        double s = 0.0;
-        for (int32_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
-            const int32_t c = a.ci[k];
-            const double q = j == 0 ? lz_start_entry(a.seed, c, inv_sqrt_n) : wr[c] * inv;
-            s = fma((double)val[k], q, s);
+    const int64_t n = a.n;
+    double* __restrict__ qj = a.Q + (int64_t)j * n;
+    const int64_t i0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x;
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + (int64_t)r * LZ_THREADS;
+        x[r] = 0.0;
+        if (i < n) {
+            double s = 0.0;
+            const int32_t kb = a.rp[i], ke = a.rp[i + 1];
+            for (int32_t k = kb; k < ke; k += 4) {
+                double q4[4], v4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (k + u < ke) {
+                        const int32_t c = a.ci[k + u];
+                        v4[u] = (double)val[k + u];
+                        q4[u] = j == 0 ? lz_start_entry(a.seed, c, inv_sqrt_n) : wr[c] * inv;
+                    } else {
+                        v4[u] = 0.0;
+                        q4[u] = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s = fma(v4[u], q4[u], s);
+            }
+            qj[i] = j == 0 ? lz_start_entry(a.seed, i, inv_sqrt_n) : wr[i] * inv;
+            ww[i] = s;
+            x[r] = s;
         }
-        const double qi = j == 0 ? lz_start_entry(a.seed, i, inv_sqrt_n) : wr[i] * inv;
-        qj[i] = qi;
-        ww[i] = s;
-        acc = fma(qi, s, acc);
     }
-    const double tot = lz_block_sum(acc, sh4);
-    if (threadIdx.x == 0) part_of(a, 0, b)[0] = tot;
+    // h_t = q_t . w for t <= j (this thread wrote its rows of q_j above).
+    for (int t = 0; t <= j; ++t) {
+        const double* __restrict__ qt = a.Q + (int64_t)t * n;
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = i0 + (int64_t)r * LZ_THREADS;
+            if (i < n) acc = fma(qt[i], x[r], acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) sh[wave][t] = acc;
+    }
+    lz_store_partials(a, 0, j + 1, sh);
 }
 
-// MODE 0: w -= alpha_j q_j + beta_{j-1} q_{j-1}, partials of Q^T w -> kind 1
-// MODE 1: w -= Q h (h from kind 1),              partials of Q^T w -> kind 2
-// MODE 2: w -= Q h (h from kind 2),              partial of w . w  -> kind 3
-template <int MODE>
+// B (PASS 0): w -= Q h1; h2 = Q^T w.   C (PASS 1): w -= Q h2; beta_j = ||w||.
+template <int PASS, int R>
 __global__ __launch_bounds__(LZ_THREADS) void lz_orth(LzArgs a, int j) {
-    extern __shared__ double xs[];  // the workgroup's chunk of w
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
     __shared__ double hs[LZ_SLOTS];
-    __shared__ double sh4[4];
-    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int J = j + 1;
     double* __restrict__ ww = a.W[j & 1];
-    const double* __restrict__ coef = a.coef;
-    lz_reduce_into(a, MODE, MODE == 0 ? 1 : J, hs);
-    if (MODE == 0 && b == 0 && threadIdx.x == 0) a.coef[j] = hs[0];
-    const int64_t i0 = (int64_t)b * a.chunk;
-    const int64_t i1 = min((int64_t)a.n, i0 + a.chunk);
-    const double* __restrict__ Q = a.Q;
+    if ((int)threadIdx.x < J) hs[threadIdx.x] = a.coef[(PASS == 0 ? 128 : 160) + threadIdx.x];
+    __syncthreads();
     const int64_t n = a.n;
-    double nrm = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += LZ_THREADS) {
-        double x = ww[i];
-        if (MODE == 0) {
-            x = x - hs[0] * Q[(int64_t)j * n + i];
-            if (j > 0) x = x - BETA(j - 1) * Q[(int64_t)(j - 1) * n + i];
-        } else {
+    const double* __restrict__ Q = a.Q;
+    const int64_t i0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x;
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + (int64_t)r * LZ_THREADS;
+        x[r] = 0.0;
+        if (i < n) {
             double s = 0.0;
             for (int t = 0; t < J; ++t) s = fma(hs[t], Q[(int64_t)t * n + i], s);
-            x = x - s;
+            x[r] = ww[i] - s;
+            ww[i] = x[r];
         }
-        ww[i] = x;
-        if (MODE == 2) nrm = fma(x, x, nrm);
-        else xs[i - i0] = x;
     }
-    if (MODE == 2) {
-        const double tot = lz_block_sum(nrm, sh4);
-        if (threadIdx.x == 0) part_of(a, 3, b)[0] = tot;
+    if (PASS == 1) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc = fma(x[r], x[r], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) sh[wave][0] = acc;
+        lz_store_partials(a, 2, 1, sh);
         return;
     }
-    __syncthreads();
     for (int t = 0; t < J; ++t) {
         const double* __restrict__ qt = Q + (int64_t)t * n;
         double acc = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += LZ_THREADS) acc = fma(qt[i], xs[i - i0], acc);
-        const double tot = lz_block_sum(acc, sh4);
-        if (threadIdx.x == 0) part_of(a, MODE + 1, b)[t] = tot;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = i0 + (int64_t)r * LZ_THREADS;
+            if (i < n) acc = fma(qt[i], x[r], acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) sh[wave][t] = acc;
+    }
+    lz_store_partials(a, 1, J, sh);
+}
+
+template <int R>
+static void lz_launch_steps(hipStream_t s, const CsrDev& A, int m, const LzArgs& a) {
+    for (int j = 0; j < m; ++j) {
+        if (A.val_f64) lz_spmv_project<double, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+        else lz_spmv_project<float, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+        lz_reduce<0><<<j + 1, LZ_THREADS, 0, s>>>(a, 0, j, a.coef + 128);
+        lz_orth<0, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+        lz_reduce<1><<<j + 1, LZ_THREADS, 0, s>>>(a, 1, j, a.coef + 160);
+        lz_orth<1, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+        lz_reduce<2><<<1, LZ_THREADS, 0, s>>>(a, 2, j, a.coef + 64 + j);
     }
 }
 
-// beta_{m-1} from the last norm partials.
-__global__ void lz_last_beta(LzArgs a, int m) {
-    const double nrm2 = lz_wave_sum_partials(a, 3, 0);
-    if (threadIdx.x == 0) a.coef[64 + m - 1] = sqrt(nrm2 > 0.0 ? nrm2 : 0.0);
+// Rows per thread: the smallest power of two (<= 16) that keeps the grid
+// at or under 1024 workgroups.
+int lanczos_rows_per_thread(int64_t n) {
+    int R = 1;
+    while (R < 16 && (int64_t)LZ_THREADS * R * 1024 < n) R *= 2;
+    return R;
 }
 
 hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, LanczosWork& W) {
@@ -200,15 +238,14 @@ hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, 
     a.n = A.n;
     a.nblk = W.nblk;
     a.chunk = W.chunk;
-    const size_t lds = (size_t)W.chunk * sizeof(double);
-    for (int j = 0; j < m; ++j) {
-        if (A.val_f64) lz_spmv<double><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
-        else lz_spmv<float><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
-        lz_orth<0><<<a.nblk, LZ_THREADS, lds, s>>>(a, j);
-        lz_orth<1><<<a.nblk, LZ_THREADS, lds, s>>>(a, j);
-        lz_orth<2><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+    switch (W.chunk / LZ_THREADS) {
+        case 1: lz_launch_steps<1>(s, A, m, a); break;
+        case 2: lz_launch_steps<2>(s, A, m, a); break;
+        case 4: lz_launch_steps<4>(s, A, m, a); break;
+        case 8: lz_launch_steps<8>(s, A, m, a); break;
+        case 16: lz_launch_steps<16>(s, A, m, a); break;
+        default: return hipErrorInvalidValue;
     }
-    lz_last_beta<<<1, 64, 0, s>>>(a, m);
     return hipGetLastError();
 }
 

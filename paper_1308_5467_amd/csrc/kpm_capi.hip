@@ -276,23 +276,18 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     const int n = A.n;
     const int m = std::min(steps, n);
     LanczosWork W;
-    W.nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, ((int64_t)n + 255) / 256));
-    W.chunk = (int)(((int64_t)n + W.nblk - 1) / W.nblk);
-    if (W.chunk > 8192) {
-        W.chunk = 8192;
-        W.nblk = (int)(((int64_t)n + 8191) / 8192);
-    }
+    W.chunk = 256 * lanczos_rows_per_thread(n);
+    W.nblk = (int)(((int64_t)n + W.chunk - 1) / W.chunk);
     void *Q, *w, *coef, *part;
     if ((st = kpm_ws(ctx, "lz_Q", (size_t)m * n * 8, &Q)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "lz_w", (size_t)2 * n * 8, &w)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "lz_coef", 256 * 8, &coef)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "lz_part", (size_t)4 * W.nblk * 32 * 8 + (size_t)2 * 8 * W.nblk, &part)) != KPM_OK)
+    if ((st = kpm_ws(ctx, "lz_part", (size_t)3 * 32 * W.nblk * 8 + (size_t)2 * 8 * W.nblk, &part)) != KPM_OK)
         return st;
     W.Q = (double*)Q;
     W.w = (double*)w;
     W.coef = (double*)coef;
     W.partial = (double*)part;
-    KPM_HIP(ctx, hipMemsetAsync(coef, 0, 256 * 8, ctx->stream));
     kpm_prof_begin(ctx, "lanczos");
     KPM_HIP(ctx, launch_lanczos(ctx->stream, A, m, seed, W));
     kpm_prof_end(ctx, "lanczos", 1);
@@ -332,7 +327,7 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     double lb0 = theta[0] - rlo, ub0 = theta[k - 1] + rhi;
     if (breakdown) {
         const int gb = W.nblk;
-        double* gout = (double*)part + (size_t)4 * W.nblk * 32;
+        double* gout = (double*)part + (size_t)3 * 32 * W.nblk;
         KPM_HIP(ctx, launch_gershgorin(ctx->stream, A, gout, gb));
         std::vector<double> hg(2 * gb);
         KPM_HIP(ctx, hipMemcpyAsync(hg.data(), gout, 2 * gb * 8, hipMemcpyDeviceToHost, ctx->stream));

@@ -24,10 +24,17 @@ hipError_t launch_jackson(hipStream_t s, int M, double* g) {
 }
 
 // phi(x) = [g_0 mu_0 + 2 sum_{k>=1} g_k mu_k T_k(t)] / (pi d sqrt(1 - t^2)),
-// t = (x - c)/d, the Chebyshev sum evaluated by Clenshaw's recurrence.
-__global__ void dos_kernel(const double* __restrict__ mu, const double* __restrict__ g, int M,
-                           double c, double d, const double* __restrict__ x, int npts,
-                           double* __restrict__ phi) {
+// t = (x - c)/d, the Chebyshev sum evaluated by Clenshaw's recurrence.  The
+// coefficients g_k mu_k are first staged in LDS when they fit.
+constexpr int kDosLds = 4096;
+__global__ __launch_bounds__(128) void dos_kernel(const double* __restrict__ mu, const double* __restrict__ g,
+                                                  int M, double c, double d, const double* __restrict__ x,
+                                                  int npts, double* __restrict__ phi) {
+    __shared__ double cf[kDosLds];
+    const bool lds = M + 1 <= kDosLds;
+    if (lds)
+        for (int k = threadIdx.x; k <= M; k += blockDim.x) cf[k] = g[k] * mu[k];
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     const double t = (x[i] - c) / d;
@@ -37,7 +44,8 @@ __global__ void dos_kernel(const double* __restrict__ mu, const double* __restri
     }
     double b1 = 0.0, b2 = 0.0;
     for (int k = M; k >= 1; --k) {
-        const double b0 = 2.0 * g[k] * mu[k] + 2.0 * t * b1 - b2;
+        const double ck = lds ? cf[k] : g[k] * mu[k];
+        const double b0 = 2.0 * ck + 2.0 * t * b1 - b2;
         b2 = b1;
         b1 = b0;
     }

@@ -56,11 +56,12 @@ hipError_t launch_validate_csr(hipStream_t s, const CsrDev& A, int* flags);
 struct LanczosWork {
     double* Q = nullptr;        // [m x n] Lanczos vectors
     double* w = nullptr;        // [2 x n] residual ping-pong buffers
-    double* coef = nullptr;     // alpha[64], beta[64]
-    double* partial = nullptr;  // [4 x nblk x 32] per-workgroup partial sums
+    double* coef = nullptr;     // alpha[64], beta[64], two projection vectors [32]
+    double* partial = nullptr;  // [3 x 32 x nblk] per-workgroup partial sums
     int nblk = 0;               // workgroups
-    int chunk = 0;              // rows per workgroup (<= 8192)
+    int chunk = 0;              // rows per workgroup = 256 * rows per thread
 };
+int lanczos_rows_per_thread(int64_t n);
 hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, LanczosWork& W);
 hipError_t launch_gershgorin(hipStream_t s, const CsrDev& A, double* out /* [2 * nblk] */, int nblk);
 

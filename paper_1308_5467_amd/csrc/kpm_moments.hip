@@ -101,6 +101,7 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
         int passes = (8192 / row_bytes + rows_per_pass / 2) / rows_per_pass;
         if (passes < 1) passes = 1;
         rows = passes * rows_per_pass;
+    }
     g.rows_per_block = rows;
     g.nblocks = (int)((n + rows - 1) / rows);
     return g;
@@ -458,39 +459,47 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
 }
 
 // ---------------------------------------------------------------- reductions
-// dots[k][t] = sum over panels b of partial[k][b][t], Neumaier-compensated.
-// Workgroup (x, k) covers columns t in [64x, 64x+64); its 4 wavefronts take
-// contiguous quarters of the panel range and are combined in order.
-__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ partial,
-                                                              int nblocks, int width,
-                                                              double* __restrict__ dots) {
-    __shared__ double sh_s[4][64], sh_c[4][64];
+// dots[k][t] = sum over workgroups b of partial[k][b][t], Neumaier-compensated.
+// Workgroup (x, k) covers columns t in [64x, 64x+64); its 16 wavefronts take
+// contiguous slices of the workgroup range and are combined in order.
+constexpr int kRedWaves = 16;
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+    const double u = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
+    s = u;
+}
+
+__global__ __launch_bounds__(64 * kRedWaves) void reduce_partials_kernel(const double* __restrict__ partial,
+                                                                        int nblocks, int width,
+                                                                        double* __restrict__ dots) {
+    __shared__ double sh_s[kRedWaves][64], sh_c[kRedWaves][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = blockIdx.x * 64 + lane;
     const int k = blockIdx.y;
-    const int per = (nblocks + 3) / 4;
+    const int per = (nblocks + kRedWaves - 1) / kRedWaves;
     const int b0 = wave * per;
     const int b1 = min(nblocks, b0 + per);
     double s = 0.0, c = 0.0;
     if (t < width) {
         const double* src = partial + (int64_t)k * nblocks * width + t;
-        for (int b = b0; b < b1; ++b) {
-            const double x = src[(int64_t)b * width];
-            const double u = s + x;
-            c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
-            s = u;
+        int b = b0;
+        for (; b + 4 <= b1; b += 4) {
+            const double x0 = src[(int64_t)b * width], x1 = src[(int64_t)(b + 1) * width];
+            const double x2 = src[(int64_t)(b + 2) * width], x3 = src[(int64_t)(b + 3) * width];
+            neumaier_add(s, c, x0);
+            neumaier_add(s, c, x1);
+            neumaier_add(s, c, x2);
+            neumaier_add(s, c, x3);
         }
+        for (; b < b1; ++b) neumaier_add(s, c, src[(int64_t)b * width]);
     }
     sh_s[wave][lane] = s;
     sh_c[wave][lane] = c;
     __syncthreads();
     if (wave == 0 && t < width) {
         double S = 0.0, C = 0.0;
-        for (int w = 0; w < 4; ++w) {
-            const double x = sh_s[w][lane];
-            const double u = S + x;
-            C += (fabs(S) >= fabs(x)) ? (S - u) + x : (x - u) + S;
-            S = u;
+        for (int w = 0; w < kRedWaves; ++w) {
+            neumaier_add(S, C, sh_s[w][lane]);
             C += sh_c[w][lane];
         }
         dots[(int64_t)k * width + t] = S + C;
@@ -501,7 +510,7 @@ hipError_t launch_reduce_partials(hipStream_t s, const double* partial, int nblo
                                   int K, double* dots) {
     if (K <= 0) return hipSuccess;
     dim3 grid((width + 63) / 64, K);
-    reduce_partials_kernel<<<grid, 256, 0, s>>>(partial, nblocks, width, dots);
+    reduce_partials_kernel<<<grid, 64 * kRedWaves, 0, s>>>(partial, nblocks, width, dots);
     return hipGetLastError();
 }
 
@@ -538,23 +547,21 @@ hipError_t launch_assemble(hipStream_t s, const double* dots, int K, int ld, int
     return hipGetLastError();
 }
 
-// mu[k] = (1/nvec) sum_l zeta_norm[l][k], compensated, in probe order.
-__global__ void mean_moments_kernel(const double* __restrict__ zeta_norm, int nvec, int M,
-                                    double* __restrict__ mu) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > M) return;
+// mu[k] = (1/nvec) sum_l zeta_norm[l][k]: one wavefront per k; lane j adds
+// probes j, j+64, ... with compensation, then a fixed butterfly.
+__global__ __launch_bounds__(64) void mean_moments_kernel(const double* __restrict__ zeta_norm, int nvec, int M,
+                                                          double* __restrict__ mu) {
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
     double s = 0.0, c = 0.0;
-    for (int l = 0; l < nvec; ++l) {
-        const double x = zeta_norm[(int64_t)l * (M + 1) + k];
-        const double u = s + x;
-        c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
-        s = u;
-    }
-    mu[k] = (s + c) / (double)nvec;
+    for (int l = lane; l < nvec; l += 64) neumaier_add(s, c, zeta_norm[(int64_t)l * (M + 1) + k]);
+    s += c;
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) mu[k] = s / (double)nvec;
 }
 
 hipError_t launch_mean_moments(hipStream_t s, const double* zeta_norm, int nvec, int M, double* mu) {
-    mean_moments_kernel<<<(M + 1 + 127) / 128, 128, 0, s>>>(zeta_norm, nvec, M, mu);
+    mean_moments_kernel<<<M + 1, 64, 0, s>>>(zeta_norm, nvec, M, mu);
     return hipGetLastError();
 }
 
