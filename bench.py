@@ -30,10 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per dispatch of the fused step kernel from rocprofv3 --pmc
-# FETCH_SIZE + WRITE_SIZE on this workload, scaled by the copy-kernel
-# calibration factor; None until measured for the current kernel.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per dispatch of the fused step kernel on the default workload,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
+# what the same counters read for a plain copy of known size (2.000 and
+# 1.000); see profiles/.  Only valid for the default workload and the
+# kernel version it was measured on.
+MEASURED_TRAFFIC_BYTES = 271789238
 
 
 def parse():
@@ -116,7 +118,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": MEASURED_TRAFFIC_BYTES,
+            "traffic": (MEASURED_TRAFFIC_BYTES if (args.grid, M, nvec, block, args.precision) == (64, 256, 64, 64, "f32")
+                        else None),
             "kernel": "cheb_step_kernel", "avg_launch_us": round(avg_ms * 1000, 2),
             "launches": nl, "algorithmic_bytes_per_launch": int(bytes_per_launch),
             "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy_probe": round(achieved / copy_gbs, 4)}

@@ -81,7 +81,13 @@ typedef struct {
     uint64_t seed;      /* probe-vector seed                                   */
     int32_t validate;   /* 1: check the CSR structure and values first          */
     int32_t rows_per_block; /* row-panel height per workgroup, 0 = library choice */
+    int32_t flags;      /* KPM_FLAG_* bits, 0 = defaults                        */
 } kpm_moment_opts;
+
+enum {
+    KPM_FLAG_NO_GRAPH = 1 /* kpm_moments_batched: launch directly instead of
+                             replaying the captured HIP graph                */
+};
 
 typedef enum {
     KPM_DAMP_NONE = 0,    /* g_k = 1                                            */
@@ -114,6 +120,12 @@ kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_t seed,
                       double margin, double* lb, double* ub);
 
 /*
+ * kpm_gershgorin -- the Gershgorin hull [min_i a_ii - sum_j!=i |a_ij|,
+ * max_i a_ii + sum_j!=i |a_ij|], which always contains the spectrum.
+ */
+kpm_status kpm_gershgorin(kpm_ctx* ctx, const kpm_csr* A, double* lo, double* hi);
+
+/*
  * kpm_moments -- normalised stochastic Chebyshev moments mu[0..M] of
  * B = (A - cI)/d (Algorithm 1; eqs. (nuk), (3term), (muEst)), using the
  * product identity T_{p+q} = 2 T_p T_q - T_{|p-q|} (Appendix A) so that
@@ -130,16 +142,40 @@ kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
                        const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
 
 /*
- * kpm_moments_batched -- the same for nmat independent matrices of uneven
- * size in one persistent launch per call (work queue over all matrices,
- * vector blocks and row panels, with per-matrix step ordering), optionally
- * replayed from a captured HIP graph.  lb, ub: host [nmat].  All matrices
- * share opts (M, nvec, block, precision, seed); matrix m uses probe vectors
- * of seed opts->seed + m.  mu: host [nmat * (M+1)].
- * A[m].on_device must be 1 for every m.
+ * kpm_moments_robust -- bounds and moments with escape recovery.  The
+ * Lanczos bound of kpm_bounds can miss an extreme eigenvalue whose
+ * eigenvector barely overlaps the start vector (e.g. localised edge states
+ * of strongly disordered models); the moments then grow exponentially
+ * (section 3.1.1), which kpm_moments detects.  This entry point runs
+ * kpm_bounds(steps, lanczos_seed, margin) and kpm_moments; on
+ * KPM_ERR_SPECTRUM it retries with margin 4x (capped at 0.4), then with the
+ * Gershgorin hull widened by `margin`.  *lb, *ub receive the interval the
+ * returned moments belong to; *attempts (nullable) the number of moment
+ * runs (1 to 3).
+ */
+kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_t lanczos_seed,
+                              double margin, const kpm_moment_opts* opts, double* mu, double* mu_per_vec,
+                              double* lb, double* ub, int* attempts);
+
+/*
+ * kpm_moments_batched -- the same moments for nmat independent matrices of
+ * uneven size.  Each recurrence step is one launch over every (matrix,
+ * probe block, row-panel range) of all matrices; the launch sequence is
+ * captured once per shape (matrix pointers and sizes, M, nvec, block,
+ * precision) in a HIP graph on a context-owned stream and replayed on later
+ * calls (KPM_FLAG_NO_GRAPH launches it directly).  lb, ub: host [nmat].
+ * All matrices share opts (M, nvec, block, precision, seed); matrix m uses
+ * probe vectors of seed opts->seed + m.  mu: host [nmat * (M+1)], mu[m*(M+1)+k].
+ * A[m].on_device must be 1 and the value type common to all m; the FP32
+ * path needs FP32 values.  max_abs_mu: host [nmat] or NULL; receives the
+ * largest |v_l^T T_k(B) v_l| / n over probes and degrees of each matrix (at
+ * most 1 when its spectrum lies in [lb, ub]; +inf if non-finite).  Returns
+ * KPM_ERR_SPECTRUM (after writing every output) if a matrix's spectrum is
+ * not inside its [lb, ub].  nmat <= 65535.
  */
 kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
-                               const double* ub, const kpm_moment_opts* opts, double* mu);
+                               const double* ub, const kpm_moment_opts* opts, double* mu,
+                               double* max_abs_mu);
 
 /*
  * kpm_damping_factors -- damping factors g[0..M] (host, written).

@@ -32,6 +32,7 @@ EXPORTS = [
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
+    "kpm_gershgorin", "kpm_moments_robust",
 ]
 
 
@@ -51,7 +52,7 @@ class kpm_csr(ctypes.Structure):
 class kpm_moment_opts(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("nvec", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("validate", ctypes.c_int32),
-                ("rows_per_block", ctypes.c_int32)]
+                ("rows_per_block", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,7 +74,9 @@ def load_library(path: str = LIB_PATH):
         "kpm_last_error": ([P], ctypes.c_char_p),
         "kpm_bounds": ([P, P, I32, U64, D, P, P], I32),
         "kpm_moments": ([P, P, D, D, P, P, P], I32),
-        "kpm_moments_batched": ([P, I32, P, P, P, P, P], I32),
+        "kpm_moments_batched": ([P, I32, P, P, P, P, P, P], I32),
+        "kpm_gershgorin": ([P, P, P, P], I32),
+        "kpm_moments_robust": ([P, P, I32, U64, D, P, P, P, P, P, P], I32),
         "kpm_damping_factors": ([P, I32, I32, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
@@ -217,9 +220,13 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
     return lb.value, ub.value
 
 
-def _opts(M, nvec, seed, precision, block, validate, rows_per_block) -> kpm_moment_opts:
+KPM_FLAG_NO_GRAPH = 1
+
+
+def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
     prec = KPM_FP64 if precision in ("f64", "float64", KPM_FP64) else KPM_FP32
-    return kpm_moment_opts(M, nvec, block, prec, seed & (2**64 - 1), 1 if validate else 0, rows_per_block)
+    return kpm_moment_opts(M, nvec, block, prec, seed & (2**64 - 1), 1 if validate else 0, rows_per_block,
+                           flags)
 
 
 def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
@@ -237,14 +244,48 @@ def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: 
 
 
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",
-                        block: int = 0, validate: bool = False):
-    o = _opts(M, nvec, seed, precision, block, validate, 0)
+                        block: int = 0, validate: bool = False, graph: bool = True, rows_per_block: int = 0,
+                        return_max_abs: bool = False):
+    """Moments [nmat, M+1] of several device-resident matrices in one launch per step.
+
+    With return_max_abs=True returns (mu, max_abs) and does not raise on a
+    spectrum escape (max_abs[m] > 1 marks the matrices whose [lb, ub] was too narrow).
+    """
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, 0 if graph else KPM_FLAG_NO_GRAPH)
     arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
     lbv, ubv = _f64(lb), _f64(ub)
     mu = np.zeros((len(mats), M + 1))
-    ctx.check(ctx.lib.kpm_moments_batched(ctx.handle, len(mats), arr, _p(lbv), _p(ubv),
-                                          ctypes.byref(o), _p(mu)))
+    mx = np.zeros(len(mats))
+    st = ctx.lib.kpm_moments_batched(ctx.handle, len(mats), arr, _p(lbv), _p(ubv), ctypes.byref(o), _p(mu), _p(mx))
+    if return_max_abs:
+        if st not in (0, -4):
+            ctx.check(st)
+        return mu, mx
+    ctx.check(st)
     return mu
+
+
+def kpm_gershgorin(ctx: Context, A):
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_gershgorin(ctx.handle, ctypes.byref(c), ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
+def kpm_moments_robust(ctx: Context, A, M: int, nvec: int, seed: int, steps: int = 20, lanczos_seed: int = 0,
+                       margin: float = 0.01, precision="f32", block: int = 0, validate: bool = True,
+                       per_vector: bool = False):
+    """Bounds + moments with escape recovery; returns (mu, lb, ub, attempts) (+ per-probe moments)."""
+    o = _opts(M, nvec, seed, precision, block, validate, 0)
+    mu = np.zeros(M + 1)
+    pv = np.zeros((nvec, M + 1)) if per_vector else None
+    lb, ub, att = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_moments_robust(ctx.handle, ctypes.byref(c), steps, lanczos_seed, margin, ctypes.byref(o),
+                                         _p(mu), _p(pv) if pv is not None else None, ctypes.byref(lb),
+                                         ctypes.byref(ub), ctypes.byref(att)))
+    out = (mu, lb.value, ub.value, att.value)
+    return out + (pv,) if per_vector else out
 
 
 def kpm_damping_factors(ctx: Context, kind: int, M: int, mu=None) -> np.ndarray:

@@ -51,7 +51,12 @@ kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out) {
     return KPM_OK;
 }
 
-void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) {
+void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) { kpm_prof_begin_on(ctx, kernel, ctx->stream); }
+void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches) {
+    kpm_prof_end_on(ctx, kernel, ctx->stream, launches);
+}
+
+void kpm_prof_begin_on(kpm_ctx* ctx, const char* kernel, hipStream_t stream) {
     if (!ctx->prof) return;
     kpm_prof_entry& e = ctx->prof_map[kernel];
     if (e.used + 2 > e.ev.size()) {
@@ -61,14 +66,14 @@ void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) {
             e.ev.push_back(ev);
         }
     }
-    hipEventRecord(e.ev[e.used], ctx->stream);
+    hipEventRecord(e.ev[e.used], stream);
 }
 
-void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches) {
+void kpm_prof_end_on(kpm_ctx* ctx, const char* kernel, hipStream_t stream, int launches) {
     if (!ctx->prof) return;
     kpm_prof_entry& e = ctx->prof_map[kernel];
     if (e.used + 2 > e.ev.size()) return;
-    hipEventRecord(e.ev[e.used + 1], ctx->stream);
+    hipEventRecord(e.ev[e.used + 1], stream);
     e.counts.push_back(launches);
     e.used += 2;
 }
@@ -108,8 +113,7 @@ static kpm_status check_csr_args(kpm_ctx* ctx, const kpm_csr* A) {
 
 // Device view of A; host arrays are copied into the context, FP64 values are
 // rounded to FP32 when the FP32 path is requested.
-static kpm_status prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, CsrDev* out,
-                              const char* tag = "") {
+kpm_status kpm_prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, CsrDev* out, const char* tag) {
     kpm_status st = check_csr_args(ctx, A);
     if (st != KPM_OK) return st;
     CsrDev D;
@@ -148,7 +152,7 @@ static kpm_status prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, Csr
     return KPM_OK;
 }
 
-static kpm_status validate_csr(kpm_ctx* ctx, const CsrDev& D) {
+kpm_status kpm_validate_csr(kpm_ctx* ctx, const CsrDev& D) {
     void* f;
     kpm_status st = kpm_ws(ctx, "flags", 64, &f);
     if (st != KPM_OK) return st;
@@ -182,6 +186,7 @@ extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
     if (!ctx) return KPM_ERR_ARG;
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
+    kpm_batch_free(ctx);
     for (auto& kv : ctx->bufs)
         if (kv.second.p) hipFree(kv.second.p);
     if (ctx->mlp_params.p) hipFree(ctx->mlp_params.p);
@@ -271,7 +276,7 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     if (!(margin >= 0.0 && margin < 0.5)) return kpm_fail(ctx, KPM_ERR_ARG, "margin must be in [0, 0.5)");
     KPM_HIP(ctx, hipSetDevice(ctx->device));
     CsrDev A;
-    kpm_status st = prepare_csr(ctx, Ain, KPM_FP64, &A);
+    kpm_status st = kpm_prepare_csr(ctx, Ain, KPM_FP64, &A, "");
     if (st != KPM_OK) return st;
     const int n = A.n;
     const int m = std::min(steps, n);
@@ -346,6 +351,32 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     return KPM_OK;
 }
 
+extern "C" kpm_status kpm_gershgorin(kpm_ctx* ctx, const kpm_csr* Ain, double* lo, double* hi) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!lo || !hi) return kpm_fail(ctx, KPM_ERR_ARG, "lo/hi output is NULL");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    CsrDev A;
+    kpm_status st = kpm_prepare_csr(ctx, Ain, KPM_FP64, &A, "");
+    if (st != KPM_OK) return st;
+    const int nblk = (int)std::min<int64_t>(1024, ((int64_t)A.n + 255) / 256);
+    void* g;
+    if ((st = kpm_ws(ctx, "gersh", (size_t)2 * nblk * 8, &g)) != KPM_OK) return st;
+    KPM_HIP(ctx, launch_gershgorin(ctx->stream, A, (double*)g, nblk));
+    std::vector<double> hg(2 * nblk);
+    KPM_HIP(ctx, hipMemcpyAsync(hg.data(), g, hg.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    double a = hg[0], b = hg[1];
+    for (int i = 1; i < nblk; ++i) {
+        a = std::min(a, hg[2 * i]);
+        b = std::max(b, hg[2 * i + 1]);
+    }
+    if (!isfinite(a) || !isfinite(b)) return kpm_fail(ctx, KPM_ERR_ARG, "matrix values are not all finite");
+    *lo = a;
+    *hi = b;
+    return KPM_OK;
+}
+
 // ---------------------------------------------------------------- moments
 static int default_block(int nvec, int precision) {
     const int maxb = precision == KPM_FP64 ? 128 : 256;
@@ -368,9 +399,9 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
     KPM_HIP(ctx, hipSetDevice(ctx->device));
     CsrDev A;
-    kpm_status st = prepare_csr(ctx, Ain, o->precision, &A);
+    kpm_status st = kpm_prepare_csr(ctx, Ain, o->precision, &A, "");
     if (st != KPM_OK) return st;
-    if (o->validate && (st = validate_csr(ctx, A)) != KPM_OK) return st;
+    if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
 
     const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
     const double alpha = 2.0 / d, beta = -2.0 * c / d;
@@ -432,6 +463,36 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
         }
     }
     return KPM_OK;
+}
+
+extern "C" kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_t lanczos_seed,
+                                         double margin, const kpm_moment_opts* o, double* mu,
+                                         double* mu_per_vec, double* lb, double* ub, int* attempts) {
+    if (!ctx) return KPM_ERR_ARG;
+    if (!lb || !ub) return kpm_fail(ctx, KPM_ERR_ARG, "lb/ub output is NULL");
+    double l, u;
+    kpm_status st = kpm_bounds(ctx, A, steps, lanczos_seed, margin, &l, &u);
+    if (st != KPM_OK) return st;
+    for (int attempt = 1; attempt <= 3; ++attempt) {
+        if (attempt == 2) {
+            if ((st = kpm_bounds(ctx, A, steps, lanczos_seed, std::min(4.0 * margin, 0.4), &l, &u)) != KPM_OK)
+                return st;
+        } else if (attempt == 3) {
+            double glo, ghi;
+            if ((st = kpm_gershgorin(ctx, A, &glo, &ghi)) != KPM_OK) return st;
+            const double c = 0.5 * (glo + ghi);
+            double d = 0.5 * (ghi - glo) / (1.0 - margin);
+            d = std::max(d, std::max(margin, 1e-3) * std::max(fabs(c), 1.0));
+            l = c - d;
+            u = c + d;
+        }
+        *lb = l;
+        *ub = u;
+        if (attempts) *attempts = attempt;
+        st = kpm_moments(ctx, A, l, u, o, mu, mu_per_vec);
+        if (st != KPM_ERR_SPECTRUM) return st;
+    }
+    return st;
 }
 
 // ---------------------------------------------------------------- damping / density

@@ -72,37 +72,6 @@ hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, d
 hipError_t launch_dos_bins(hipStream_t s, const double* mu, const double* g, int M, double c,
                            double d, const double* edges, int nbins, double* mass);
 
-// ---------------------------------------------------------------- batched
-struct BatchTile {       // one row panel of one matrix
-    int32_t mat;         // matrix index
-    int32_t panel;       // panel index within the matrix
-};
-struct BatchMat {        // per-matrix data for the persistent kernel
-    const int32_t* rp;
-    const int32_t* ci;
-    const float* val;
-    float* X0;           // v_{even} buffer [n x ld]
-    float* X1;           // v_{odd}  buffer [n x ld]
-    double alpha, beta;  // 2B = alpha A + beta I
-    int32_t n;
-    int32_t npanels;
-    int32_t tile0;       // first tile of this matrix within one step's tile list
-    int32_t part0;       // first partial slot of this matrix within one step
-};
-hipError_t launch_batched_persistent(hipStream_t s, const BatchMat* mats, int nmat,
-                                     const BatchTile* tiles, int ntiles_per_step, int K,
-                                     const BlockGeom& g, int nparts_per_step, double* partial,
-                                     uint32_t* counters, uint32_t* queue, int* status,
-                                     int grid, uint32_t spin_limit);
-hipError_t launch_batched_fill(hipStream_t s, const BatchMat* mats, int nmat, int ld, int ncols,
-                               uint64_t seed, int64_t max_n);
-hipError_t launch_batched_assemble(hipStream_t s, const double* dots, int nmat, int K, int ld,
-                                   int ncols, int M, const int32_t* n_of, double* zeta_norm,
-                                   int nparts_per_step, const int32_t* part0,
-                                   const int32_t* npanels, double* dots_out);
-hipError_t launch_clear_u32(hipStream_t s, uint32_t* p, int64_t count);
-int batched_max_resident_blocks(int precision);
-
 // ---------------------------------------------------------------- MLP
 hipError_t mlp_forward_dev(hipStream_t s, int N, const float* x, const float* params,
                            float* z1, float* h1, float* z2, float* h2, float* g);
@@ -132,6 +101,8 @@ struct kpm_prof_entry {
     double total_ms = 0.0;
 };
 
+struct kpm_batch_state;  // batched-moments plan and captured graph (kpm_batched.hip)
+
 struct kpm_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -141,10 +112,17 @@ struct kpm_ctx {
     // damping network
     bool mlp_ready = false;
     kpm_dev_buf mlp_params;
+    kpm_batch_state* batch = nullptr;
     // profiling
     bool prof = false;
     std::map<std::string, kpm_prof_entry> prof_map;
 };
+
+// Device view of a kpm_csr (host arrays copied into role-named workspace,
+// FP64 values rounded to FP32 for the FP32 path) and its validation.
+kpm_status kpm_prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, kpm::CsrDev* out, const char* tag);
+kpm_status kpm_validate_csr(kpm_ctx* ctx, const kpm::CsrDev& D);
+void kpm_batch_free(kpm_ctx* ctx);
 
 // Learned damping (damping network on the device); host mu/g arrays.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g);
@@ -157,6 +135,8 @@ kpm_status kpm_hip_fail(kpm_ctx* ctx, hipError_t e, const char* what);
 // one kernel with an event pair when profiling is on.
 void kpm_prof_begin(kpm_ctx* ctx, const char* kernel);
 void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches);
+void kpm_prof_begin_on(kpm_ctx* ctx, const char* kernel, hipStream_t s);
+void kpm_prof_end_on(kpm_ctx* ctx, const char* kernel, hipStream_t s, int launches);
 // Fold recorded events into the totals (call after a stream sync).
 void kpm_prof_collect(kpm_ctx* ctx);
 

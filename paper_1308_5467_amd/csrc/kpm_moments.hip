@@ -29,57 +29,9 @@
 #include <algorithm>
 
 #include "kpm_internal.h"
+#include "kpm_step.h"
 
 namespace kpm {
-
-// ---------------------------------------------------------------- helpers
-__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
-// Entry i of probe vector l of `seed`: sign of output ((l<<32)|i)+1 of SplitMix64.
-__device__ __forceinline__ float rademacher_sign(uint64_t seed, uint64_t l, uint64_t i) {
-    const uint64_t k = ((l << 32) | i) + 1ull;
-    return (sm64_mix(seed + k * 0x9e3779b97f4a7c15ull) >> 63) ? -1.0f : 1.0f;
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X.  Map
-// workgroup b to a row panel so that each XCD owns one contiguous run of
-// panels: neighbouring rows (and most gathered rows of a banded matrix) then
-// share that XCD's L2.  Bijective for every count.
-__device__ __forceinline__ int xcd_panel(int b, int nb) {
-    const int X = 8;
-    const int q = nb / X, r = nb - q * X;
-    const int x = b % X, li = b / X;
-    return x * q + min(x, r) + li;
-}
-
-template <typename T>
-struct Pack;
-template <>
-struct Pack<float> {
-    static constexpr int N = 4;
-    __device__ static __forceinline__ void load(const float* p, float (&v)[4]) {
-        const float4 t = *reinterpret_cast<const float4*>(p);
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    }
-    __device__ static __forceinline__ void store(float* p, const float (&v)[4]) {
-        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-    }
-};
-template <>
-struct Pack<double> {
-    static constexpr int N = 2;
-    __device__ static __forceinline__ void load(const double* p, double (&v)[2]) {
-        const double2 t = *reinterpret_cast<const double2*>(p);
-        v[0] = t.x; v[1] = t.y;
-    }
-    __device__ static __forceinline__ void store(double* p, const double (&v)[2]) {
-        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
-    }
-};
 
 BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint) {
     BlockGeom g;
@@ -147,87 +99,8 @@ struct StepParams {
     void* U;          // in: v_{k-1} (unless FIRST), out: v_{k+1}
     double* partial;  // [nblocks][2][ld]: <U_new, V>, <U_new, U_new> per panel
     double alpha, beta;
-    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
+    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage, nt;
 };
-
-// Byte offset of element (row, column group) in a vector block.  With
-// OFF32 the block is known to be smaller than 4 GiB and the offset is an
-// unsigned 32-bit value added to a uniform base (one address register per
-// load instead of two).
-template <bool OFF32>
-__device__ __forceinline__ uint64_t voff(uint32_t row, uint32_t ldb, uint32_t coffb) {
-    if (OFF32) return (uint32_t)(row * ldb + coffb);
-    return (uint64_t)row * ldb + coffb;
-}
-
-// One matrix row of the fused step for the lanes of one row group: gather
-// the CSR row in predicated batches of G entries (one memory round trip
-// for rows of up to G entries), combine, store, and accumulate the two
-// dot products.
-//
-// EARLY (indices in LDS): the own-row and U loads go out first and overlap
-// the gathers.  Without staging the index loads share the in-order vector
-// memory counter with them, so the own-row and U loads are issued after the
-// gathers instead.
-template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G>
-__device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t* __restrict__ cidx,
-                                         const TA* __restrict__ cval, const char* __restrict__ Vb,
-                                         char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
-                                         double alpha, double beta, double (&sx)[Pack<TV>::N],
-                                         double (&ss)[Pack<TV>::N]) {
-    constexpr int N = Pack<TV>::N;
-    const uint64_t orow = voff<OFF32>(row, ldb, coffb);
-    TV own[N], u[N];
-    if (EARLY) {
-        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
-        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
-    }
-    TV acc[N];
-#pragma unroll
-    for (int e = 0; e < N; ++e) acc[e] = (TV)0;
-    for (int k = kb; k < ke; k += G) {
-        TV x[G][N];
-        TV a[G];
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-            if (k + i < ke) {
-                const int j = cidx[k + i];
-                a[i] = (TV)cval[k + i];
-                Pack<TV>::load(reinterpret_cast<const TV*>(Vb + voff<OFF32>(j, ldb, coffb)), x[i]);
-            } else {
-                a[i] = (TV)0;
-#pragma unroll
-                for (int e = 0; e < N; ++e) x[i][e] = (TV)0;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < G; ++i)
-#pragma unroll
-            for (int e = 0; e < N; ++e) acc[e] = fma(a[i], x[i][e], acc[e]);
-    }
-    if (!EARLY) {
-        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
-        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
-    }
-    TV out[N];
-    if (FIRST) {
-        // v1 = B v0 = (alpha/2) A v0 + (beta/2) v0
-#pragma unroll
-        for (int e = 0; e < N; ++e)
-            out[e] = (TV)fma(0.5 * alpha, (double)acc[e], 0.5 * beta * (double)own[e]);
-    } else {
-#pragma unroll
-        for (int e = 0; e < N; ++e)
-            out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], -(double)u[e]));
-    }
-    Pack<TV>::store(reinterpret_cast<TV*>(Ub + orow), out);
-#pragma unroll
-    for (int e = 0; e < N; ++e) {
-        const double o = (double)out[e];
-        sx[e] = fma(o, (double)own[e], sx[e]);
-        ss[e] = fma(o, o, ss[e]);
-    }
-}
 
 // Fused step.  The grid is sized to the number of workgroups that fit on
 // the device at once; workgroups running on XCD x (hardware round-robin
@@ -287,39 +160,8 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     for (int panel = first; panel < p_end; panel += p_stride) {
         const int r0 = panel * p.rows_per_block;
         const int r1 = min(p.n, r0 + p.rows_per_block);
-
-        // Staging layout in LDS (bytes): [row offsets (R+1) x 4, padded to 8]
-        // [values pnnz x sizeof(TA)] [column indices pnnz x 4].
-        const int R = r1 - r0;
-        const int kbase = rp[r0];
-        const int pnnz = rp[r1] - kbase;
-        const int off_val = ((R + 1) * 4 + 7) & ~7;
-        const int off_ci = off_val + pnnz * (int)sizeof(TA);
-        const bool staged = p.stage && off_ci + pnnz * 4 <= (int)sizeof(smem);
-        if (staged) {
-            char* base = reinterpret_cast<char*>(smem);
-            int32_t* s_rp = reinterpret_cast<int32_t*>(base);
-            TA* s_val = reinterpret_cast<TA*>(base + off_val);
-            int32_t* s_ci = reinterpret_cast<int32_t*>(base + off_ci);
-            for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = rp[r0 + t] - kbase;
-            for (int t = threadIdx.x; t < pnnz; t += kThreads) {
-                s_val[t] = val[kbase + t];
-                s_ci[t] = ci[kbase + t];
-            }
-            __syncthreads();
-            if (lane_on) {
-                for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows) {
-                    const int lr = row - r0;
-                    step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], s_ci, s_val, Vb, Ub, ldb,
-                                                            coffb, p.alpha, p.beta, sx, ss);
-                }
-            }
-            __syncthreads();  // before the LDS is restaged or reused below
-        } else if (lane_on) {
-            for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows)
-                step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], ci, val, Vb, Ub, ldb, coffb,
-                                                         p.alpha, p.beta, sx, ss);
-        }
+        process_panel<TA, TV, FIRST, OFF32, G>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha, p.beta, p.stage,
+                                               p.nt, smem, lane_on, wave, rw, p.rpw, sx, ss);
     }
 
     // One partial per workgroup: the lanes' sums over every row they
@@ -344,11 +186,12 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     }
 }
 
-// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8").
+// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8,nt=0|1").
 struct StepTune {
     int stage = 1;
     int persist = 1;
     int gather = 8;
+    int nt = 0;
 };
 static StepTune read_tune() {
     StepTune t;
@@ -358,6 +201,7 @@ static StepTune read_tune() {
         if ((s = strstr(e, "stage="))) t.stage = atoi(s + 6);
         if ((s = strstr(e, "persist="))) t.persist = atoi(s + 8);
         if ((s = strstr(e, "gather="))) t.gather = atoi(s + 7) == 4 ? 4 : 8;
+        if ((s = strstr(e, "nt="))) t.nt = atoi(s + 3);
     }
     return t;
 }
@@ -435,6 +279,7 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.rows_per_block = g.rows_per_block;
     p.npanels = g.nblocks;
     p.stage = tune().stage;
+    p.nt = tune().nt;
     const bool off32 = step_off32(A, g, precision);
     const bool g4 = tune().gather == 4;
 #define KPM_STEP_G(TA, TV, GG)                                                                   \

@@ -5,10 +5,6 @@
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int, const double*, double*) {
     return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "learned damping not built");
 }
-extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int, const kpm_csr*, const double*, const double*,
-                                          const kpm_moment_opts*, double*) {
-    return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "batched moments not built");
-}
 extern "C" int64_t kpm_mlp_param_count(void) { return 128 * 256 + 256 + 256 * 256 + 256 + 256 * 128 + 128; }
 extern "C" kpm_status kpm_mlp_set_params(kpm_ctx* c, const float*) { return kpm_fail(c, KPM_ERR_UNSUPPORTED, "mlp"); }
 extern "C" kpm_status kpm_mlp_get_params(kpm_ctx* c, float*) { return kpm_fail(c, KPM_ERR_UNSUPPORTED, "mlp"); }

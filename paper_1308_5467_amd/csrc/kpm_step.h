@@ -1,0 +1,213 @@
+// Device code shared by the single-matrix and the batched step kernels:
+// probe signs, the XCD-aware workgroup map, vector packs, and the fused
+// per-row / per-panel Chebyshev step (Lin, Saad & Yang, eq. (3term) with
+// the product identity of Appendix A).  Included by .hip sources only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Entry i of probe vector l of `seed`: sign of output ((l<<32)|i)+1 of SplitMix64.
+__device__ __forceinline__ float rademacher_sign(uint64_t seed, uint64_t l, uint64_t i) {
+    const uint64_t k = ((l << 32) | i) + 1ull;
+    return (sm64_mix(seed + k * 0x9e3779b97f4a7c15ull) >> 63) ? -1.0f : 1.0f;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X.  Map
+// workgroup b to a row panel so that each XCD owns one contiguous run of
+// panels: neighbouring rows (and most gathered rows of a banded matrix) then
+// share that XCD's L2.  Bijective for every count.
+__device__ __forceinline__ int xcd_panel(int b, int nb) {
+    const int X = 8;
+    const int q = nb / X, r = nb - q * X;
+    const int x = b % X, li = b / X;
+    return x * q + min(x, r) + li;
+}
+
+// Loads of data used once per step (the U block, the CSR slice) may be
+// marked non-temporal so that L2 keeps the gathered V rows instead.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p, bool nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <typename T>
+struct Pack;
+template <>
+struct Pack<float> {
+    static constexpr int N = 4;
+    __device__ static __forceinline__ void load(const float* p, float (&v)[4]) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+    __device__ static __forceinline__ void load_nt(const float* p, float (&v)[4]) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    }
+    __device__ static __forceinline__ void store(float* p, const float (&v)[4]) {
+        *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+template <>
+struct Pack<double> {
+    static constexpr int N = 2;
+    __device__ static __forceinline__ void load(const double* p, double (&v)[2]) {
+        const double2 t = *reinterpret_cast<const double2*>(p);
+        v[0] = t.x; v[1] = t.y;
+    }
+    __device__ static __forceinline__ void load_nt(const double* p, double (&v)[2]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+        v[0] = t.x; v[1] = t.y;
+    }
+    __device__ static __forceinline__ void store(double* p, const double (&v)[2]) {
+        *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    }
+};
+
+// Byte offset of element (row, column group) in a vector block.  With
+// OFF32 the block is known to be smaller than 4 GiB and the offset is an
+// unsigned 32-bit value added to a uniform base (one address register per
+// load instead of two).
+template <bool OFF32>
+__device__ __forceinline__ uint64_t voff(uint32_t row, uint32_t ldb, uint32_t coffb) {
+    if (OFF32) return (uint32_t)(row * ldb + coffb);
+    return (uint64_t)row * ldb + coffb;
+}
+
+// One matrix row of the fused step for the lanes of one row group: gather
+// the CSR row in predicated batches of G entries (one memory round trip
+// for rows of up to G entries), combine, store, and accumulate the two
+// dot products.
+//
+// EARLY (indices in LDS): the own-row and U loads go out first and overlap
+// the gathers.  Without staging the index loads share the in-order vector
+// memory counter with them, so the own-row and U loads are issued after the
+// gathers instead.
+template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G>
+__device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t* __restrict__ cidx,
+                                         const TA* __restrict__ cval, const char* __restrict__ Vb,
+                                         char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
+                                         double alpha, double beta, double (&sx)[Pack<TV>::N],
+                                         double (&ss)[Pack<TV>::N], bool nt) {
+    constexpr int N = Pack<TV>::N;
+    const uint64_t orow = voff<OFF32>(row, ldb, coffb);
+    TV own[N], u[N];
+    if (EARLY) {
+        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
+        if (!FIRST) {
+            if (nt) Pack<TV>::load_nt(reinterpret_cast<const TV*>(Ub + orow), u);
+            else Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        }
+    }
+    TV acc[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) acc[e] = (TV)0;
+    for (int k = kb; k < ke; k += G) {
+        TV x[G][N];
+        TV a[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (k + i < ke) {
+                const int j = cidx[k + i];
+                a[i] = (TV)cval[k + i];
+                Pack<TV>::load(reinterpret_cast<const TV*>(Vb + voff<OFF32>(j, ldb, coffb)), x[i]);
+            } else {
+                a[i] = (TV)0;
+#pragma unroll
+                for (int e = 0; e < N; ++e) x[i][e] = (TV)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+#pragma unroll
+            for (int e = 0; e < N; ++e) acc[e] = fma(a[i], x[i][e], acc[e]);
+    }
+    if (!EARLY) {
+        Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
+        if (!FIRST) {
+            if (nt) Pack<TV>::load_nt(reinterpret_cast<const TV*>(Ub + orow), u);
+            else Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        }
+    }
+    TV out[N];
+    if (FIRST) {
+        // v1 = B v0 = (alpha/2) A v0 + (beta/2) v0
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = (TV)fma(0.5 * alpha, (double)acc[e], 0.5 * beta * (double)own[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], -(double)u[e]));
+    }
+    Pack<TV>::store(reinterpret_cast<TV*>(Ub + orow), out);
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        const double o = (double)out[e];
+        sx[e] = fma(o, (double)own[e], sx[e]);
+        ss[e] = fma(o, o, ss[e]);
+    }
+}
+
+// One row panel [r0, r1) of the fused step for one workgroup.  With `stage`
+// set and when it fits, the panel's slice of the CSR arrays (row offsets,
+// values, column indices) is first copied to LDS with coalesced loads, so
+// each row costs one round of independent gathers.  The dots are added to
+// the caller's per-lane accumulators sx/ss.
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G, int LDS_DOUBLES>
+__device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __restrict__ rp,
+                                              const int32_t* __restrict__ ci, const TA* __restrict__ val,
+                                              const char* __restrict__ Vb, char* __restrict__ Ub, uint32_t ldb,
+                                              uint32_t coffb, double alpha, double beta, int stage, int nt,
+                                              double (&smem)[LDS_DOUBLES], bool lane_on, int wave, int rw,
+                                              int rpw, double (&sx)[Pack<TV>::N],
+                                              double (&ss)[Pack<TV>::N]) {
+    const int pass_rows = kWaves * rpw;
+    // Staging layout in LDS (bytes): [row offsets (R+1) x 4, padded to 8]
+    // [values pnnz x sizeof(TA)] [column indices pnnz x 4].
+    const int R = r1 - r0;
+    const int kbase = rp[r0];
+    const int pnnz = rp[r1] - kbase;
+    const int off_val = ((R + 1) * 4 + 7) & ~7;
+    const int off_ci = off_val + pnnz * (int)sizeof(TA);
+    const bool staged = stage && off_ci + pnnz * 4 <= (int)sizeof(smem);
+    if (staged) {
+        char* base = reinterpret_cast<char*>(smem);
+        int32_t* s_rp = reinterpret_cast<int32_t*>(base);
+        TA* s_val = reinterpret_cast<TA*>(base + off_val);
+        int32_t* s_ci = reinterpret_cast<int32_t*>(base + off_ci);
+        for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = ld_stream(rp + r0 + t, nt) - kbase;
+        for (int t = threadIdx.x; t < pnnz; t += kThreads) {
+            s_val[t] = ld_stream(val + kbase + t, nt);
+            s_ci[t] = ld_stream(ci + kbase + t, nt);
+        }
+        __syncthreads();
+        if (lane_on) {
+            for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows) {
+                const int lr = row - r0;
+                step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], s_ci, s_val, Vb, Ub, ldb,
+                                                        coffb, alpha, beta, sx, ss, nt);
+            }
+        }
+        __syncthreads();  // before the LDS is restaged or reused
+    } else if (lane_on) {
+        for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows)
+            step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], ci, val, Vb, Ub, ldb, coffb,
+                                                     alpha, beta, sx, ss, nt);
+    }
+}
+
+}  // namespace kpm

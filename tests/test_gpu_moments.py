@@ -258,3 +258,32 @@ def test_c2_full_size_sampled(ctx):
         z = oracle.moments_per_vector(Ao, c, d, 256, 1, 2002, vec0=l)[0] / A.n
         assert np.max(np.abs(pv[l] - z)) < TOL32, l
     assert mu[0] == 1.0 and np.all(np.abs(pv) <= 1 + 1e-5)
+
+
+def test_c5_full_size_sampled(ctx):
+    """c5 at full size: 3D Anderson 128^3 plus random long-range hoppings
+    (n = 2,097,152, nnz ~ 23M), 256 probes in blocks of 64, FP32.
+
+    The degree-1000 run is checked by invariants, and its first 201 moments
+    must equal those of a degree-200 run bitwise (the first 100 steps are
+    the same deterministic launches).  The degree-200 run is checked against
+    the oracle on probes 254 and 255 (the last block)."""
+    _say("c5 full size: generating matrix")
+    A = synth.config_matrix("c5")
+    assert A.n == 128**3 and 20_000_000 < A.nnz < 26_000_000
+    D = dev(A, "f32")
+    _say("c5 bounds")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3005, 0.01)
+    _say("c5 moments M=1000")
+    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 1000, 256, 2005, precision="f32", block=64,
+                             validate=True, per_vector=True)
+    assert mu[0] == 1.0 and np.all(np.abs(pv) <= 1 + 1e-5)
+    _say("c5 moments M=200")
+    mu2, pv2 = kpm.kpm_moments(ctx, D, lb, ub, 200, 256, 2005, precision="f32", block=64,
+                               validate=False, per_vector=True)
+    assert np.array_equal(pv[:, :201], pv2)
+    Ao = A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    _say("c5 oracle probes 254, 255 at M=200")
+    z = oracle.moments_per_vector(Ao, c, d, 200, 2, 2005, vec0=254, nthreads=2) / A.n
+    assert np.max(np.abs(pv2[254:256] - z)) < TOL32
