@@ -1,0 +1,158 @@
+"""GPU parity of the learned damping network (forward, loss, gradients)
+against the FP64 oracle, and a held-out test of what training gains over
+Jackson damping.
+
+Parity of the network with the paper is unpinned (the paper has no learned
+part); the oracle network is pinned by finite differences and library
+layers (tests/test_oracle_mlp.py).  Tolerances: forward 2e-5 absolute on g;
+loss 1e-5 relative; each gradient tensor within 2e-4 of its largest entry.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1308_5467_amd as kpm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = kpm.Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed, scale_out=1.0):
+    p = oracle.mlp_init(seed)
+    rng = np.random.default_rng(seed + 1)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.normal(0, 0.1, p[k].shape)
+    p["W3"] = p["W3"] * scale_out
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def _batch(N, seed):
+    rng = np.random.default_rng(seed)
+    X = np.concatenate([np.ones((N, 1)), rng.normal(0, 0.3, (N, 127)) / np.sqrt(np.arange(1, 128))], axis=1)
+    T = np.abs(rng.normal(0, 1.0, (N, 200)))
+    return X.astype(np.float32).astype(np.float64), T.astype(np.float32).astype(np.float64)
+
+
+def test_forward_parity(ctx):
+    p = _params(3)
+    X, _ = _batch(300, 4)
+    kpm.kpm_mlp_set_params(ctx, kpm.mlp_pack(p))
+    g = kpm.kpm_mlp_forward(ctx, X)
+    ref, _ = oracle.mlp_forward(p, X)
+    assert np.max(np.abs(g - ref)) < 2e-5
+    assert np.all(g[:, 0] == 1.0)
+
+
+def test_loss_and_gradient_parity(ctx):
+    p = _params(5)
+    X, T = _batch(257, 6)
+    kpm.kpm_mlp_set_params(ctx, kpm.mlp_pack(p))
+    loss, grads = kpm.kpm_mlp_loss_grad(ctx, X, T, 0.05)
+    K = oracle.blur_operator(128, 200, 0.05, 8192)
+    rl, rg, _ = oracle.mlp_loss_and_grads(p, X, T, K)
+    assert abs(loss - rl) <= 1e-5 * rl
+    got = kpm.mlp_unpack(grads)
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        scale = np.max(np.abs(rg[name]))
+        assert np.max(np.abs(got[name] - rg[name])) <= 2e-4 * scale, name
+
+
+def test_init_starts_near_jackson_and_is_deterministic(ctx):
+    kpm.kpm_mlp_init(ctx, 11)
+    p1 = kpm.kpm_mlp_get_params(ctx)
+    kpm.kpm_mlp_init(ctx, 11)
+    assert np.array_equal(p1, kpm.kpm_mlp_get_params(ctx))
+    X, _ = _batch(64, 7)
+    g = kpm.kpm_mlp_forward(ctx, X)
+    assert np.mean(np.abs(g[:, 1:] - oracle.jackson(127)[1:])) < 0.05
+
+
+def test_save_load_and_learned_damping_entry(ctx, tmp_path):
+    kpm.kpm_mlp_init(ctx, 12)
+    path = str(tmp_path / "net.bin")
+    kpm.kpm_mlp_save(ctx, path)
+    p = kpm.kpm_mlp_get_params(ctx)
+    kpm.kpm_mlp_init(ctx, 99)
+    kpm.kpm_mlp_load(ctx, path)
+    assert np.array_equal(p, kpm.kpm_mlp_get_params(ctx))
+    X, _ = _batch(1, 8)
+    g_fwd = kpm.kpm_mlp_forward(ctx, X)[0]
+    g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 127, X[0])
+    assert g[0] == 1.0 and np.allclose(g[1:], g_fwd[1:], rtol=0, atol=0)
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 100, np.ones(101))
+    with open(path, "r+b") as f:
+        f.write(b"XXXX")
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_mlp_load(ctx, path)
+
+
+# ---------------------------------------------------------------- training gain
+SIGMA = 0.02
+
+
+def _dataset(count, seed0, nvec, ctx):
+    """Random sparse symmetric (n = 512) and 2D Anderson (16 x 32) matrices:
+    moments mu_0..127 from the library's batched path (the network's input),
+    labels = exact Gaussian-blurred DOS from dense eigh (oracle)."""
+    mats = []
+    for i in range(count):
+        if i % 2 == 0:
+            mats.append(synth.random_sparse_symmetric(512, 4.5, seed0 + i))
+        else:
+            W = 1.0 + 15.0 * ((seed0 + i) * 0.6180339887 % 1.0)
+            mats.append(synth.add_diagonal_disorder(synth.laplacian2d_periodic(16, 32), W, seed0 + i))
+    D = [kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32") for A in mats]
+    t = oracle.midpoints(200)
+    lb, ub, targets = [], [], []
+    for A in mats:
+        lam = np.linalg.eigvalsh(A.rounded_f32().dense())
+        c, d = 0.5 * (lam[0] + lam[-1]), 0.5 * (lam[-1] - lam[0]) / 0.98
+        lb.append(c - d)
+        ub.append(c + d)
+        targets.append(oracle.blurred_exact((lam - c) / d, t, SIGMA))
+    mu = kpm.kpm_moments_batched(ctx, D, np.array(lb), np.array(ub), 127, nvec, 7000 + seed0)
+    return mu, np.array(targets)
+
+
+def _l1(mu, g, targets):
+    K = oracle.blur_operator(128, 200, SIGMA, 8192)
+    phi = (g * mu) @ K.T
+    return np.sum(np.abs(phi - targets), axis=1) * (2.0 / 200)
+
+
+def test_training_beats_jackson_on_held_out(ctx):
+    _say("building training set")
+    mu_tr, t_tr = _dataset(320, 100, 64, ctx)
+    _say("building held-out set")
+    mu_te, t_te = _dataset(80, 5000, 64, ctx)
+    kpm.kpm_mlp_init(ctx, 2024)
+    _say("training")
+    losses = kpm.kpm_mlp_train(ctx, mu_tr, t_tr, SIGMA, 300, 64, 1e-3, 1)
+    assert losses[-1] < 0.8 * losses[0]
+    g_learned = kpm.kpm_mlp_forward(ctx, mu_te).astype(np.float64)
+    e_learned = _l1(mu_te, g_learned, t_te)
+    e_jackson = _l1(mu_te, np.tile(oracle.jackson(127), (len(mu_te), 1)), t_te)
+    e_none = _l1(mu_te, np.ones_like(mu_te), t_te)
+    _say(f"held-out mean L1: learned {e_learned.mean():.4f}  jackson {e_jackson.mean():.4f}  none {e_none.mean():.4f}"
+         f"  (train loss {losses[0]:.4f} -> {losses[-1]:.4f})")
+    assert e_learned.mean() < e_jackson.mean()
+    assert np.mean(e_learned < e_jackson) > 0.7
