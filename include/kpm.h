@@ -107,8 +107,9 @@ const char* kpm_last_error(const kpm_ctx* ctx);
 /*
  * kpm_bounds -- lower and upper bounds of the spectrum of A (section 3.1.1,
  * the paragraph after eq. (cd)).  Runs `steps` Lanczos steps in FP64 on the
- * device (start vector: probe vector 2^31 - 1 of `seed`, normalised; two
- * passes of full re-orthogonalisation per step), takes the extreme Ritz
+ * device (start vector: probe vector 2^31 - 1 of `seed`, normalised; each
+ * new vector orthogonalised against all previous ones by one classical
+ * Gram-Schmidt pass), takes the extreme Ritz
  * values theta_1, theta_k of the tridiagonal matrix and widens each by its
  * residual norm beta_k |z_{k,j}|.  On breakdown the Gershgorin hull is merged
  * in.  The interval [lb0, ub0] is finally widened so that it maps into

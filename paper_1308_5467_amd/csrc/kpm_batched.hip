@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
         const int r0 = panel * rows_per_panel;
         const int r1 = min(mv.n, r0 + rows_per_panel);
         process_panel<TA, TV, FIRST, true, G>(r0, r1, mv.rp, mv.ci, val, Vb, Ub, ldb, coffb, mv.alpha, mv.beta,
-                                              stage, 0, smem, lane_on, wave, rw, rpw, sx, ss);
+                                              stage, smem, lane_on, wave, rw, rpw, sx, ss);
     }
     double* red = smem;
     if (lane_on) {

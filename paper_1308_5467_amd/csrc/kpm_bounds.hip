@@ -1,17 +1,19 @@
 // Spectral bounds (Lin, Saad & Yang, section 3.1.1, the paragraph after
 // eq. (cd)): a k-step Lanczos run in FP64 on the device with full
-// re-orthogonalisation (classical Gram-Schmidt applied twice).  It leaves
+// re-orthogonalisation (one classical Gram-Schmidt pass against every
+// previous Lanczos vector).  It leaves
 // alpha[0..m-1] and beta[0..m-1] (beta[j] = norm of the residual after step
 // j) in device memory; the host part of kpm_bounds solves the m x m
 // tridiagonal eigenproblem and widens the extreme Ritz values by their
 // residuals.
 //
-// Step j is three data-parallel launches, each followed by a small
-// reduction launch, all enqueued without any host sync:
+// Step j is two data-parallel launches, each followed by a small reduction
+// launch, all enqueued without any host sync:
 //   A  q_j = r_{j-1} / beta_{j-1} (q_0 = start probe / sqrt(n)), stored as
 //      row j of Q;  w = A q_j;  partials of h = Q^T w    (alpha_j = h_j)
-//   B  w -= Q h;  partials of h' = Q^T w                  (second pass)
-//   C  w -= Q h';  partial of ||w||^2                      (-> beta_j)
+//   B  w -= Q h;  partial of ||w||^2                      (-> beta_j)
+// (h_{j-1} plays the part of beta_{j-1} in the three-term recurrence and
+// the other h_t remove the components along older vectors.)
 // Every workgroup owns a contiguous chunk of rows (R rows per thread, held
 // in registers) and writes one partial per coefficient; the reduction
 // launch adds them in a fixed order (one workgroup per coefficient), so
@@ -38,7 +40,7 @@ __device__ __forceinline__ double lz_start_entry(uint64_t seed, int64_t i, doubl
     return ((lz_mix(seed + k * 0x9e3779b97f4a7c15ull) >> 63) ? -1.0 : 1.0) * inv_sqrt_n;
 }
 
-// coef layout (doubles): alpha[0..63], beta[64..127], h1[128..159], h2[160..191]
+// coef layout (doubles): alpha[0..63], beta[64..127], h[128..159]
 struct LzArgs {
     const int32_t* rp;
     const int32_t* ci;
@@ -70,7 +72,8 @@ __device__ __forceinline__ void lz_store_partials(const LzArgs& a, int kind, int
 }
 
 // out[t] = sum over workgroups of partial slot t of `kind` (square root when
-// MODE == 2; MODE == 0 also copies slot j to alpha_j).  Workgroup t: each
+// MODE == 2; MODE == 0 also copies slot j to alpha_j).  Kinds: 0 projection
+// partials of launch A, 2 norm partials of launch B.  Workgroup t: each
 // thread adds workgroups tid, tid+256, ... in order, then a fixed tree.
 template <int MODE>
 __global__ __launch_bounds__(LZ_THREADS) void lz_reduce(LzArgs a, int kind, int j, double* out) {
@@ -155,52 +158,34 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
     lz_store_partials(a, 0, j + 1, sh);
 }
 
-// B (PASS 0): w -= Q h1; h2 = Q^T w.   C (PASS 1): w -= Q h2; beta_j = ||w||.
-template <int PASS, int R>
+// B: w -= Q h (h from A's reduction); partial of ||w||^2 (-> beta_j).
+template <int R>
 __global__ __launch_bounds__(LZ_THREADS) void lz_orth(LzArgs a, int j) {
     __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
     __shared__ double hs[LZ_SLOTS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int J = j + 1;
     double* __restrict__ ww = a.W[j & 1];
-    if ((int)threadIdx.x < J) hs[threadIdx.x] = a.coef[(PASS == 0 ? 128 : 160) + threadIdx.x];
+    if ((int)threadIdx.x < J) hs[threadIdx.x] = a.coef[128 + threadIdx.x];
     __syncthreads();
     const int64_t n = a.n;
     const double* __restrict__ Q = a.Q;
     const int64_t i0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x;
-    double x[R];
+    double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = i0 + (int64_t)r * LZ_THREADS;
-        x[r] = 0.0;
         if (i < n) {
             double s = 0.0;
             for (int t = 0; t < J; ++t) s = fma(hs[t], Q[(int64_t)t * n + i], s);
-            x[r] = ww[i] - s;
-            ww[i] = x[r];
+            const double x = ww[i] - s;
+            ww[i] = x;
+            acc = fma(x, x, acc);
         }
     }
-    if (PASS == 1) {
-        double acc = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc = fma(x[r], x[r], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) sh[wave][0] = acc;
-        lz_store_partials(a, 2, 1, sh);
-        return;
-    }
-    for (int t = 0; t < J; ++t) {
-        const double* __restrict__ qt = Q + (int64_t)t * n;
-        double acc = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = i0 + (int64_t)r * LZ_THREADS;
-            if (i < n) acc = fma(qt[i], x[r], acc);
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) sh[wave][t] = acc;
-    }
-    lz_store_partials(a, 1, J, sh);
+    acc = wave_sum(acc);
+    if (lane == 0) sh[wave][0] = acc;
+    lz_store_partials(a, 2, 1, sh);
 }
 
 template <int R>
@@ -209,9 +194,7 @@ static void lz_launch_steps(hipStream_t s, const CsrDev& A, int m, const LzArgs&
         if (A.val_f64) lz_spmv_project<double, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
         else lz_spmv_project<float, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
         lz_reduce<0><<<j + 1, LZ_THREADS, 0, s>>>(a, 0, j, a.coef + 128);
-        lz_orth<0, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
-        lz_reduce<1><<<j + 1, LZ_THREADS, 0, s>>>(a, 1, j, a.coef + 160);
-        lz_orth<1, R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
+        lz_orth<R><<<a.nblk, LZ_THREADS, 0, s>>>(a, j);
         lz_reduce<2><<<1, LZ_THREADS, 0, s>>>(a, 2, j, a.coef + 64 + j);
     }
 }

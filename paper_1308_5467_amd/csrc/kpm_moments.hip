@@ -99,7 +99,7 @@ struct StepParams {
     void* U;          // in: v_{k-1} (unless FIRST), out: v_{k+1}
     double* partial;  // [nblocks][2][ld]: <U_new, V>, <U_new, U_new> per panel
     double alpha, beta;
-    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage, nt;
+    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
 };
 
 // Fused step.  The grid is sized to the number of workgroups that fit on
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
         const int r0 = panel * p.rows_per_block;
         const int r1 = min(p.n, r0 + p.rows_per_block);
         process_panel<TA, TV, FIRST, OFF32, G>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha, p.beta, p.stage,
-                                               p.nt, smem, lane_on, wave, rw, p.rpw, sx, ss);
+                                               smem, lane_on, wave, rw, p.rpw, sx, ss);
     }
 
     // One partial per workgroup: the lanes' sums over every row they
@@ -186,12 +186,11 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     }
 }
 
-// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8,nt=0|1").
+// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8").
 struct StepTune {
     int stage = 1;
     int persist = 1;
     int gather = 8;
-    int nt = 0;
 };
 static StepTune read_tune() {
     StepTune t;
@@ -201,7 +200,6 @@ static StepTune read_tune() {
         if ((s = strstr(e, "stage="))) t.stage = atoi(s + 6);
         if ((s = strstr(e, "persist="))) t.persist = atoi(s + 8);
         if ((s = strstr(e, "gather="))) t.gather = atoi(s + 7) == 4 ? 4 : 8;
-        if ((s = strstr(e, "nt="))) t.nt = atoi(s + 3);
     }
     return t;
 }
@@ -249,15 +247,19 @@ static bool step_off32(const CsrDev& A, const BlockGeom& g, int precision) {
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
     const bool off32 = step_off32(A, g, precision);
     const bool g4 = tune().gather == 4;
-#define KPM_GRID(TA, TV)                                                                     \
-    return off32 ? (g4 ? grid_of<TA, TV, true, 4>(g.nblocks) : grid_of<TA, TV, true, 8>(g.nblocks)) \
-                 : (g4 ? grid_of<TA, TV, false, 4>(g.nblocks) : grid_of<TA, TV, false, 8>(g.nblocks))
+#define KPM_GRID_V(TA, TV, O) return g4 ? grid_of<TA, TV, O, 4>(g.nblocks) : grid_of<TA, TV, O, 8>(g.nblocks)
+#define KPM_GRID(TA, TV)          \
+    if (off32) {                  \
+        KPM_GRID_V(TA, TV, true); \
+    }                             \
+    KPM_GRID_V(TA, TV, false)
     if (precision == KPM_FP64) {
         if (A.val_f64) KPM_GRID(double, double);
         KPM_GRID(float, double);
     }
     KPM_GRID(float, float);
 #undef KPM_GRID
+#undef KPM_GRID_V
 }
 
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
@@ -279,7 +281,6 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.rows_per_block = g.rows_per_block;
     p.npanels = g.nblocks;
     p.stage = tune().stage;
-    p.nt = tune().nt;
     const bool off32 = step_off32(A, g, precision);
     const bool g4 = tune().gather == 4;
 #define KPM_STEP_G(TA, TV, GG)                                                                   \

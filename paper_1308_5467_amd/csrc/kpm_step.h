@@ -35,13 +35,6 @@ __device__ __forceinline__ int xcd_panel(int b, int nb) {
     return x * q + min(x, r) + li;
 }
 
-// Loads of data used once per step (the U block, the CSR slice) may be
-// marked non-temporal so that L2 keeps the gathered V rows instead.
-template <typename T>
-__device__ __forceinline__ T ld_stream(const T* p, bool nt) {
-    return nt ? __builtin_nontemporal_load(p) : *p;
-}
-
 template <typename T>
 struct Pack;
 template <>
@@ -51,13 +44,13 @@ struct Pack<float> {
         const float4 t = *reinterpret_cast<const float4*>(p);
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     }
-    __device__ static __forceinline__ void load_nt(const float* p, float (&v)[4]) {
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    }
     __device__ static __forceinline__ void store(float* p, const float (&v)[4]) {
         *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    __device__ static __forceinline__ void store_nt(float* p, const float (&v)[4]) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 t = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(t, reinterpret_cast<f4*>(p));
     }
 };
 template <>
@@ -67,13 +60,13 @@ struct Pack<double> {
         const double2 t = *reinterpret_cast<const double2*>(p);
         v[0] = t.x; v[1] = t.y;
     }
-    __device__ static __forceinline__ void load_nt(const double* p, double (&v)[2]) {
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
-        v[0] = t.x; v[1] = t.y;
-    }
     __device__ static __forceinline__ void store(double* p, const double (&v)[2]) {
         *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    }
+    __device__ static __forceinline__ void store_nt(double* p, const double (&v)[2]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        d2 t = {v[0], v[1]};
+        __builtin_nontemporal_store(t, reinterpret_cast<d2*>(p));
     }
 };
 
@@ -101,16 +94,13 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t*
                                          const TA* __restrict__ cval, const char* __restrict__ Vb,
                                          char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
                                          double alpha, double beta, double (&sx)[Pack<TV>::N],
-                                         double (&ss)[Pack<TV>::N], bool nt) {
+                                         double (&ss)[Pack<TV>::N]) {
     constexpr int N = Pack<TV>::N;
     const uint64_t orow = voff<OFF32>(row, ldb, coffb);
     TV own[N], u[N];
     if (EARLY) {
         Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
-        if (!FIRST) {
-            if (nt) Pack<TV>::load_nt(reinterpret_cast<const TV*>(Ub + orow), u);
-            else Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
-        }
+        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
     }
     TV acc[N];
 #pragma unroll
@@ -137,10 +127,7 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t*
     }
     if (!EARLY) {
         Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
-        if (!FIRST) {
-            if (nt) Pack<TV>::load_nt(reinterpret_cast<const TV*>(Ub + orow), u);
-            else Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
-        }
+        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
     }
     TV out[N];
     if (FIRST) {
@@ -153,7 +140,9 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t*
         for (int e = 0; e < N; ++e)
             out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], -(double)u[e]));
     }
-    Pack<TV>::store(reinterpret_cast<TV*>(Ub + orow), out);
+    // U_new is not read again in this step: a non-temporal store leaves the
+    // L2 to the gathered V rows (measured faster than a cached store).
+    Pack<TV>::store_nt(reinterpret_cast<TV*>(Ub + orow), out);
 #pragma unroll
     for (int e = 0; e < N; ++e) {
         const double o = (double)out[e];
@@ -171,7 +160,7 @@ template <typename TA, typename TV, bool FIRST, bool OFF32, int G, int LDS_DOUBL
 __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci, const TA* __restrict__ val,
                                               const char* __restrict__ Vb, char* __restrict__ Ub, uint32_t ldb,
-                                              uint32_t coffb, double alpha, double beta, int stage, int nt,
+                                              uint32_t coffb, double alpha, double beta, int stage,
                                               double (&smem)[LDS_DOUBLES], bool lane_on, int wave, int rw,
                                               int rpw, double (&sx)[Pack<TV>::N],
                                               double (&ss)[Pack<TV>::N]) {
@@ -189,24 +178,24 @@ __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __r
         int32_t* s_rp = reinterpret_cast<int32_t*>(base);
         TA* s_val = reinterpret_cast<TA*>(base + off_val);
         int32_t* s_ci = reinterpret_cast<int32_t*>(base + off_ci);
-        for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = ld_stream(rp + r0 + t, nt) - kbase;
+        for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = rp[r0 + t] - kbase;
         for (int t = threadIdx.x; t < pnnz; t += kThreads) {
-            s_val[t] = ld_stream(val + kbase + t, nt);
-            s_ci[t] = ld_stream(ci + kbase + t, nt);
+            s_val[t] = val[kbase + t];
+            s_ci[t] = ci[kbase + t];
         }
         __syncthreads();
         if (lane_on) {
             for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows) {
                 const int lr = row - r0;
                 step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], s_ci, s_val, Vb, Ub, ldb,
-                                                        coffb, alpha, beta, sx, ss, nt);
+                                                        coffb, alpha, beta, sx, ss);
             }
         }
         __syncthreads();  // before the LDS is restaged or reused
     } else if (lane_on) {
         for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows)
             step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], ci, val, Vb, Ub, ldb, coffb,
-                                                     alpha, beta, sx, ss, nt);
+                                                     alpha, beta, sx, ss);
     }
 }
 
