@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
                                                                 int ld, int lpr, int rpw, int rows_per_panel,
                                                                 int stage, double* __restrict__ partial) {
     constexpr int N = Pack<TV>::N;
-    __shared__ double smem[kWaves * 64 * 2 * N];
+    __shared__ __align__(16) double smem[kWaves * 64 * 2 * N];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rw = lane / lpr;
@@ -70,7 +70,10 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
     double sx[N], ss[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) sx[i] = ss[i] = 0.0;
-    for (int panel = E.p0; panel < E.p1; ++panel) {
+    // Odd steps walk the entry's panels backwards, starting on the rows the
+    // previous step ended with (still in this XCD's L2).
+    for (int q = E.p0; q < E.p1; ++q) {
+        const int panel = parity ? E.p0 + E.p1 - 1 - q : q;
         const int r0 = panel * rows_per_panel;
         const int r1 = min(mv.n, r0 + rows_per_panel);
         process_panel<TA, TV, FIRST, true, G>(r0, r1, mv.rp, mv.ci, val, Vb, Ub, ldb, coffb, mv.alpha, mv.beta,

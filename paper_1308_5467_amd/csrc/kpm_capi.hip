@@ -435,8 +435,10 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
             // remaining steps (events between launches would add gaps).
             if (s == 0) kpm_prof_begin(ctx, "cheb_first");
             if (s == 1) kpm_prof_begin(ctx, "cheb_step");
+            // Odd steps walk the panels backwards: they start on the rows
+            // the previous step finished with, still in the XCD's L2.
             KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, gridb, X[s & 1],
-                                          X[(s + 1) & 1], alpha, beta, ps));
+                                          X[(s + 1) & 1], alpha, beta, ps, (s & 1) != 0));
             if (s == 0) kpm_prof_end(ctx, "cheb_first", 1);
             if (s == K - 1 && K > 1) kpm_prof_end(ctx, "cheb_step", K - 1);
         }

@@ -43,7 +43,7 @@ hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int nco
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g);
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
                             const BlockGeom& g, int grid, const void* V, void* U, double alpha,
-                            double beta, double* partial);
+                            double beta, double* partial, bool reverse);
 hipError_t launch_reduce_partials(hipStream_t s, const double* partial, int nblocks, int width,
                                   int K, double* dots);
 hipError_t launch_assemble(hipStream_t s, const double* dots, int K, int ld, int ncols, int M,

@@ -97,27 +97,31 @@ struct StepParams {
     const void* val;
     const void* V;    // v_k, gathered
     void* U;          // in: v_{k-1} (unless FIRST), out: v_{k+1}
-    double* partial;  // [nblocks][2][ld]: <U_new, V>, <U_new, U_new> per panel
+    double* partial;  // [grid][2][ld]: <U_new, V>, <U_new, U_new> per workgroup
     double alpha, beta;
     int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
+    int32_t reverse;  // walk each XCD's panel range from its end
 };
 
 // Fused step.  The grid is sized to the number of workgroups that fit on
 // the device at once; workgroups running on XCD x (hardware round-robin
 // b % 8) walk the x-th contiguous eighth of the row panels, so neighbouring
 // rows -- and the gathered rows of banded matrices -- share that XCD's L2.
-// With `stage` set, a panel's slice of the CSR arrays (row offsets, column
-// indices, values) is first copied to LDS with coalesced loads when it fits
-// (rows of up to ~15 entries at the default panel height), so each row costs
-// one round of independent gathers.  Each workgroup accumulates its dot
+// With `reverse` set the walk runs from the end of each eighth: alternate
+// steps then begin on the rows the previous step ended with.  With `stage`
+// set, a panel's slice of the CSR arrays (row offsets, column indices,
+// values) is first copied to LDS with coalesced loads when it fits (about 60
+// entries per row on average at the default FP32 panel height, 30 for FP64),
+// so each row costs one round of independent gathers.  Each workgroup accumulates its dot
 // products over all the rows it processes and writes one partial pair per
 // probe column at the end; the grid size and the panel-to-workgroup map are
-// fixed for a device, so results are bitwise reproducible run to run.
+// fixed for a device and direction, so results are bitwise reproducible run
+// to run.
 template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
 __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     constexpr int N = Pack<TV>::N;
     constexpr int kLdsDoubles = kWaves * 64 * 2 * N;
-    __shared__ double smem[kLdsDoubles];
+    __shared__ __align__(16) double smem[kLdsDoubles];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -132,7 +136,6 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     const uint32_t ldb = (uint32_t)p.ld * (uint32_t)sizeof(TV);
     const int coff = cg * N;
     const uint32_t coffb = (uint32_t)coff * (uint32_t)sizeof(TV);
-    const int pass_rows = kWaves * p.rpw;
     const int nslots = kWaves * p.rpw;
 
     // Panel range of this workgroup.
@@ -151,13 +154,13 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
         first = blockIdx.x;
         p_stride = nb;
     }
-    (void)p_begin;
 
     double sx[N], ss[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) sx[e] = ss[e] = 0.0;
 
-    for (int panel = first; panel < p_end; panel += p_stride) {
+    for (int q = first; q < p_end; q += p_stride) {
+        const int panel = p.reverse ? p_begin + p_end - 1 - q : q;
         const int r0 = panel * p.rows_per_block;
         const int r1 = min(p.n, r0 + p.rows_per_block);
         process_panel<TA, TV, FIRST, OFF32, G>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha, p.beta, p.stage,
@@ -186,11 +189,12 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     }
 }
 
-// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8").
+// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8,rev=0|1").
 struct StepTune {
     int stage = 1;
     int persist = 1;
     int gather = 8;
+    int rev = 1;
 };
 static StepTune read_tune() {
     StepTune t;
@@ -200,6 +204,7 @@ static StepTune read_tune() {
         if ((s = strstr(e, "stage="))) t.stage = atoi(s + 6);
         if ((s = strstr(e, "persist="))) t.persist = atoi(s + 8);
         if ((s = strstr(e, "gather="))) t.gather = atoi(s + 7) == 4 ? 4 : 8;
+        if ((s = strstr(e, "rev="))) t.rev = atoi(s + 4);
     }
     return t;
 }
@@ -264,7 +269,7 @@ int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
 
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
                             const BlockGeom& g, int grid, const void* V, void* U, double alpha,
-                            double beta, double* partial) {
+                            double beta, double* partial, bool reverse) {
     StepParams p;
     p.rp = A.rp;
     p.ci = A.ci;
@@ -281,6 +286,7 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.rows_per_block = g.rows_per_block;
     p.npanels = g.nblocks;
     p.stage = tune().stage;
+    p.reverse = reverse && tune().rev;
     const bool off32 = step_off32(A, g, precision);
     const bool g4 = tune().gather == 4;
 #define KPM_STEP_G(TA, TV, GG)                                                                   \

@@ -80,18 +80,56 @@ __device__ __forceinline__ uint64_t voff(uint32_t row, uint32_t ldb, uint32_t co
     return (uint64_t)row * ldb + coffb;
 }
 
+// Readers of a row's CSR entries (column index, value) at position k:
+// the two global arrays, or the panel's (index, value) pairs staged in LDS
+// (one 8- or 16-byte LDS read per entry).
+template <typename TA>
+struct CsrArrays {
+    const int32_t* __restrict__ ci;
+    const TA* __restrict__ val;
+    __device__ __forceinline__ void get(int k, int& j, TA& a) const {
+        j = ci[k];
+        a = val[k];
+    }
+};
+template <typename TA>
+struct CsrPair;
+template <>
+struct CsrPair<float> {
+    int32_t c;
+    float v;
+};
+template <>
+struct __align__(16) CsrPair<double> {
+    double v;
+    int32_t c, pad;
+};
+template <typename TA>
+struct CsrPairs {
+    const CsrPair<TA>* e;
+    __device__ __forceinline__ void get(int k, int& j, TA& a) const {
+        const CsrPair<TA> t = e[k];
+        j = t.c;
+        a = t.v;
+    }
+};
+
 // One matrix row of the fused step for the lanes of one row group: gather
-// the CSR row in predicated batches of G entries (one memory round trip
-// for rows of up to G entries), combine, store, and accumulate the two
-// dot products.
+// the CSR row in batches of G entries (one memory round trip for rows of up
+// to G entries), combine, store, and accumulate the two dot products.
+//
+// A batch first reads its G (index, value) pairs, then issues its G gathers
+// back to back; slots past the end of the row take value 0 and gather the
+// row's own entry (already being loaded, so it costs no extra DRAM traffic),
+// which keeps the loads unconditional instead of behind one branch and one
+// index wait each.
 //
 // EARLY (indices in LDS): the own-row and U loads go out first and overlap
 // the gathers.  Without staging the index loads share the in-order vector
 // memory counter with them, so the own-row and U loads are issued after the
 // gathers instead.
-template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G>
-__device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t* __restrict__ cidx,
-                                         const TA* __restrict__ cval, const char* __restrict__ Vb,
+template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G, typename E>
+__device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, const char* __restrict__ Vb,
                                          char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
                                          double alpha, double beta, double (&sx)[Pack<TV>::N],
                                          double (&ss)[Pack<TV>::N]) {
@@ -106,20 +144,22 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t*
 #pragma unroll
     for (int e = 0; e < N; ++e) acc[e] = (TV)0;
     for (int k = kb; k < ke; k += G) {
-        TV x[G][N];
+        int j[G];
         TV a[G];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            if (k + i < ke) {
-                const int j = cidx[k + i];
-                a[i] = (TV)cval[k + i];
-                Pack<TV>::load(reinterpret_cast<const TV*>(Vb + voff<OFF32>(j, ldb, coffb)), x[i]);
-            } else {
-                a[i] = (TV)0;
-#pragma unroll
-                for (int e = 0; e < N; ++e) x[i][e] = (TV)0;
-            }
+            const bool on = k + i < ke;
+            const int ks = on ? k + i : k;  // k < ke: always a valid entry
+            int jj;
+            TA vv;
+            csr.get(ks, jj, vv);
+            j[i] = on ? jj : row;
+            a[i] = on ? (TV)vv : (TV)0;
         }
+        TV x[G][N];
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+            Pack<TV>::load(reinterpret_cast<const TV*>(Vb + voff<OFF32>(j[i], ldb, coffb)), x[i]);
 #pragma unroll
         for (int i = 0; i < G; ++i)
 #pragma unroll
@@ -153,9 +193,9 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const int32_t*
 
 // One row panel [r0, r1) of the fused step for one workgroup.  With `stage`
 // set and when it fits, the panel's slice of the CSR arrays (row offsets,
-// values, column indices) is first copied to LDS with coalesced loads, so
-// each row costs one round of independent gathers.  The dots are added to
-// the caller's per-lane accumulators sx/ss.
+// and the column indices and values as interleaved pairs) is first copied
+// to LDS with coalesced loads, so each row costs one round of independent
+// gathers.  The dots are added to the caller's per-lane accumulators sx/ss.
 template <typename TA, typename TV, bool FIRST, bool OFF32, int G, int LDS_DOUBLES>
 __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci, const TA* __restrict__ val,
@@ -165,37 +205,37 @@ __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __r
                                               int rpw, double (&sx)[Pack<TV>::N],
                                               double (&ss)[Pack<TV>::N]) {
     const int pass_rows = kWaves * rpw;
-    // Staging layout in LDS (bytes): [row offsets (R+1) x 4, padded to 8]
-    // [values pnnz x sizeof(TA)] [column indices pnnz x 4].
+    // Staging layout in LDS: [row offsets (R+1) x 4 bytes, padded to 16]
+    // [(index, value) pairs pnnz x sizeof(CsrPair<TA>)].
     const int R = r1 - r0;
     const int kbase = rp[r0];
     const int pnnz = rp[r1] - kbase;
-    const int off_val = ((R + 1) * 4 + 7) & ~7;
-    const int off_ci = off_val + pnnz * (int)sizeof(TA);
-    const bool staged = stage && off_ci + pnnz * 4 <= (int)sizeof(smem);
+    const int off_e = ((R + 1) * 4 + 15) & ~15;
+    const bool staged = stage && off_e + pnnz * (int)sizeof(CsrPair<TA>) <= (int)sizeof(smem);
     if (staged) {
         char* base = reinterpret_cast<char*>(smem);
         int32_t* s_rp = reinterpret_cast<int32_t*>(base);
-        TA* s_val = reinterpret_cast<TA*>(base + off_val);
-        int32_t* s_ci = reinterpret_cast<int32_t*>(base + off_ci);
+        CsrPair<TA>* s_e = reinterpret_cast<CsrPair<TA>*>(base + off_e);
         for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = rp[r0 + t] - kbase;
         for (int t = threadIdx.x; t < pnnz; t += kThreads) {
-            s_val[t] = val[kbase + t];
-            s_ci[t] = ci[kbase + t];
+            s_e[t].c = ci[kbase + t];
+            s_e[t].v = val[kbase + t];
         }
         __syncthreads();
         if (lane_on) {
+            const CsrPairs<TA> csr{s_e};
             for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows) {
                 const int lr = row - r0;
-                step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], s_ci, s_val, Vb, Ub, ldb,
-                                                        coffb, alpha, beta, sx, ss);
+                step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], csr, Vb, Ub, ldb, coffb, alpha,
+                                                        beta, sx, ss);
             }
         }
         __syncthreads();  // before the LDS is restaged or reused
     } else if (lane_on) {
+        const CsrArrays<TA> csr{ci, val};
         for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows)
-            step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], ci, val, Vb, Ub, ldb, coffb,
-                                                     alpha, beta, sx, ss);
+            step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], csr, Vb, Ub, ldb, coffb, alpha,
+                                                     beta, sx, ss);
     }
 }
 
