@@ -120,23 +120,33 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
         const int64_t i = i0 + (int64_t)r * LZ_THREADS;
         x[r] = 0.0;
         if (i < n) {
+            // Row entries in batches of 8: indices and values first, then 8
+            // independent gathers (slots past the row's end repeat the
+            // batch's first entry with value 0), then the sums in order.
             double s = 0.0;
             const int32_t kb = a.rp[i], ke = a.rp[i + 1];
-            for (int32_t k = kb; k < ke; k += 4) {
-                double q4[4], v4[4];
+            for (int32_t k = kb; k < ke; k += 8) {
+                int32_t c[8];
+                double v[8], q[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (k + u < ke) {
-                        const int32_t c = a.ci[k + u];
-                        v4[u] = (double)val[k + u];
-                        q4[u] = j == 0 ? lz_start_entry(a.seed, c, inv_sqrt_n) : wr[c] * inv;
-                    } else {
-                        v4[u] = 0.0;
-                        q4[u] = 0.0;
-                    }
+                for (int u = 0; u < 8; ++u) {
+                    const bool on = k + u < ke;
+                    const int32_t ks = on ? k + u : k;
+                    c[u] = a.ci[ks];
+                    // value 0 past the end, as a bit mask so that the load
+                    // stays unconditional
+                    const double vv = (double)val[ks];
+                    v[u] = __longlong_as_double(__double_as_longlong(vv) & (on ? ~0ll : 0ll));
+                }
+                if (j == 0) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) q[u] = lz_start_entry(a.seed, c[u], inv_sqrt_n);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) q[u] = wr[c[u]] * inv;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s = fma(v4[u], q4[u], s);
+                for (int u = 0; u < 8; ++u) s = fma(v[u], q[u], s);
             }
             qj[i] = j == 0 ? lz_start_entry(a.seed, i, inv_sqrt_n) : wr[i] * inv;
             ww[i] = s;
@@ -144,16 +154,30 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
         }
     }
     // h_t = q_t . w for t <= j (this thread wrote its rows of q_j above).
-    for (int t = 0; t <= j; ++t) {
-        const double* __restrict__ qt = a.Q + (int64_t)t * n;
-        double acc = 0.0;
+    // Vectors go in groups of TG (8 loads per thread in flight) whose loads
+    // are all issued before any sum (the group's last slots repeat q_j: same
+    // address, discarded), so a step costs ceil((j+1)/TG) memory round trips
+    // instead of j+1.
+    constexpr int TG = R >= 8 ? 1 : 8 / R;
+    for (int t0 = 0; t0 <= j; t0 += TG) {
+        double q[TG][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = i0 + (int64_t)r * LZ_THREADS;
-            if (i < n) acc = fma(qt[i], x[r], acc);
+        for (int u = 0; u < TG; ++u) {
+            const double* __restrict__ qt = a.Q + (int64_t)min(t0 + u, j) * n;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = i0 + (int64_t)r * LZ_THREADS;
+                q[u][r] = i < n ? qt[i] : 0.0;
+            }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) sh[wave][t] = acc;
+#pragma unroll
+        for (int u = 0; u < TG; ++u) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc = fma(q[u][r], x[r], acc);
+            acc = wave_sum(acc);
+            if (lane == 0 && t0 + u <= j) sh[wave][t0 + u] = acc;
+        }
     }
     lz_store_partials(a, 0, j + 1, sh);
 }

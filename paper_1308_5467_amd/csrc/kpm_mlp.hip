@@ -278,6 +278,41 @@ struct MlpBufs {  // activations for a batch of N rows
     float *z1, *h1, *z2, *h2, *g, *dphi, *absE, *d3, *d2, *d1;
 };
 
+// Forward pass of a few rows (inference on one moment vector): one
+// workgroup per row keeps the activations in LDS and runs the three layers
+// in one launch; thread t owns output column t of each layer and reads
+// column t of the weights (coalesced over the workgroup).  Each output is
+// the same k-ordered FMA chain plus bias as in the tiled GEMM, so the
+// result is bitwise that of the batched path.
+constexpr int kSmallRows = 16;
+__global__ __launch_bounds__(NH) void forward_small_kernel(const float* __restrict__ x, const float* __restrict__ p,
+                                                           float* __restrict__ g) {
+    __shared__ float xs[NIN], h1[NH], h2[NH];
+    const int t = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    if (t < NIN) xs[t] = x[row * NIN + t];
+    __syncthreads();
+    const float* __restrict__ W1 = p + P_W1;
+    const float* __restrict__ W2 = p + P_W2;
+    const float* __restrict__ W3 = p + P_W3;
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < NIN; ++k) acc = fmaf(xs[k], W1[k * NH + t], acc);
+    h1[t] = gelu_f(acc + p[P_B1 + t]);
+    __syncthreads();
+    acc = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < NH; ++k) acc = fmaf(h1[k], W2[k * NH + t], acc);
+    h2[t] = gelu_f(acc + p[P_B2 + t]);
+    __syncthreads();
+    if (t < NOUT) {
+        acc = 0.0f;
+#pragma unroll 8
+        for (int k = 0; k < NH; ++k) acc = fmaf(h2[k], W3[k * NOUT + t], acc);
+        g[row * NOUT + t] = t == 0 ? 1.0f : sigmoid_f(acc + p[P_B3 + t]);
+    }
+}
+
 static hipError_t forward(hipStream_t s, int N, const float* x, const float* p, const MlpBufs& b) {
     hipError_t e;
     if ((e = gemm<false, false>(s, N, NH, NIN, x, NIN, p + P_W1, NH, EpiBiasGelu{p + P_B1, b.z1, b.h1, NH})))
@@ -466,7 +501,12 @@ extern "C" kpm_status kpm_mlp_forward(kpm_ctx* ctx, int N, const float* x, float
     float* xd;
     if ((st = mlp_work(ctx, N, &w)) != KPM_OK) return st;
     if ((st = upload(ctx, "mlp_x", x, (size_t)N * NIN, &xd)) != KPM_OK) return st;
-    KPM_HIP(ctx, forward(ctx->stream, N, xd, (const float*)ctx->mlp_params.p, w.b));
+    if (N <= kSmallRows) {
+        forward_small_kernel<<<N, NH, 0, ctx->stream>>>(xd, (const float*)ctx->mlp_params.p, w.b.g);
+        KPM_HIP(ctx, hipGetLastError());
+    } else {
+        KPM_HIP(ctx, forward(ctx->stream, N, xd, (const float*)ctx->mlp_params.p, w.b));
+    }
     KPM_HIP(ctx, hipMemcpyAsync(g, w.b.g, (size_t)N * NOUT * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
     KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return KPM_OK;

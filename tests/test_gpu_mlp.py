@@ -61,6 +61,20 @@ def test_forward_parity(ctx):
     assert np.all(g[:, 0] == 1.0)
 
 
+def test_small_batch_forward_matches_batched_path(ctx):
+    """Up to 16 rows run in the one-launch inference kernel, more rows in the
+    tiled GEMM path; both sum each output in the same order."""
+    p = _params(9)
+    X, _ = _batch(40, 10)
+    kpm.kpm_mlp_set_params(ctx, kpm.mlp_pack(p))
+    g_big = kpm.kpm_mlp_forward(ctx, X)
+    for rows in (slice(0, 1), slice(3, 19), slice(39, 40)):
+        g_small = kpm.kpm_mlp_forward(ctx, X[rows])
+        assert np.array_equal(g_small, g_big[rows])
+    ref, _ = oracle.mlp_forward(p, X[:1])
+    assert np.max(np.abs(kpm.kpm_mlp_forward(ctx, X[:1]) - ref)) < 2e-5
+
+
 def test_loss_and_gradient_parity(ctx):
     p = _params(5)
     X, T = _batch(257, 6)
