@@ -205,6 +205,52 @@ kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, 
                         double ub, const double* edges, int nbins, double* mass);
 
 /*
+ * kpm_slq -- the stochastic Lanczos method of section 3.2.1.  For every probe
+ * vector v_l (l < nvec, the Rademacher vectors of opts->seed) an M-step
+ * Lanczos factorisation A V_M = V_M T_M + f_M e_M^T (eq. (lanfact)) from
+ * v_l / ||v_l|| by the plain three-term recurrence (no re-orthogonalisation),
+ * in FP64 on B = (A - cI)/d, c = (lb+ub)/2, d = (ub-lb)/2 (lb < ub need not
+ * enclose the spectrum; they only centre and scale the arithmetic).  The run
+ * of a probe stops at the first step k whose residual norm beta_k is at most
+ * 1e-12 of the largest |alpha_j|, beta_j so far (breakdown: an invariant
+ * subspace was found).  Outputs, row l for probe l (host, nvec x M):
+ *   theta:  Ritz values c + d theta_k of the probe's tridiagonal matrix,
+ *           ascending (eq. (landist)); 0 past steps_used[l];
+ *   tau2:   squared first components of its normalised eigenvectors, the
+ *           node weights (sum 1 per probe: a Rademacher probe has ||v||^2 = n,
+ *           which cancels the 1/n of eq. (lanapprox)); 0 past steps_used[l];
+ *   steps_used (nullable, int [nvec]): size of the tridiagonal matrix;
+ *   alpha, beta (nullable): T of B, alpha[l*M+k] = q_k.B q_k (diagonal),
+ *           beta[l*M+k] = ||r_k|| (coupling of q_k and q_{k+1}; the last one
+ *           is ||f_M||).
+ * opts: M = Lanczos steps in [1, 4096], nvec, block (0 = min(nvec, 64),
+ * <= 128), seed, validate, rows_per_block; precision must be KPM_FP64
+ * (KPM_ERR_UNSUPPORTED otherwise).  FP32 or FP64 matrix values.
+ */
+kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub, const kpm_moment_opts* opts,
+                   double* theta, double* tau2, int* steps_used, double* alpha, double* beta);
+
+/*
+ * kpm_slq_dos -- eq. (landos): the Gaussian-blurred Lanczos density
+ *   phi(x_i) = (1/nvec) sum_l sum_k tau2[l*M+k] g_sigma(x_i - theta[l*M+k]),
+ * g_sigma(t) = exp(-t^2 / (2 sigma^2)) / sqrt(2 pi sigma^2) (eq. (gauss)),
+ * at npts points x (host) into phi (host), all in A's units.  theta, tau2:
+ * host [nvec * M] as written by kpm_slq.  Non-negative by construction.
+ */
+kpm_status kpm_slq_dos(kpm_ctx* ctx, const double* theta, const double* tau2, int nvec, int M, double sigma,
+                       const double* x, int npts, double* phi);
+
+/*
+ * kpm_tridiag_eig -- host-only helper (no device work): eigenvalues theta
+ * (ascending) and squared first eigenvector components tau2 of the
+ * symmetric tridiagonal matrix with diagonal alpha[0..m-1] and off-diagonal
+ * beta[0..m-2] (beta may be NULL when m = 1), i.e. the nodes and weights of
+ * eq. (landist) (Gauss quadrature, eq. (tauexpand)).  KPM_ERR_ARG for m < 1
+ * or non-finite input, KPM_ERR_NOCONV if the QR iteration does not converge.
+ */
+kpm_status kpm_tridiag_eig(int m, const double* alpha, const double* beta, double* theta, double* tau2);
+
+/*
  * kpm_rademacher -- fill a device block out[i * ld + j] (i < n, j < nvec)
  * with probe vectors vec0 .. vec0+nvec-1 of `seed` as float (precision
  * KPM_FP32) or double (KPM_FP64).  Columns nvec .. ld-1 are left untouched.

@@ -29,6 +29,7 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
+    "kpm_slq", "kpm_slq_dos", "kpm_tridiag_eig",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -78,6 +79,9 @@ def load_library(path: str = LIB_PATH):
         "kpm_gershgorin": ([P, P, P, P], I32),
         "kpm_moments_robust": ([P, P, I32, U64, D, P, P, P, P, P, P], I32),
         "kpm_damping_factors": ([P, I32, I32, P, P], I32),
+        "kpm_slq": ([P, P, D, D, P, P, P, P, P, P], I32),
+        "kpm_slq_dos": ([P, P, P, I32, I32, D, P, I32, P], I32),
+        "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_rademacher": ([P, U64, I64, I32, I64, I64, I32, P], I32),
@@ -263,6 +267,49 @@ def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int
         return mu, mx
     ctx.check(st)
     return mu
+
+
+def kpm_slq(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int, block: int = 0,
+            validate: bool = False, rows_per_block: int = 0, coefficients: bool = False):
+    """Stochastic Lanczos nodes: theta [nvec, M] (A's units), tau2 [nvec, M],
+    steps_used [nvec]; with coefficients=True also alpha, beta [nvec, M] of B."""
+    o = _opts(M, nvec, seed, "f64", block, validate, rows_per_block)
+    theta = np.zeros((nvec, M))
+    tau2 = np.zeros((nvec, M))
+    used = np.zeros(nvec, dtype=np.int32)
+    al = np.zeros((nvec, M)) if coefficients else None
+    be = np.zeros((nvec, M)) if coefficients else None
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_slq(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), _p(theta), _p(tau2),
+                              used.ctypes.data_as(ctypes.c_void_p), _p(al) if coefficients else None,
+                              _p(be) if coefficients else None))
+    return (theta, tau2, used, al, be) if coefficients else (theta, tau2, used)
+
+
+def kpm_slq_dos(ctx: Context, theta, tau2, sigma: float, x) -> np.ndarray:
+    """Eq. (landos) at points x (A's units)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    w = np.ascontiguousarray(tau2, dtype=np.float64)
+    if th.ndim != 2 or th.shape != w.shape:
+        raise ValueError("theta and tau2 must be [nvec, M] arrays of the same shape")
+    x = _f64(x)
+    phi = np.zeros(x.size)
+    ctx.check(ctx.lib.kpm_slq_dos(ctx.handle, _p(th), _p(w), th.shape[0], th.shape[1], sigma, _p(x), x.size,
+                                  _p(phi)))
+    return phi
+
+
+def kpm_tridiag_eig(alpha, beta):
+    """Host-only: eigenvalues and squared first eigenvector components of tridiag(beta, alpha, beta)."""
+    lib = load_library()
+    a = _f64(alpha)
+    b = _f64(beta) if a.size > 1 else np.zeros(1)
+    th = np.zeros(a.size)
+    w = np.zeros(a.size)
+    st = lib.kpm_tridiag_eig(a.size, _p(a), _p(b), _p(th), _p(w))
+    if st != 0:
+        raise KpmError(st, "kpm_tridiag_eig failed")
+    return th, w
 
 
 def kpm_gershgorin(ctx: Context, A):

@@ -1,0 +1,600 @@
+// Stochastic Lanczos DOS (Lin, Saad & Yang, section 3.2.1): for every probe
+// vector v_l an M-step Lanczos factorisation A V_M = V_M T_M + f_M e_M^T
+// (eq. (lanfact)) started from v_l / ||v_l||, the eigenvalues theta_k of
+// T_M and the squared first components tau_k^2 of its eigenvectors
+// (eq. (landist)), and the Gaussian-blurred average over probes
+// (eq. (landos)).  The run is on B = (A - cI)/d (eq. (cd)), which only
+// conditions the arithmetic (Lanczos is shift- and scale-invariant); Ritz
+// values are returned in A's units.
+//
+// Device part: a block of b probes runs the plain three-term recurrence
+// (no re-orthogonalisation) one sparse product per step, on the same
+// row-major [n x ld] probe-block layout, LDS-staged CSR panels and
+// XCD-aware resident grid as the Chebyshev step.  Step k reads
+// u_{k-1} = B q_{k-1} - beta_{k-2} q_{k-2} and q_{k-1} and forms, per row,
+//   q_k     = (u_{k-1} - alpha_{k-1} q_{k-1}) / beta_{k-1}
+//   u_k     = B q_k - beta_{k-1} q_{k-1}
+// (neighbour entries of q_k are formed the same way from gathered u_{k-1},
+// q_{k-1}), stores q_k and u_k, and accumulates per column q_k.u_k,
+// u_k.u_k and q_k.q_k.  A reduction launch then sets
+//   alpha_k = q_k.u_k,   beta_k = ||u_k - alpha_k q_k||
+//           = sqrt(u.u - 2 alpha_k q.u + alpha_k^2 q.q),
+// so one step is one data-parallel launch plus one small reduction.  The
+// last form cancels as beta_k -> 0 (near a breakdown u_k is almost parallel
+// to q_k), so the three sums are carried as unevaluated pairs hi + lo
+// (error-free products by FMA, error-free additions) through the per-lane
+// accumulation, the workgroup combination and the reduction, and the
+// expression is evaluated in the same pair arithmetic: beta_k keeps full
+// relative accuracy down to the rounding noise of u_k - alpha_k q_k.  Step 0
+// starts from u_{-1} = v, q_{-1} = 0, alpha_{-1} = 0, beta_{-1} = ||v|| = sqrt(n).
+//
+// Host part: per probe, the breakdown rule (stop at the first beta_k below
+// 1e-12 of the largest coefficient so far), the eigenvalues and first
+// eigenvector components of the symmetric tridiagonal matrix by implicit
+// QR steps with Wilkinson shifts accumulating only the first row of the
+// eigenvector matrix (Golub & Welsch), and the blurred density on the device.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kpm_internal.h"
+#include "kpm_step.h"
+
+namespace kpm {
+
+namespace {
+
+constexpr int kSlqG = 4;  // gathers per batch (two gathered blocks per entry)
+
+// Pair ("double-double") arithmetic: a value is hi + lo with |lo| <= ulp(hi)/2.
+struct Dd {
+    double hi, lo;
+};
+__device__ __forceinline__ Dd two_sum(double a, double b) {
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ Dd dd_add(Dd a, Dd b) {
+    Dd s = two_sum(a.hi, b.hi);
+    s.lo += a.lo + b.lo;
+    return two_sum(s.hi, s.lo);
+}
+// a += x * y with the product's rounding error kept
+__device__ __forceinline__ void dd_fma_acc(Dd& a, double x, double y) {
+    const double p = x * y;
+    const double e = fma(x, y, -p);
+    const Dd s = two_sum(a.hi, p);
+    a.hi = s.hi;
+    a.lo += s.lo + e;
+}
+__device__ __forceinline__ Dd dd_mul_d(Dd a, double b) {
+    const double p = a.hi * b;
+    const double e = fma(a.hi, b, -p);
+    return two_sum(p, fma(a.lo, b, e));
+}
+
+struct SlqParams {
+    const int32_t* rp;
+    const int32_t* ci;
+    const void* val;
+    const char* Wp;        // u_{k-1}
+    const char* Qp;        // q_{k-1}
+    char* Wn;              // u_k
+    char* Qn;              // q_k
+    const double* coef;    // [2][ld]: alpha_{k-1}, beta_{k-1}
+    double* partial;       // [grid][6][ld]: q.u, u.u, q.q per workgroup as (hi, lo) pairs
+    double sA, sI;         // B = sA A + sI I
+    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage, reverse;
+};
+
+// One matrix row for the lanes of one row group (N = 2 columns per lane).
+template <typename TA, bool EARLY, int G, typename E>
+__device__ __forceinline__ void slq_row(int row, int kb, int ke, const E& csr, const SlqParams& p, uint32_t ldb,
+                                        uint32_t coffb, const double (&ap)[2], const double (&inv)[2],
+                                        const double (&bp)[2], Dd (&s_qu)[2], Dd (&s_uu)[2], Dd (&s_qq)[2]) {
+    const uint32_t orow = row * ldb + coffb;
+    double w0[2], q0[2];
+    if (EARLY) {
+        Pack<double>::load(reinterpret_cast<const double*>(p.Wp + orow), w0);
+        Pack<double>::load(reinterpret_cast<const double*>(p.Qp + orow), q0);
+    }
+    double accw[2] = {0.0, 0.0}, accq[2] = {0.0, 0.0};
+    for (int k = kb; k < ke; k += G) {
+        int j[G];
+        double a[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const bool on = k + i < ke;
+            const int ks = on ? k + i : k;
+            int jj;
+            TA vv;
+            csr.get(ks, jj, vv);
+            j[i] = on ? jj : row;
+            a[i] = on ? (double)vv : 0.0;
+        }
+        double xw[G][2], xq[G][2];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const uint32_t o = (uint32_t)j[i] * ldb + coffb;
+            Pack<double>::load(reinterpret_cast<const double*>(p.Wp + o), xw[i]);
+            Pack<double>::load(reinterpret_cast<const double*>(p.Qp + o), xq[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                accw[e] = fma(a[i], xw[i][e], accw[e]);
+                accq[e] = fma(a[i], xq[i][e], accq[e]);
+            }
+    }
+    if (!EARLY) {
+        Pack<double>::load(reinterpret_cast<const double*>(p.Wp + orow), w0);
+        Pack<double>::load(reinterpret_cast<const double*>(p.Qp + orow), q0);
+    }
+    double qn[2], un[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        qn[e] = fma(-ap[e], q0[e], w0[e]) * inv[e];
+        const double aq = fma(-ap[e], accq[e], accw[e]) * inv[e];  // (A q_k)_row
+        un[e] = fma(p.sA, aq, fma(p.sI, qn[e], -bp[e] * q0[e]));
+    }
+    Pack<double>::store_nt(reinterpret_cast<double*>(p.Qn + orow), qn);
+    Pack<double>::store_nt(reinterpret_cast<double*>(p.Wn + orow), un);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        dd_fma_acc(s_qu[e], qn[e], un[e]);
+        dd_fma_acc(s_uu[e], un[e], un[e]);
+        dd_fma_acc(s_qq[e], qn[e], qn[e]);
+    }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
+    constexpr int kLdsDoubles = kWaves * 64 * 6 * 2;
+    __shared__ __align__(16) double smem[kLdsDoubles];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rw = lane / p.lpr;
+    const int cg = lane - rw * p.lpr;
+    const bool lane_on = rw < p.rpw;
+    const TA* __restrict__ val = static_cast<const TA*>(p.val);
+    const uint32_t ldb = (uint32_t)p.ld * 8u;
+    const int coff = cg * 2;
+    const uint32_t coffb = (uint32_t)coff * 8u;
+    const int pass_rows = kWaves * p.rpw;
+    const int nslots = kWaves * p.rpw;
+
+    double ap[2], inv[2], bp[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int c = lane_on ? coff + e : 0;
+        ap[e] = p.coef[c];
+        bp[e] = p.coef[p.ld + c];
+        inv[e] = bp[e] > 0.0 ? 1.0 / bp[e] : 0.0;
+    }
+
+    const int nb = gridDim.x;
+    int p_begin, p_end, p_stride, first;
+    if (nb >= 8) {
+        const int x = blockIdx.x & 7, li = blockIdx.x >> 3;
+        p_begin = (int)((int64_t)p.npanels * x / 8);
+        p_end = (int)((int64_t)p.npanels * (x + 1) / 8);
+        first = p_begin + li;
+        p_stride = nb / 8 + (x < (nb & 7) ? 1 : 0);
+    } else {
+        p_begin = 0;
+        p_end = p.npanels;
+        first = blockIdx.x;
+        p_stride = nb;
+    }
+
+    Dd s_qu[2] = {{0.0, 0.0}, {0.0, 0.0}}, s_uu[2] = {{0.0, 0.0}, {0.0, 0.0}}, s_qq[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int q = first; q < p_end; q += p_stride) {
+        const int panel = p.reverse ? p_begin + p_end - 1 - q : q;
+        const int r0 = panel * p.rows_per_block;
+        const int r1 = min(p.n, r0 + p.rows_per_block);
+        const int R = r1 - r0;
+        const int kbase = p.rp[r0];
+        const int pnnz = p.rp[r1] - kbase;
+        const int off_e = ((R + 1) * 4 + 15) & ~15;
+        const bool staged = p.stage && off_e + pnnz * (int)sizeof(CsrPair<TA>) <= (int)sizeof(smem);
+        if (staged) {
+            char* base = reinterpret_cast<char*>(smem);
+            int32_t* s_rp = reinterpret_cast<int32_t*>(base);
+            CsrPair<TA>* s_e = reinterpret_cast<CsrPair<TA>*>(base + off_e);
+            for (int t = threadIdx.x; t <= R; t += kThreads) s_rp[t] = p.rp[r0 + t] - kbase;
+            for (int t = threadIdx.x; t < pnnz; t += kThreads) {
+                s_e[t].c = p.ci[kbase + t];
+                s_e[t].v = val[kbase + t];
+            }
+            __syncthreads();
+            if (lane_on) {
+                const CsrPairs<TA> csr{s_e};
+                for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows) {
+                    const int lr = row - r0;
+                    slq_row<TA, true, kSlqG>(row, s_rp[lr], s_rp[lr + 1], csr, p, ldb, coffb, ap, inv, bp, s_qu,
+                                             s_uu, s_qq);
+                }
+            }
+            __syncthreads();
+        } else if (lane_on) {
+            const CsrArrays<TA> csr{p.ci, val};
+            for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows)
+                slq_row<TA, false, kSlqG>(row, p.rp[row], p.rp[row + 1], csr, p, ldb, coffb, ap, inv, bp, s_qu,
+                                          s_uu, s_qq);
+        }
+    }
+
+    // One partial triple (as hi, lo pairs) per workgroup and column,
+    // combined over row slots in a fixed order.
+    double* red = smem;
+    if (lane_on) {
+        const int slot = wave * p.rpw + rw;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const Dd v[3] = {s_qu[e], s_uu[e], s_qq[e]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                red[(slot * 6 + 2 * d) * p.ld + coff + e] = v[d].hi;
+                red[(slot * 6 + 2 * d + 1) * p.ld + coff + e] = v[d].lo;
+            }
+        }
+    }
+    __syncthreads();
+    double* __restrict__ outp = p.partial + (int64_t)blockIdx.x * 6 * p.ld;
+    for (int t = threadIdx.x; t < 3 * p.ld; t += kThreads) {
+        const int d = t / p.ld;
+        const int c = t - d * p.ld;
+        Dd s = {0.0, 0.0};
+        for (int sl = 0; sl < nslots; ++sl)
+            s = dd_add(s, Dd{red[(sl * 6 + 2 * d) * p.ld + c], red[(sl * 6 + 2 * d + 1) * p.ld + c]});
+        outp[(2 * d) * p.ld + c] = s.hi;
+        outp[(2 * d + 1) * p.ld + c] = s.lo;
+    }
+}
+
+// alpha_k, beta_k per column from the partial triples of step k (pairs):
+// workgroup x covers columns [64x, 64x+64); its 4 wavefronts add contiguous
+// quarters of the workgroup partials in pair arithmetic, combined in a fixed
+// order; beta_k^2 = u.u - 2 alpha q.u + alpha^2 q.q is evaluated in pairs.
+__global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restrict__ partial, int nblocks, int ld,
+                                                         double* __restrict__ coef_next) {
+    __shared__ double sh[3][2][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int per = (nblocks + 3) / 4;
+    const int b0 = wave * per, b1 = min(nblocks, b0 + per);
+    for (int kind = 0; kind < 3; ++kind) {
+        Dd s = {0.0, 0.0};
+        if (c < ld)
+            for (int b = b0; b < b1; ++b)
+                s = dd_add(s, Dd{partial[((int64_t)b * 6 + 2 * kind) * ld + c],
+                                 partial[((int64_t)b * 6 + 2 * kind + 1) * ld + c]});
+        sh[kind][0][wave][lane] = s.hi;
+        sh[kind][1][wave][lane] = s.lo;
+    }
+    __syncthreads();
+    if (wave == 0 && c < ld) {
+        Dd r[3];
+        for (int kind = 0; kind < 3; ++kind) {
+            r[kind] = {0.0, 0.0};
+            for (int w = 0; w < 4; ++w) r[kind] = dd_add(r[kind], Dd{sh[kind][0][w][lane], sh[kind][1][w][lane]});
+        }
+        const double alpha = r[0].hi + r[0].lo;
+        // u.u - 2 alpha q.u + alpha^2 q.q
+        const Dd t1 = dd_mul_d(r[0], -2.0 * alpha);
+        const Dd t2 = dd_mul_d(dd_mul_d(r[2], alpha), alpha);
+        const Dd b2 = dd_add(dd_add(r[1], t1), t2);
+        const double b2d = b2.hi + b2.lo;
+        coef_next[c] = alpha;
+        coef_next[ld + c] = sqrt(b2d > 0.0 ? b2d : 0.0);
+    }
+}
+
+// coef0 = (alpha_{-1} = 0, beta_{-1} = ||v|| = sqrt(n)) for the ncols probe
+// columns, (0, 0) for padding columns; q_{-1} = 0.
+__global__ void slq_init_kernel(double* __restrict__ coef0, int ld, int ncols, double sqrt_n,
+                                double* __restrict__ Q, int64_t total) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 < ld) {
+        coef0[i0] = 0.0;
+        coef0[ld + i0] = i0 < ncols ? sqrt_n : 0.0;
+    }
+    for (int64_t i = i0; i < total; i += (int64_t)gridDim.x * blockDim.x) Q[i] = 0.0;
+}
+
+// Eq. (landos): phi(x_i) = (1/nvec) sum over nodes of tau2 g_sigma(x_i - theta);
+// one workgroup per point, fixed-order tree.
+__global__ __launch_bounds__(256) void slq_dos_kernel(const double* __restrict__ theta,
+                                                      const double* __restrict__ tau2, int64_t nnodes, int nvec,
+                                                      double sigma, const double* __restrict__ x,
+                                                      double* __restrict__ phi) {
+    __shared__ double sh[256];
+    const double xi = x[blockIdx.x];
+    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    const double norm = 1.0 / sqrt(2.0 * M_PI * sigma * sigma);
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < nnodes; k += 256) {
+        const double w = tau2[k];
+        if (w != 0.0) {
+            const double t = xi - theta[k];
+            s = fma(w, exp(-t * t * inv2s2), s);
+        }
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) phi[blockIdx.x] = sh[0] * norm / nvec;
+}
+
+int slq_grid(bool f64vals, int npanels) {
+    static int res[2] = {-1, -1};
+    int& r = res[f64vals ? 1 : 0];
+    if (r < 0) {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        const void* k = f64vals ? reinterpret_cast<const void*>(slq_step_kernel<double>)
+                                : reinterpret_cast<const void*>(slq_step_kernel<float>);
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) == hipSuccess)
+            r = per_cu * prop.multiProcessorCount;
+        else
+            r = 0;
+    }
+    return r > 0 && r < npanels ? r : npanels;
+}
+
+}  // namespace
+
+}  // namespace kpm
+
+using namespace kpm;
+
+// ---------------------------------------------------------------- host eigensolver
+// Eigenvalues (ascending) and squared first eigenvector components of the
+// symmetric tridiagonal matrix with diagonal a[0..m-1] and off-diagonal
+// b[0..m-2]: implicit symmetric QR steps with Wilkinson shifts (Golub & Van
+// Loan, section 8.3), each Givens rotation also applied to the first row z
+// of the accumulated orthogonal matrix (z starts as e_1), so the weights
+// z_k^2 come out without forming eigenvectors (Golub & Welsch).
+static bool tridiag_first_row(int m, std::vector<double>& a, std::vector<double>& b, std::vector<double>& z) {
+    z.assign(m, 0.0);
+    z[0] = 1.0;
+    if (m == 1) return true;
+    const double eps = 2.220446049250313e-16;
+    double anorm = 0.0;
+    for (int k = 0; k < m; ++k) anorm = std::max(anorm, fabs(a[k]) + (k > 0 ? fabs(b[k - 1]) : 0.0) +
+                                                            (k + 1 < m ? fabs(b[k]) : 0.0));
+    // a coupling is negligible against its neighbours or against the norm
+    auto small = [&](int i) { return fabs(b[i]) <= eps * (fabs(a[i]) + fabs(a[i + 1])) || fabs(b[i]) <= 0.5 * eps * anorm; };
+    int hi = m - 1;
+    int iter = 0;
+    while (hi > 0) {
+        // deflate negligible couplings at the bottom
+        if (small(hi - 1)) {
+            b[hi - 1] = 0.0;
+            --hi;
+            iter = 0;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && !small(lo - 1)) --lo;
+        if (lo > 0) b[lo - 1] = 0.0;
+        if (++iter > 60) return false;
+        // Wilkinson shift from the trailing 2 x 2 block
+        const double dd = 0.5 * (a[hi - 1] - a[hi]);
+        const double e2 = b[hi - 1] * b[hi - 1];
+        const double mu = a[hi] - e2 / (dd + copysign(sqrt(dd * dd + e2), dd == 0.0 ? 1.0 : dd));
+        double x = a[lo] - mu, y = b[lo];
+        for (int k = lo; k < hi; ++k) {
+            // rotation G = [c s; -s c] with G^T [x; y] = [r; 0]
+            double c, s;
+            if (y == 0.0) {
+                c = 1.0;
+                s = 0.0;
+            } else if (fabs(y) > fabs(x)) {
+                const double t = -x / y;
+                s = 1.0 / sqrt(1.0 + t * t);
+                c = s * t;
+            } else {
+                const double t = -y / x;
+                c = 1.0 / sqrt(1.0 + t * t);
+                s = c * t;
+            }
+            if (k > lo) b[k - 1] = c * x - s * y;  // the bulge row becomes the new coupling
+            const double p = a[k], q = b[k], r = a[k + 1];
+            a[k] = c * c * p - 2.0 * c * s * q + s * s * r;
+            a[k + 1] = s * s * p + 2.0 * c * s * q + c * c * r;
+            b[k] = c * s * (p - r) + (c * c - s * s) * q;
+            if (k + 1 < hi) {
+                y = -s * b[k + 1];  // new bulge below the coupling
+                b[k + 1] = c * b[k + 1];
+            }
+            x = b[k];
+            const double z0 = z[k], z1 = z[k + 1];
+            z[k] = c * z0 - s * z1;
+            z[k + 1] = s * z0 + c * z1;
+        }
+    }
+    return true;
+}
+
+extern "C" kpm_status kpm_tridiag_eig(int m, const double* alpha, const double* beta, double* theta,
+                                      double* tau2) {
+    if (m < 1 || !alpha || !theta || !tau2 || (m > 1 && !beta)) return KPM_ERR_ARG;
+    std::vector<double> a(alpha, alpha + m), b(m > 1 ? m - 1 : 1, 0.0), z;
+    for (int k = 0; k + 1 < m; ++k) {
+        if (!std::isfinite(beta[k]) || !std::isfinite(alpha[k])) return KPM_ERR_ARG;
+        b[k] = beta[k];
+    }
+    if (!std::isfinite(alpha[m - 1])) return KPM_ERR_ARG;
+    if (!tridiag_first_row(m, a, b, z)) return KPM_ERR_NOCONV;
+    std::vector<int> idx(m);
+    for (int k = 0; k < m; ++k) idx[k] = k;
+    std::sort(idx.begin(), idx.end(), [&](int i, int j) { return a[i] < a[j] || (a[i] == a[j] && i < j); });
+    for (int k = 0; k < m; ++k) {
+        theta[k] = a[idx[k]];
+        tau2[k] = z[idx[k]] * z[idx[k]];
+    }
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- kpm_slq
+extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub, const kpm_moment_opts* o,
+                              double* theta, double* tau2, int* steps_used, double* alpha_out,
+                              double* beta_out) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!o || !theta || !tau2) return kpm_fail(ctx, KPM_ERR_ARG, "opts, theta or tau2 is NULL");
+    if (o->M < 1 || o->M > 4096) return kpm_fail(ctx, KPM_ERR_ARG, "M (Lanczos steps) must be in [1, 4096]");
+    if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
+    if (o->precision != KPM_FP64)
+        return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "the Lanczos method runs in FP64 (precision KPM_FP64)");
+    if (o->block < 0 || o->block > 128) return kpm_fail(ctx, KPM_ERR_ARG, "block out of range");
+    if (o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
+        return kpm_fail(ctx, KPM_ERR_ARG, "rows_per_block out of range");
+    if (!(std::isfinite(lb) && std::isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    CsrDev A;
+    kpm_status st = kpm_prepare_csr(ctx, Ain, KPM_FP64, &A, "");
+    if (st != KPM_OK) return st;
+    if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
+
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    const int M = o->M, nvec = o->nvec;
+    int b = o->block > 0 ? std::min(o->block, nvec) : std::min(nvec, 64);
+    while (b > 1 && (uint64_t)A.n * ((b + 1) / 2 * 2) * 8 >= (1ull << 32)) b /= 2;
+    if ((uint64_t)A.n * ((b + 1) / 2 * 2) * 8 >= (1ull << 32))
+        return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "probe blocks of the Lanczos method must be smaller than 4 GiB");
+    const BlockGeom g = make_geom(A.n, b, KPM_FP64, o->rows_per_block);
+    const int grid = slq_grid(A.val_f64 != 0, g.nblocks);
+    const size_t vbytes = (size_t)A.n * g.ld * 8;
+    void *W0, *W1, *Q0, *Q1, *part, *coef;
+    if ((st = kpm_ws(ctx, "X0", vbytes, &W0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X1", vbytes, &W1)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "slq_Q0", vbytes, &Q0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "slq_Q1", vbytes, &Q1)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "partial", (size_t)grid * 6 * g.ld * 8, &part)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "slq_coef", (size_t)(M + 1) * 2 * g.ld * 8, &coef)) != KPM_OK) return st;
+
+    std::vector<double> hc((size_t)(M + 1) * 2 * g.ld);
+    std::vector<double> al((size_t)nvec * M), be((size_t)nvec * M);
+    const int nblk_vec = (nvec + b - 1) / b;
+    for (int blk = 0; blk < nblk_vec; ++blk) {
+        const int ncols = std::min(b, nvec - blk * b);
+        const BlockGeom gb = ncols == b ? g : make_geom(A.n, ncols, KPM_FP64, o->rows_per_block);
+        const int gridb = ncols == b ? grid : slq_grid(A.val_f64 != 0, gb.nblocks);
+        const int64_t vec0 = (int64_t)blk * b;
+        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, KPM_FP64, 1, W0));
+        const int64_t total = (int64_t)A.n * gb.ld;
+        const int ib = (int)std::min<int64_t>(4096, (total + 255) / 256);
+        slq_init_kernel<<<std::max(ib, 1), 256, 0, ctx->stream>>>((double*)coef, gb.ld, ncols, sqrt((double)A.n),
+                                                                   (double*)Q0, total);
+        KPM_HIP(ctx, hipGetLastError());
+        char* W[2] = {(char*)W0, (char*)W1};
+        char* Q[2] = {(char*)Q0, (char*)Q1};
+        SlqParams p;
+        p.rp = A.rp;
+        p.ci = A.ci;
+        p.val = A.val;
+        p.partial = (double*)part;
+        p.sA = 1.0 / d;
+        p.sI = -c / d;
+        p.n = A.n;
+        p.ld = gb.ld;
+        p.lpr = gb.lpr;
+        p.rpw = gb.rpw;
+        p.rows_per_block = gb.rows_per_block;
+        p.npanels = gb.nblocks;
+        p.stage = 1;
+        kpm_prof_begin(ctx, "slq_step");
+        for (int k = 0; k < M; ++k) {
+            p.Wp = W[k & 1];
+            p.Qp = Q[k & 1];
+            p.Wn = W[(k + 1) & 1];
+            p.Qn = Q[(k + 1) & 1];
+            p.coef = (const double*)coef + (size_t)k * 2 * gb.ld;
+            p.reverse = k & 1;  // start on the rows the previous step ended with
+            if (A.val_f64) slq_step_kernel<double><<<gridb, kThreads, 0, ctx->stream>>>(p);
+            else slq_step_kernel<float><<<gridb, kThreads, 0, ctx->stream>>>(p);
+            KPM_HIP(ctx, hipGetLastError());
+            slq_reduce_kernel<<<(gb.ld + 63) / 64, 256, 0, ctx->stream>>>(
+                (double*)part, gridb, gb.ld, (double*)coef + (size_t)(k + 1) * 2 * gb.ld);
+            KPM_HIP(ctx, hipGetLastError());
+        }
+        kpm_prof_end(ctx, "slq_step", M);
+        KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, (size_t)(M + 1) * 2 * gb.ld * 8, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        kpm_prof_collect(ctx);
+        for (int col = 0; col < ncols; ++col)
+            for (int k = 0; k < M; ++k) {
+                al[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + col];
+                be[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + gb.ld + col];
+            }
+    }
+    if (alpha_out) memcpy(alpha_out, al.data(), al.size() * 8);
+    if (beta_out) memcpy(beta_out, be.data(), be.size() * 8);
+    // Per probe: breakdown rule, nodes and weights, Ritz values in A's units.
+    std::vector<double> th(M), w(M);
+    for (int l = 0; l < nvec; ++l) {
+        const double* a = &al[(size_t)l * M];
+        const double* bb = &be[(size_t)l * M];
+        int m = M;
+        double scale = 0.0;
+        for (int k = 0; k + 1 < M; ++k) {
+            if (!std::isfinite(a[k]) || !std::isfinite(bb[k]))
+                return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
+            scale = std::max(scale, std::max(fabs(a[k]), bb[k]));
+            if (bb[k] <= 1e-12 * scale) {
+                m = k + 1;
+                break;
+            }
+        }
+        const kpm_status es = kpm_tridiag_eig(m, a, bb, th.data(), w.data());
+        if (es == KPM_ERR_NOCONV)
+            return kpm_fail(ctx, KPM_ERR_NOCONV, "tridiagonal eigenvalue iteration did not converge");
+        if (es != KPM_OK) return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient");
+        for (int k = 0; k < M; ++k) {
+            theta[(size_t)l * M + k] = k < m ? c + d * th[k] : 0.0;
+            tau2[(size_t)l * M + k] = k < m ? w[k] : 0.0;
+        }
+        if (steps_used) steps_used[l] = m;
+    }
+    return KPM_OK;
+}
+
+extern "C" kpm_status kpm_slq_dos(kpm_ctx* ctx, const double* theta, const double* tau2, int nvec, int M,
+                                  double sigma, const double* x, int npts, double* phi) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!theta || !tau2 || !x || !phi || nvec < 1 || M < 1 || npts < 0 || !(sigma > 0.0) || !std::isfinite(sigma))
+        return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (npts == 0) return KPM_OK;
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t nn = (size_t)nvec * M;
+    void *thd, *wd, *xd, *pd;
+    kpm_status st;
+    if ((st = kpm_ws(ctx, "slq_theta", nn * 8, &thd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "slq_tau2", nn * 8, &wd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_x", (size_t)npts * 8, &xd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_phi", (size_t)npts * 8, &pd)) != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemcpyAsync(thd, theta, nn * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(wd, tau2, nn * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(xd, x, (size_t)npts * 8, hipMemcpyHostToDevice, ctx->stream));
+    slq_dos_kernel<<<npts, 256, 0, ctx->stream>>>((const double*)thd, (const double*)wd, (int64_t)nn, nvec, sigma,
+                                                  (const double*)xd, (double*)pd);
+    KPM_HIP(ctx, hipGetLastError());
+    KPM_HIP(ctx, hipMemcpyAsync(phi, pd, (size_t)npts * 8, hipMemcpyDeviceToHost, ctx->stream));
+    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return KPM_OK;
+}

@@ -1,0 +1,131 @@
+"""GPU parity of the stochastic Lanczos method (section 3.2.1) through the C
+ABI against the CPU oracle (``oracle/slq.py``), same probes and the same
+(lb, ub).
+
+Tolerances: Lanczos coefficients alpha_k, beta_k 1e-11 absolute (T of B, so
+O(1) entries); nodes 1e-10 and weights 1e-10 absolute where the run sizes
+agree; blurred density (eq. (landos)) 1e-11 relative to its maximum.  The
+plain recurrence is not re-orthogonalised on either side; differences in
+rounding order stay at the 1e-15 level over 100 steps on these matrices.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1308_5467_amd as kpm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = kpm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(A, dtype):
+    vals = A.val if dtype == "f64" else A.val.astype(np.float32)
+    return kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, dtype)
+
+
+def _check(A, dtype, lb, ub, M, nvec, seed, block=0, vec_ids=None, ctx=None, dos_sigma=0.05):
+    Ao = A if dtype == "f64" else A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    th, t2, used, al, be = kpm.kpm_slq(ctx, dev(A, dtype), lb, ub, M, nvec, seed, block=block, validate=True,
+                                       coefficients=True)
+    ids = range(nvec) if vec_ids is None else vec_ids
+    for l in ids:
+        ra, rb = oracle.lanczos_tridiag(Ao, c, d, M, 1, seed, vec0=l)
+        assert np.max(np.abs(al[l] - ra[0])) < 1e-11, l
+        assert np.max(np.abs(be[l] - rb[0])) < 1e-11, l
+        rth, rt2, rm = oracle.lanczos_nodes(ra, rb)
+        assert used[l] == rm[0], l
+        assert np.max(np.abs(th[l] - (c + d * rth[0]) * (rt2[0] > 0))) < 1e-10 * max(1.0, d), l
+        assert np.max(np.abs(t2[l] - rt2[0])) < 1e-10, l
+    assert np.max(np.abs(t2.sum(axis=1) - 1.0)) < 1e-12
+    x = np.linspace(lb, ub, 200)
+    sig = dos_sigma * d
+    phi = kpm.kpm_slq_dos(ctx, th, t2, sig, x)
+    ref = oracle.lanczos_dos(th, t2, x, sig)
+    assert np.max(np.abs(phi - ref)) < 1e-11 * np.max(ref)
+    assert np.all(phi >= 0.0)
+    return th, t2, used
+
+
+@pytest.mark.parametrize("dtype,L,M,nvec,block", [("f64", 13, 40, 10, 4), ("f32", 13, 40, 10, 4),
+                                                  ("f64", 9, 1, 3, 0), ("f64", 11, 100, 6, 0)])
+def test_anderson3d_parity(ctx, dtype, L, M, nvec, block):
+    """Several workgroups, a ragged row tail and a ragged last probe block."""
+    _say(f"slq anderson3d {dtype} L={L} M={M} nvec={nvec} block={block}")
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(L), 16.0, 70 + L)
+    b = oracle.lanczos_bounds(A if dtype == "f64" else A.rounded_f32(), 20, 3)
+    _check(A, dtype, b["lb"], b["ub"], M, nvec, 123, block=block, ctx=ctx)
+
+
+def test_c1_laplacian(ctx):
+    """2D Dirichlet Laplacian 32 x 32, 100 steps, 20 probes (FP64)."""
+    A = synth.laplacian2d_dirichlet(32)
+    _check(A, "f64", -0.1, 8.1, 100, 20, 2001, ctx=ctx)
+
+
+def test_random_sparse_parity(ctx):
+    A = synth.random_sparse_symmetric(3001, 4.5, 17)
+    b = oracle.lanczos_bounds(A, 20, 4)
+    _check(A, "f64", b["lb"], b["ub"], 60, 5, 9, block=2, ctx=ctx)
+
+
+def test_breakdown_on_repeated_values(ctx):
+    vals = np.array([-0.5] * 50 + [0.1] * 30 + [0.7] * 40)
+    A = synth.diagonal_matrix(np.random.default_rng(2).permutation(vals))
+    th, t2, used = kpm.kpm_slq(ctx, dev(A, "f64"), -1.0, 1.0, 8, 3, 4)
+    assert np.all(used == 3)
+    assert np.max(np.abs(th[:, :3] - np.array([-0.5, 0.1, 0.7]))) < 1e-13
+    assert np.max(np.abs(t2[:, :3] - np.array([50, 30, 40]) / 120.0)) < 1e-13
+    assert np.all(t2[:, 3:] == 0.0) and np.all(th[:, 3:] == 0.0)
+
+
+def test_one_by_one(ctx):
+    A = synth.diagonal_matrix(np.array([2.5]))
+    th, t2, used = kpm.kpm_slq(ctx, dev(A, "f64"), 2.0, 3.0, 5, 1, 0)
+    assert used[0] == 1 and th[0, 0] == 2.5 and t2[0, 0] == 1.0
+
+
+def test_deterministic_and_errors(ctx):
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(20), 8.0, 2)
+    D = dev(A, "f32")
+    r1 = kpm.kpm_slq(ctx, D, -7.0, 12.0, 30, 16, 3)
+    r2 = kpm.kpm_slq(ctx, D, -7.0, 12.0, 30, 16, 3)
+    assert all(np.array_equal(a, b) for a, b in zip(r1, r2))
+    o = kpm.kpm_moment_opts(M=10, nvec=2, block=0, precision=kpm.KPM_FP32, seed=1, validate=0, rows_per_block=0,
+                            flags=0)
+    out = np.zeros(20)
+    c = D.as_c()
+    st = kpm.load_library().kpm_slq(ctx.handle, kpm.ctypes.byref(c), -7.0, 12.0, kpm.ctypes.byref(o),
+                                    out.ctypes.data_as(kpm.ctypes.c_void_p),
+                                    out.ctypes.data_as(kpm.ctypes.c_void_p), None, None, None)
+    assert st == -6
+    for M, nvec, lb, ub in ((0, 2, -7.0, 12.0), (10, 0, -7.0, 12.0), (10, 2, 3.0, 3.0)):
+        with pytest.raises(kpm.KpmError) as e:
+            kpm.kpm_slq(ctx, D, lb, ub, M, nvec, 1)
+        assert e.value.status == -1
+
+
+def test_c2_full_size_sampled(ctx):
+    """64^3 Anderson (n = 262,144), 100 steps, 64 probes, FP32 values on the
+    FP64 Lanczos path; the oracle runs probes 0, 31 and 63."""
+    _say("slq c2 full size")
+    A = synth.config_matrix("c2")
+    D = dev(A, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
+    _check(A, "f32", lb, ub, 100, 64, 2002, vec_ids=[0, 31, 63], ctx=ctx, dos_sigma=0.02)

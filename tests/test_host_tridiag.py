@@ -1,0 +1,69 @@
+"""Host logic of the stochastic Lanczos path: the library's tridiagonal
+eigensolver (nodes and weights of eq. (landist)) against LAPACK through
+scipy, on the CPU (no device work)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import paper_1308_5467_amd as kpm
+
+
+def _ref(a, b):
+    if len(a) == 1:
+        return np.array(a, dtype=float), np.ones(1)
+    w, Z = sla.eigh_tridiagonal(a, b)
+    return w, Z[0] ** 2
+
+
+@pytest.mark.parametrize("m,seed", [(1, 0), (2, 1), (3, 2), (17, 3), (100, 4), (300, 5)])
+def test_random_tridiagonal(m, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1, 1, m)
+    b = rng.uniform(0.05, 0.7, max(m - 1, 0))
+    th, w = kpm.kpm_tridiag_eig(a, b)
+    rth, rw = _ref(a, b)
+    assert np.max(np.abs(th - rth)) < 1e-13
+    assert np.max(np.abs(w - rw)) < 1e-11
+    assert abs(w.sum() - 1.0) < 1e-13 and np.all(np.diff(th) >= 0)
+
+
+def test_lanczos_like_matrix_with_close_nodes():
+    """Coefficients of a long run on a 2D Laplacian: clustered Ritz values."""
+    n = 40
+    lam = np.sort(np.add.outer(2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)),
+                               2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))).ravel())
+    s = (lam - 4.0) / 4.1
+    v = np.random.default_rng(0).choice([-1.0, 1.0], s.size) / np.sqrt(s.size)
+    # Lanczos on diag(s) (plain recurrence, 120 steps)
+    q, qp, bp = v.copy(), np.zeros_like(v), 0.0
+    a, b = [], []
+    for _ in range(120):
+        w = s * q - bp * qp
+        al = q @ w
+        w -= al * q
+        be = np.linalg.norm(w)
+        a.append(al)
+        b.append(be)
+        qp, q, bp = q, w / be, be
+    th, w = kpm.kpm_tridiag_eig(np.array(a), np.array(b[:-1]))
+    rth, rw = _ref(np.array(a), np.array(b[:-1]))
+    assert np.max(np.abs(th - rth)) < 1e-12
+    assert np.max(np.abs(w - rw)) < 1e-10
+
+
+def test_decoupled_blocks_and_zero_diagonal():
+    a = np.array([0.0, 0.0, 0.3, 0.3, -0.2])
+    b = np.array([0.5, 0.0, 1e-20, 0.4])
+    th, w = kpm.kpm_tridiag_eig(a, b)
+    rth, rw = _ref(a, b)
+    assert np.max(np.abs(th - rth)) < 1e-14
+    assert np.max(np.abs(w - rw)) < 1e-14
+    # weight only on the block that contains the first unit vector
+    assert abs(w[np.argmin(np.abs(th + 0.5))] - 0.5) < 1e-14
+
+
+def test_rejects_bad_input():
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_tridiag_eig(np.array([1.0, np.nan]), np.array([0.1]))
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_tridiag_eig(np.array([1.0, 2.0]), np.array([np.inf]))
