@@ -223,8 +223,9 @@ kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, 
  *   alpha, beta (nullable): T of B, alpha[l*M+k] = q_k.B q_k (diagonal),
  *           beta[l*M+k] = ||r_k|| (coupling of q_k and q_{k+1}; the last one
  *           is ||f_M||).
- * opts: M = Lanczos steps in [1, 4096], nvec, block (0 = min(nvec, 64),
- * <= 128), seed, validate, rows_per_block; precision must be KPM_FP64
+ * opts: M = Lanczos steps in [1, 4096], nvec, block (probes per device
+ * block, 0 = min(nvec, 32), <= 64), seed, validate, rows_per_block;
+ * precision must be KPM_FP64
  * (KPM_ERR_UNSUPPORTED otherwise).  FP32 or FP64 matrix values.
  */
 kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub, const kpm_moment_opts* opts,

@@ -49,7 +49,10 @@ namespace kpm {
 
 namespace {
 
-constexpr int kSlqG = 4;  // gathers per batch (two gathered blocks per entry)
+#ifndef KPM_SLQ_G
+#define KPM_SLQ_G 4
+#endif
+constexpr int kSlqG = KPM_SLQ_G;  // gathers per batch (two gathered blocks per entry)
 
 // Pair ("double-double") arithmetic: a value is hi + lo with |lo| <= ulp(hi)/2.
 struct Dd {
@@ -83,28 +86,24 @@ struct SlqParams {
     const int32_t* rp;
     const int32_t* ci;
     const void* val;
-    const char* Wp;        // u_{k-1}
-    const char* Qp;        // q_{k-1}
-    char* Wn;              // u_k
-    char* Qn;              // q_k
+    const char* Zp;        // (u_{k-1}, q_{k-1}) pairs, [n][ld][2]
+    char* Zn;              // (u_k, q_k) pairs
     const double* coef;    // [2][ld]: alpha_{k-1}, beta_{k-1}
-    double* partial;       // [grid][6][ld]: q.u, u.u, q.q per workgroup as (hi, lo) pairs
+    double* partial;       // [6][ld][grid]: q.u, u.u, q.q per workgroup as (hi, lo) pairs
     double sA, sI;         // B = sA A + sI I
-    int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage, reverse;
+    int32_t n, ld, rpw, rows_per_block, npanels, stage, reverse;
 };
 
-// One matrix row for the lanes of one row group (N = 2 columns per lane).
+// One matrix row for one lane (one probe column).  The state of a row is
+// stored as (u, q) pairs, so a gathered neighbour is one 16-byte load.
 template <typename TA, bool EARLY, int G, typename E>
 __device__ __forceinline__ void slq_row(int row, int kb, int ke, const E& csr, const SlqParams& p, uint32_t ldb,
-                                        uint32_t coffb, const double (&ap)[2], const double (&inv)[2],
-                                        const double (&bp)[2], Dd (&s_qu)[2], Dd (&s_uu)[2], Dd (&s_qq)[2]) {
+                                        uint32_t coffb, double ap, double inv, double bp, Dd& s_qu, Dd& s_uu,
+                                        Dd& s_qq) {
     const uint32_t orow = row * ldb + coffb;
-    double w0[2], q0[2];
-    if (EARLY) {
-        Pack<double>::load(reinterpret_cast<const double*>(p.Wp + orow), w0);
-        Pack<double>::load(reinterpret_cast<const double*>(p.Qp + orow), q0);
-    }
-    double accw[2] = {0.0, 0.0}, accq[2] = {0.0, 0.0};
+    double z0[2];
+    if (EARLY) Pack<double>::load(reinterpret_cast<const double*>(p.Zp + orow), z0);
+    double accw = 0.0, accq = 0.0;
     for (int k = kb; k < ke; k += G) {
         int j[G];
         double a[G];
@@ -118,66 +117,47 @@ __device__ __forceinline__ void slq_row(int row, int kb, int ke, const E& csr, c
             j[i] = on ? jj : row;
             a[i] = on ? (double)vv : 0.0;
         }
-        double xw[G][2], xq[G][2];
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const uint32_t o = (uint32_t)j[i] * ldb + coffb;
-            Pack<double>::load(reinterpret_cast<const double*>(p.Wp + o), xw[i]);
-            Pack<double>::load(reinterpret_cast<const double*>(p.Qp + o), xq[i]);
-        }
+        double x[G][2];
 #pragma unroll
         for (int i = 0; i < G; ++i)
+            Pack<double>::load(reinterpret_cast<const double*>(p.Zp + ((uint32_t)j[i] * ldb + coffb)), x[i]);
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                accw[e] = fma(a[i], xw[i][e], accw[e]);
-                accq[e] = fma(a[i], xq[i][e], accq[e]);
-            }
+        for (int i = 0; i < G; ++i) {
+            accw = fma(a[i], x[i][0], accw);
+            accq = fma(a[i], x[i][1], accq);
+        }
     }
-    if (!EARLY) {
-        Pack<double>::load(reinterpret_cast<const double*>(p.Wp + orow), w0);
-        Pack<double>::load(reinterpret_cast<const double*>(p.Qp + orow), q0);
-    }
-    double qn[2], un[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        qn[e] = fma(-ap[e], q0[e], w0[e]) * inv[e];
-        const double aq = fma(-ap[e], accq[e], accw[e]) * inv[e];  // (A q_k)_row
-        un[e] = fma(p.sA, aq, fma(p.sI, qn[e], -bp[e] * q0[e]));
-    }
-    Pack<double>::store_nt(reinterpret_cast<double*>(p.Qn + orow), qn);
-    Pack<double>::store_nt(reinterpret_cast<double*>(p.Wn + orow), un);
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        dd_fma_acc(s_qu[e], qn[e], un[e]);
-        dd_fma_acc(s_uu[e], un[e], un[e]);
-        dd_fma_acc(s_qq[e], qn[e], qn[e]);
-    }
+    if (!EARLY) Pack<double>::load(reinterpret_cast<const double*>(p.Zp + orow), z0);
+    double zn[2];
+    const double qn = fma(-ap, z0[1], z0[0]) * inv;
+    const double aq = fma(-ap, accq, accw) * inv;  // (A q_k)_row
+    zn[0] = fma(p.sA, aq, fma(p.sI, qn, -bp * z0[1]));
+    zn[1] = qn;
+    Pack<double>::store_nt(reinterpret_cast<double*>(p.Zn + orow), zn);
+    dd_fma_acc(s_qu, zn[1], zn[0]);
+    dd_fma_acc(s_uu, zn[0], zn[0]);
+    dd_fma_acc(s_qq, zn[1], zn[1]);
 }
 
 template <typename TA>
 __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
-    constexpr int kLdsDoubles = kWaves * 64 * 6 * 2;
+    constexpr int kLdsDoubles = kWaves * 64 * 6;
     __shared__ __align__(16) double smem[kLdsDoubles];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int rw = lane / p.lpr;
-    const int cg = lane - rw * p.lpr;
+    const int rw = lane / p.ld;
+    const int col = lane - rw * p.ld;
     const bool lane_on = rw < p.rpw;
     const TA* __restrict__ val = static_cast<const TA*>(p.val);
-    const uint32_t ldb = (uint32_t)p.ld * 8u;
-    const int coff = cg * 2;
-    const uint32_t coffb = (uint32_t)coff * 8u;
+    const uint32_t ldb = (uint32_t)p.ld * 16u;
+    const uint32_t coffb = (uint32_t)col * 16u;
     const int pass_rows = kWaves * p.rpw;
     const int nslots = kWaves * p.rpw;
 
-    double ap[2], inv[2], bp[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int c = lane_on ? coff + e : 0;
-        ap[e] = p.coef[c];
-        bp[e] = p.coef[p.ld + c];
-        inv[e] = bp[e] > 0.0 ? 1.0 / bp[e] : 0.0;
-    }
+    const int cc = lane_on ? col : 0;
+    const double ap = p.coef[cc];
+    const double bp = p.coef[p.ld + cc];
+    const double inv = bp > 0.0 ? 1.0 / bp : 0.0;
 
     const int nb = gridDim.x;
     int p_begin, p_end, p_stride, first;
@@ -194,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
         p_stride = nb;
     }
 
-    Dd s_qu[2] = {{0.0, 0.0}, {0.0, 0.0}}, s_uu[2] = {{0.0, 0.0}, {0.0, 0.0}}, s_qq[2] = {{0.0, 0.0}, {0.0, 0.0}};
+    Dd s_qu = {0.0, 0.0}, s_uu = {0.0, 0.0}, s_qq = {0.0, 0.0};
     for (int q = first; q < p_end; q += p_stride) {
         const int panel = p.reverse ? p_begin + p_end - 1 - q : q;
         const int r0 = panel * p.rows_per_block;
@@ -236,77 +216,85 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
     double* red = smem;
     if (lane_on) {
         const int slot = wave * p.rpw + rw;
+        const Dd v[3] = {s_qu, s_uu, s_qq};
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const Dd v[3] = {s_qu[e], s_uu[e], s_qq[e]};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                red[(slot * 6 + 2 * d) * p.ld + coff + e] = v[d].hi;
-                red[(slot * 6 + 2 * d + 1) * p.ld + coff + e] = v[d].lo;
-            }
+        for (int d = 0; d < 3; ++d) {
+            red[(slot * 6 + 2 * d) * p.ld + col] = v[d].hi;
+            red[(slot * 6 + 2 * d + 1) * p.ld + col] = v[d].lo;
         }
     }
     __syncthreads();
-    double* __restrict__ outp = p.partial + (int64_t)blockIdx.x * 6 * p.ld;
+    // layout [6][ld][grid]: the reduction reads each (quantity, column) row contiguously
+    const int nbk = gridDim.x;
     for (int t = threadIdx.x; t < 3 * p.ld; t += kThreads) {
         const int d = t / p.ld;
         const int c = t - d * p.ld;
         Dd s = {0.0, 0.0};
         for (int sl = 0; sl < nslots; ++sl)
             s = dd_add(s, Dd{red[(sl * 6 + 2 * d) * p.ld + c], red[(sl * 6 + 2 * d + 1) * p.ld + c]});
-        outp[(2 * d) * p.ld + c] = s.hi;
-        outp[(2 * d + 1) * p.ld + c] = s.lo;
+        p.partial[((int64_t)(2 * d) * p.ld + c) * nbk + blockIdx.x] = s.hi;
+        p.partial[((int64_t)(2 * d + 1) * p.ld + c) * nbk + blockIdx.x] = s.lo;
     }
 }
 
-// alpha_k, beta_k per column from the partial triples of step k (pairs):
-// workgroup x covers columns [64x, 64x+64); its 4 wavefronts add contiguous
-// quarters of the workgroup partials in pair arithmetic, combined in a fixed
-// order; beta_k^2 = u.u - 2 alpha q.u + alpha^2 q.q is evaluated in pairs.
+// alpha_k, beta_k of column blockIdx.x from the partial triples of step k
+// (pairs): each of the 256 threads adds a strided subset of the workgroup
+// partials in pair arithmetic, then a fixed tree combines them;
+// beta_k^2 = u.u - 2 alpha q.u + alpha^2 q.q is evaluated in pairs.
 __global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restrict__ partial, int nblocks, int ld,
                                                          double* __restrict__ coef_next) {
-    __shared__ double sh[3][2][4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = blockIdx.x * 64 + lane;
-    const int per = (nblocks + 3) / 4;
-    const int b0 = wave * per, b1 = min(nblocks, b0 + per);
+    __shared__ double sh[3][2][256];
+    const int t = threadIdx.x;
+    const int c = blockIdx.x;
     for (int kind = 0; kind < 3; ++kind) {
         Dd s = {0.0, 0.0};
-        if (c < ld)
-            for (int b = b0; b < b1; ++b)
-                s = dd_add(s, Dd{partial[((int64_t)b * 6 + 2 * kind) * ld + c],
-                                 partial[((int64_t)b * 6 + 2 * kind + 1) * ld + c]});
-        sh[kind][0][wave][lane] = s.hi;
-        sh[kind][1][wave][lane] = s.lo;
+        const double* __restrict__ ph = partial + ((int64_t)(2 * kind) * ld + c) * nblocks;
+        const double* __restrict__ pl = partial + ((int64_t)(2 * kind + 1) * ld + c) * nblocks;
+        for (int b = t; b < nblocks; b += 256) s = dd_add(s, Dd{ph[b], pl[b]});
+        sh[kind][0][t] = s.hi;
+        sh[kind][1][t] = s.lo;
     }
     __syncthreads();
-    if (wave == 0 && c < ld) {
-        Dd r[3];
-        for (int kind = 0; kind < 3; ++kind) {
-            r[kind] = {0.0, 0.0};
-            for (int w = 0; w < 4; ++w) r[kind] = dd_add(r[kind], Dd{sh[kind][0][w][lane], sh[kind][1][w][lane]});
-        }
-        const double alpha = r[0].hi + r[0].lo;
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st)
+            for (int kind = 0; kind < 3; ++kind) {
+                const Dd r = dd_add(Dd{sh[kind][0][t], sh[kind][1][t]}, Dd{sh[kind][0][t + st], sh[kind][1][t + st]});
+                sh[kind][0][t] = r.hi;
+                sh[kind][1][t] = r.lo;
+            }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const Dd qu = {sh[0][0][0], sh[0][1][0]}, uu = {sh[1][0][0], sh[1][1][0]}, qq = {sh[2][0][0], sh[2][1][0]};
+        const double alpha = qu.hi + qu.lo;
         // u.u - 2 alpha q.u + alpha^2 q.q
-        const Dd t1 = dd_mul_d(r[0], -2.0 * alpha);
-        const Dd t2 = dd_mul_d(dd_mul_d(r[2], alpha), alpha);
-        const Dd b2 = dd_add(dd_add(r[1], t1), t2);
+        const Dd t1 = dd_mul_d(qu, -2.0 * alpha);
+        const Dd t2 = dd_mul_d(dd_mul_d(qq, alpha), alpha);
+        const Dd b2 = dd_add(dd_add(uu, t1), t2);
         const double b2d = b2.hi + b2.lo;
         coef_next[c] = alpha;
         coef_next[ld + c] = sqrt(b2d > 0.0 ? b2d : 0.0);
     }
 }
 
-// coef0 = (alpha_{-1} = 0, beta_{-1} = ||v|| = sqrt(n)) for the ncols probe
-// columns, (0, 0) for padding columns; q_{-1} = 0.
-__global__ void slq_init_kernel(double* __restrict__ coef0, int ld, int ncols, double sqrt_n,
-                                double* __restrict__ Q, int64_t total) {
+// Z = (u_{-1}, q_{-1}) = (v, 0) for the ncols probe columns vec0.. of `seed`,
+// (0, 0) for padding columns; coef0 = (alpha_{-1} = 0, beta_{-1} = ||v|| =
+// sqrt(n)) for probe columns, (0, 0) for padding.
+__global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int ncols, int ld, int64_t n, double sqrt_n,
+                                double* __restrict__ Z, double* __restrict__ coef0) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 < ld) {
         coef0[i0] = 0.0;
         coef0[ld + i0] = i0 < ncols ? sqrt_n : 0.0;
     }
-    for (int64_t i = i0; i < total; i += (int64_t)gridDim.x * blockDim.x) Q[i] = 0.0;
+    const int64_t total = n * ld;
+    for (int64_t idx = i0; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / ld;
+        const int c = (int)(idx - i * ld);
+        const double v = c < ncols ? (double)rademacher_sign(seed, (uint64_t)(vec0 + c), (uint64_t)i) : 0.0;
+        Z[2 * idx] = v;
+        Z[2 * idx + 1] = 0.0;
+    }
 }
 
 // Eq. (landos): phi(x_i) = (1/nvec) sum over nodes of tau2 g_sigma(x_i - theta);
@@ -334,6 +322,24 @@ __global__ __launch_bounds__(256) void slq_dos_kernel(const double* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) phi[blockIdx.x] = sh[0] * norm / nvec;
+}
+
+// Probe-block geometry: one lane per probe column (ld = columns <= 64),
+// rpw = 64 / ld rows per wavefront, row panels of about 8 KB of (u, q) rows.
+constexpr int kSlqDefaultBlock = 32;
+struct SlqGeom {
+    int ld = 0, rpw = 0, rows_per_block = 0, nblocks = 0;
+};
+SlqGeom slq_geom(int64_t n, int ncols, int hint) {
+    SlqGeom g;
+    g.ld = ncols;
+    g.rpw = 64 / ncols;
+    const int rpp = kWaves * g.rpw;
+    int passes = hint > 0 ? (hint + rpp - 1) / rpp : (8192 / (16 * ncols) + rpp / 2) / rpp;
+    if (passes < 1) passes = 1;
+    g.rows_per_block = passes * rpp;
+    g.nblocks = (int)((n + g.rows_per_block - 1) / g.rows_per_block);
+    return g;
 }
 
 int slq_grid(bool f64vals, int npanels) {
@@ -459,7 +465,7 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
     if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
     if (o->precision != KPM_FP64)
         return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "the Lanczos method runs in FP64 (precision KPM_FP64)");
-    if (o->block < 0 || o->block > 128) return kpm_fail(ctx, KPM_ERR_ARG, "block out of range");
+    if (o->block < 0 || o->block > 64) return kpm_fail(ctx, KPM_ERR_ARG, "block out of range (<= 64)");
     if (o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
         return kpm_fail(ctx, KPM_ERR_ARG, "rows_per_block out of range");
     if (!(std::isfinite(lb) && std::isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
@@ -471,37 +477,34 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
 
     const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
     const int M = o->M, nvec = o->nvec;
-    int b = o->block > 0 ? std::min(o->block, nvec) : std::min(nvec, 64);
-    while (b > 1 && (uint64_t)A.n * ((b + 1) / 2 * 2) * 8 >= (1ull << 32)) b /= 2;
-    if ((uint64_t)A.n * ((b + 1) / 2 * 2) * 8 >= (1ull << 32))
+    int b = o->block > 0 ? std::min(o->block, nvec) : std::min(nvec, kSlqDefaultBlock);
+    while (b > 1 && (uint64_t)A.n * b * 16 >= (1ull << 32)) b /= 2;
+    if ((uint64_t)A.n * b * 16 >= (1ull << 32))
         return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "probe blocks of the Lanczos method must be smaller than 4 GiB");
-    const BlockGeom g = make_geom(A.n, b, KPM_FP64, o->rows_per_block);
+    const SlqGeom g = slq_geom(A.n, b, o->rows_per_block);
     const int grid = slq_grid(A.val_f64 != 0, g.nblocks);
-    const size_t vbytes = (size_t)A.n * g.ld * 8;
-    void *W0, *W1, *Q0, *Q1, *part, *coef;
-    if ((st = kpm_ws(ctx, "X0", vbytes, &W0)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "X1", vbytes, &W1)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "slq_Q0", vbytes, &Q0)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "slq_Q1", vbytes, &Q1)) != KPM_OK) return st;
+    const size_t zbytes = (size_t)A.n * g.ld * 16;
+    void *Z0, *Z1, *part, *coef;
+    if ((st = kpm_ws(ctx, "X0", zbytes, &Z0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X1", zbytes, &Z1)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "partial", (size_t)grid * 6 * g.ld * 8, &part)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "slq_coef", (size_t)(M + 1) * 2 * g.ld * 8, &coef)) != KPM_OK) return st;
 
     std::vector<double> hc((size_t)(M + 1) * 2 * g.ld);
     std::vector<double> al((size_t)nvec * M), be((size_t)nvec * M);
     const int nblk_vec = (nvec + b - 1) / b;
+    kpm_prof_begin(ctx, "slq_step");
     for (int blk = 0; blk < nblk_vec; ++blk) {
         const int ncols = std::min(b, nvec - blk * b);
-        const BlockGeom gb = ncols == b ? g : make_geom(A.n, ncols, KPM_FP64, o->rows_per_block);
+        const SlqGeom gb = ncols == b ? g : slq_geom(A.n, ncols, o->rows_per_block);
         const int gridb = ncols == b ? grid : slq_grid(A.val_f64 != 0, gb.nblocks);
         const int64_t vec0 = (int64_t)blk * b;
-        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, KPM_FP64, 1, W0));
         const int64_t total = (int64_t)A.n * gb.ld;
         const int ib = (int)std::min<int64_t>(4096, (total + 255) / 256);
-        slq_init_kernel<<<std::max(ib, 1), 256, 0, ctx->stream>>>((double*)coef, gb.ld, ncols, sqrt((double)A.n),
-                                                                   (double*)Q0, total);
+        slq_init_kernel<<<std::max(ib, 1), 256, 0, ctx->stream>>>(o->seed, vec0, ncols, gb.ld, A.n,
+                                                                   sqrt((double)A.n), (double*)Z0, (double*)coef);
         KPM_HIP(ctx, hipGetLastError());
-        char* W[2] = {(char*)W0, (char*)W1};
-        char* Q[2] = {(char*)Q0, (char*)Q1};
+        char* Z[2] = {(char*)Z0, (char*)Z1};
         SlqParams p;
         p.rp = A.rp;
         p.ci = A.ci;
@@ -511,37 +514,34 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
         p.sI = -c / d;
         p.n = A.n;
         p.ld = gb.ld;
-        p.lpr = gb.lpr;
         p.rpw = gb.rpw;
         p.rows_per_block = gb.rows_per_block;
         p.npanels = gb.nblocks;
         p.stage = 1;
-        kpm_prof_begin(ctx, "slq_step");
         for (int k = 0; k < M; ++k) {
-            p.Wp = W[k & 1];
-            p.Qp = Q[k & 1];
-            p.Wn = W[(k + 1) & 1];
-            p.Qn = Q[(k + 1) & 1];
+            p.Zp = Z[k & 1];
+            p.Zn = Z[(k + 1) & 1];
             p.coef = (const double*)coef + (size_t)k * 2 * gb.ld;
             p.reverse = k & 1;  // start on the rows the previous step ended with
             if (A.val_f64) slq_step_kernel<double><<<gridb, kThreads, 0, ctx->stream>>>(p);
             else slq_step_kernel<float><<<gridb, kThreads, 0, ctx->stream>>>(p);
             KPM_HIP(ctx, hipGetLastError());
-            slq_reduce_kernel<<<(gb.ld + 63) / 64, 256, 0, ctx->stream>>>(
+            slq_reduce_kernel<<<gb.ld, 256, 0, ctx->stream>>>(
                 (double*)part, gridb, gb.ld, (double*)coef + (size_t)(k + 1) * 2 * gb.ld);
             KPM_HIP(ctx, hipGetLastError());
         }
-        kpm_prof_end(ctx, "slq_step", M);
         KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, (size_t)(M + 1) * 2 * gb.ld * 8, hipMemcpyDeviceToHost,
                                     ctx->stream));
         KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        kpm_prof_collect(ctx);
         for (int col = 0; col < ncols; ++col)
             for (int k = 0; k < M; ++k) {
                 al[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + col];
                 be[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + gb.ld + col];
             }
     }
+    kpm_prof_end(ctx, "slq_step", M * nblk_vec);
+    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    kpm_prof_collect(ctx);
     if (alpha_out) memcpy(alpha_out, al.data(), al.size() * 8);
     if (beta_out) memcpy(beta_out, be.data(), be.size() * 8);
     // Per probe: breakdown rule, nodes and weights, Ritz values in A's units.

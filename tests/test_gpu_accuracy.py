@@ -1,5 +1,6 @@
 """Equal-accuracy comparison on the 64^3 Anderson workload: FP32 moments +
-learned damping against FP64 moments + Jackson damping (Appendix A).
+learned damping against FP64 moments + Jackson damping (Appendix A), and
+the stochastic Lanczos method (section 3.2.1) on the same probes.
 
 Error metric: L1 distance (eq. (err2), p = 1) on 200 midpoints of [-1, 1]
 between Gaussian-blurred densities (sigma = 0.02 in the scaled variable, as
@@ -32,6 +33,7 @@ pytestmark = pytest.mark.gpu
 SIGMA = 0.02
 TRUNC = (15, 23, 31, 47, 63, 95, 127)
 DEGREES = (16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 127)
+SLQ_STEPS = (40, 50, 60, 65, 70, 80, 100)
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -121,12 +123,24 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx):
              % (r["M"], r["fp64_jackson"], r["fp32_learned"], r["fp32_none"], r["fp32_jackson"]))
     M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
     M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
+
+    # Stochastic Lanczos method (section 3.2.1), same probes, FP64 recurrence:
+    # M Lanczos steps = M sparse products per probe (KPM of degree M uses M/2).
+    slq_rows = []
+    for Ms in SLQ_STEPS:
+        th, t2, _ = kpm.kpm_slq(ctx, D32, lb, ub, Ms, 64, 2002)
+        phi = oracle.lanczos_dos((th - c) / d, t2, t, SIGMA)
+        assert np.all(phi >= 0.0)
+        slq_rows.append(dict(M=Ms, slq_fp64=oracle.l1_error(ref, phi)))
+        _say("Lanczos steps=%3d  L1 %.4f" % (Ms, slq_rows[-1]["slq_fp64"]))
+    M_S = min(r["M"] for r in slq_rows if r["slq_fp64"] <= 1e-2)
     summary = dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L,
+                   slq_rows=slq_rows, M_slq_fp64=M_S,
                    train_loss_first=float(losses[0]), train_loss_last=float(losses[-1]))
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
     with open(os.path.join(ROOT, "gpurun_out", "accuracy_study.json"), "w") as f:
         json.dump(summary, f, indent=1)
-    _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}")
+    _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}; Lanczos steps {M_S}")
     assert M_L < M_J
     # the network must not be worse than Jackson at the same degree and precision
     for r in rows:
