@@ -56,6 +56,8 @@ def parse():
                     help="only run the streaming-copy bandwidth probe (counter calibration)")
     ap.add_argument("--slq-only", action="store_true",
                     help="only run the stochastic Lanczos leg on the workload (profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 48-matrix batched leg (profiling)")
     ap.add_argument("--cpu-sample-vectors", type=int, default=0,
                     help="probes in the oracle sample (0 = all cores' worth)")
     return ap.parse_args()
@@ -69,6 +71,11 @@ def main():
     import torch
     import paper_1308_5467_amd as kpm
     import synth
+
+    if args.batched_only:
+        ctx = kpm.Context(0)
+        print(json.dumps({"batched_uneven_48": batched_leg(kpm, ctx, synth)}))
+        return
 
     if args.copy_probe_only:
         ctx = kpm.Context(0)

@@ -5,12 +5,14 @@
 // Work decomposition.  Every (matrix, probe block) pair -- an "mv" -- has
 // its own ping-pong vector blocks.  One launch per recurrence step covers
 // every mv of every matrix: a host-built work table gives each workgroup a
-// contiguous range of row panels of one mv, the number of workgroups per mv
+// share of the row panels of one mv, the number of workgroups per mv
 // proportional to its bytes of work and the total close to the number of
 // workgroups resident on the device, so small matrices never leave the GPU
 // idle and each workgroup writes exactly one dot partial per step.
-// Workgroup b reads table entry xcd_panel(b): consecutive entries (adjacent
-// panels of one matrix) run on the same XCD and share its L2.
+// Workgroup b reads table entry xcd_panel(b), so consecutive entries run on
+// the same XCD; the entries of one mv on one XCD share a contiguous panel
+// range and stride through it together (one moving band of rows per mv and
+// XCD, whose plane-apart gathers stay in that XCD's L2).
 //
 // Steps are separate launches rather than one kernel with device-wide
 // barriers between steps: on MI355X a device-scope release/acquire writes
@@ -32,8 +34,10 @@
 
 namespace kpm {
 
-struct BatchEntryDev {  // one workgroup: row panels [p0, p1) of mv
-    int32_t mv, p0, p1, pad;
+// One workgroup: panels first, first + stride, ... < end of mv, one of the
+// `stride` workgroups that share the panel range [base, end) on one XCD.
+struct BatchEntryDev {
+    int32_t mv, first, end, stride, base, pad0, pad1, pad2;
 };
 
 struct BatchMvDev {  // one (matrix, probe block)
@@ -70,10 +74,12 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
     double sx[N], ss[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) sx[i] = ss[i] = 0.0;
-    // Odd steps walk the entry's panels backwards, starting on the rows the
-    // previous step ended with (still in this XCD's L2).
-    for (int q = E.p0; q < E.p1; ++q) {
-        const int panel = parity ? E.p0 + E.p1 - 1 - q : q;
+    // The workgroups sharing a range stride through it together, so the rows
+    // they work on at a time form one band and the gathered rows a few
+    // planes away stay in the XCD's L2.  Odd steps walk the range backwards,
+    // starting on the rows the previous step ended with.
+    for (int q = E.first; q < E.end; q += E.stride) {
+        const int panel = parity ? E.base + E.end - 1 - q : q;
         const int r0 = panel * rows_per_panel;
         const int r1 = min(mv.n, r0 + rows_per_panel);
         process_panel<TA, TV, FIRST, true, G>(r0, r1, mv.rp, mv.ci, val, Vb, Ub, ldb, coffb, mv.alpha, mv.beta,
@@ -374,22 +380,52 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
                 work[m * nvb + vb] = w;
                 wsum += w;
             }
+        // Workgroup b runs entry xcd_panel(b, nentries): XCD x runs the x-th
+        // contiguous run of entries.  The entries of one mv that fall on one
+        // XCD share a contiguous panel range (its share in proportion) and
+        // stride through it.
+        int64_t total_entries = 0;
+        std::vector<int> gws(P.nmv);
+        for (int m = 0; m < nmat; ++m)
+            for (int vb = 0; vb < nvb; ++vb) {
+                const int mv = m * nvb + vb;
+                const int panels = (int)((D[m].n + P.rows - 1) / P.rows);
+                int gw = (int)std::lround(target * work[mv] / wsum);
+                gws[mv] = std::max(1, std::min(gw, panels));
+                total_entries += gws[mv];
+            }
+        const int nb = (int)total_entries;
+        auto xcd_of = [&](int e) {  // XCD that runs entry e (inverse of xcd_panel)
+            if (nb < 8) return e;
+            const int q = nb / 8, r = nb % 8;
+            int x = 0;
+            while (x < 7 && e >= (x + 1) * q + std::min(x + 1, r)) ++x;
+            return x;
+        };
         std::vector<BatchEntryDev> entries;
         std::vector<int32_t> e0(P.nmv), e1(P.nmv);
         for (int m = 0; m < nmat; ++m)
             for (int vb = 0; vb < nvb; ++vb) {
                 const int mv = m * nvb + vb;
                 const int panels = (int)((D[m].n + P.rows - 1) / P.rows);
-                int gw = (int)std::lround(target * work[mv] / wsum);
-                gw = std::max(1, std::min(gw, panels));
-                e0[mv] = (int32_t)entries.size();
-                for (int i = 0; i < gw; ++i) {
-                    BatchEntryDev e;
-                    e.mv = mv;
-                    e.p0 = (int32_t)((int64_t)panels * i / gw);
-                    e.p1 = (int32_t)((int64_t)panels * (i + 1) / gw);
-                    e.pad = 0;
-                    entries.push_back(e);
+                const int gw = gws[mv];
+                const int a0 = (int)entries.size();
+                e0[mv] = a0;
+                int i = 0;
+                while (i < gw) {  // runs of consecutive entries on one XCD
+                    int j = i + 1;
+                    while (j < gw && xcd_of(a0 + j) == xcd_of(a0 + i)) ++j;
+                    const int P0 = (int)((int64_t)panels * i / gw), P1 = (int)((int64_t)panels * j / gw);
+                    for (int u = i; u < j; ++u) {
+                        BatchEntryDev e = {};
+                        e.mv = mv;
+                        e.first = P0 + (u - i);
+                        e.end = P1;
+                        e.stride = j - i;
+                        e.base = P0;
+                        entries.push_back(e);
+                    }
+                    i = j;
                 }
                 e1[mv] = (int32_t)entries.size();
             }

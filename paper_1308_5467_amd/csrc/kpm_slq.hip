@@ -7,10 +7,12 @@
 // conditions the arithmetic (Lanczos is shift- and scale-invariant); Ritz
 // values are returned in A's units.
 //
-// Device part: a block of b probes runs the plain three-term recurrence
-// (no re-orthogonalisation) one sparse product per step, on the same
-// row-major [n x ld] probe-block layout, LDS-staged CSR panels and
-// XCD-aware resident grid as the Chebyshev step.  Step k reads
+// Device part: a block of b <= 64 probes runs the plain three-term
+// recurrence (no re-orthogonalisation), one sparse product per step, with
+// the same LDS-staged CSR panels and XCD-aware resident grid as the
+// Chebyshev step.  The state of a row is stored as interleaved pairs
+// (u_{k-1}, q_{k-1}) per probe, [n][b][2] FP64, one lane per probe column,
+// so a gathered neighbour is one 16-byte load.  Step k reads
 // u_{k-1} = B q_{k-1} - beta_{k-2} q_{k-2} and q_{k-1} and forms, per row,
 //   q_k     = (u_{k-1} - alpha_{k-1} q_{k-1}) / beta_{k-1}
 //   u_k     = B q_k - beta_{k-1} q_{k-1}
@@ -49,10 +51,7 @@ namespace kpm {
 
 namespace {
 
-#ifndef KPM_SLQ_G
-#define KPM_SLQ_G 4
-#endif
-constexpr int kSlqG = KPM_SLQ_G;  // gathers per batch (two gathered blocks per entry)
+constexpr int kSlqG = 4;  // gathers per batch (8 measured within 1 %, at more registers)
 
 // Pair ("double-double") arithmetic: a value is hi + lo with |lo| <= ulp(hi)/2.
 struct Dd {
