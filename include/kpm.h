@@ -224,7 +224,8 @@ kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, 
  *           beta[l*M+k] = ||r_k|| (coupling of q_k and q_{k+1}; the last one
  *           is ||f_M||).
  * opts: M = Lanczos steps in [1, 4096], nvec, block (probes per device
- * block, 0 = min(nvec, 32), <= 64), seed, validate, rows_per_block;
+ * block, 0 = min(nvec, 16), <= 64; up to 8 blocks run concurrently, one
+ * group of XCDs each), seed, validate, rows_per_block;
  * precision must be KPM_FP64
  * (KPM_ERR_UNSUPPORTED otherwise).  FP32 or FP64 matrix values.
  */

@@ -85,13 +85,31 @@ struct SlqParams {
     const int32_t* rp;
     const int32_t* ci;
     const void* val;
-    const char* Zp;        // (u_{k-1}, q_{k-1}) pairs, [n][ld][2]
+    const char* Zp;        // (u_{k-1}, q_{k-1}) pairs, [S][n][ld][2]
     char* Zn;              // (u_k, q_k) pairs
-    const double* coef;    // [2][ld]: alpha_{k-1}, beta_{k-1}
-    double* partial;       // [6][ld][grid]: q.u, u.u, q.q per workgroup as (hi, lo) pairs
+    const double* coef;    // slice s at coef + s * coef_stride: [2][ld] alpha_{k-1}, beta_{k-1}
+    double* partial;       // [S][6][ld][pstride]: q.u, u.u, q.q per workgroup as (hi, lo) pairs
     double sA, sI;         // B = sA A + sI I
+    int64_t zstride;       // bytes between the slices' (u, q) blocks
+    int64_t coef_stride;   // doubles between the slices' coefficient tables
     int32_t n, ld, rpw, rows_per_block, npanels, stage, reverse;
+    int32_t slices, pstride;
 };
+
+// Slices: S probe blocks run in one launch, block s on the XCDs
+// [s * 8/S, (s+1) * 8/S) (hardware round-robin: workgroup b runs on XCD
+// b % 8).  Workgroups of one slice are numbered densely, XCD by XCD.
+__device__ __forceinline__ void slq_slice_of(int b, int nb, int S, int& slice, int& xg, int& li, int& local,
+                                             int& nlocal) {
+    const int x = b & 7, q = nb >> 3, r = nb & 7, gsz = 8 / S;
+    slice = x / gsz;
+    xg = x - slice * gsz;
+    li = b >> 3;
+    const int x0 = slice * gsz;
+    // workgroups on XCDs x0 .. x-1 of this slice, then on the whole slice
+    local = (x - x0) * q + max(0, min(x, r) - min(x0, r)) + li;
+    nlocal = gsz * q + max(0, min(x0 + gsz, r) - min(x0, r));
+}
 
 // One matrix row for one lane (one probe column).  The state of a row is
 // stored as (u, q) pairs, so a gathered neighbour is one 16-byte load.
@@ -153,25 +171,32 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
     const int pass_rows = kWaves * p.rpw;
     const int nslots = kWaves * p.rpw;
 
-    const int cc = lane_on ? col : 0;
-    const double ap = p.coef[cc];
-    const double bp = p.coef[p.ld + cc];
-    const double inv = bp > 0.0 ? 1.0 / bp : 0.0;
-
     const int nb = gridDim.x;
-    int p_begin, p_end, p_stride, first;
+    int slice = 0, p_begin, p_end, p_stride, first, local = blockIdx.x;
     if (nb >= 8) {
-        const int x = blockIdx.x & 7, li = blockIdx.x >> 3;
-        p_begin = (int)((int64_t)p.npanels * x / 8);
-        p_end = (int)((int64_t)p.npanels * (x + 1) / 8);
+        int xg, li, nlocal;
+        slq_slice_of(blockIdx.x, nb, p.slices, slice, xg, li, local, nlocal);
+        const int gsz = 8 / p.slices;
+        const int x = blockIdx.x & 7;
+        p_begin = (int)((int64_t)p.npanels * xg / gsz);
+        p_end = (int)((int64_t)p.npanels * (xg + 1) / gsz);
         first = p_begin + li;
         p_stride = nb / 8 + (x < (nb & 7) ? 1 : 0);
-    } else {
+    } else {  // one slice only (the host never splits a grid this small)
         p_begin = 0;
         p_end = p.npanels;
         first = blockIdx.x;
         p_stride = nb;
     }
+    SlqParams ps = p;  // this slice's blocks
+    ps.Zp = p.Zp + slice * p.zstride;
+    ps.Zn = p.Zn + slice * p.zstride;
+    const double* coef = p.coef + slice * p.coef_stride;
+
+    const int cc = lane_on ? col : 0;
+    const double ap = coef[cc];
+    const double bp = coef[p.ld + cc];
+    const double inv = bp > 0.0 ? 1.0 / bp : 0.0;
 
     Dd s_qu = {0.0, 0.0}, s_uu = {0.0, 0.0}, s_qq = {0.0, 0.0};
     for (int q = first; q < p_end; q += p_stride) {
@@ -197,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
                 const CsrPairs<TA> csr{s_e};
                 for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows) {
                     const int lr = row - r0;
-                    slq_row<TA, true, kSlqG>(row, s_rp[lr], s_rp[lr + 1], csr, p, ldb, coffb, ap, inv, bp, s_qu,
+                    slq_row<TA, true, kSlqG>(row, s_rp[lr], s_rp[lr + 1], csr, ps, ldb, coffb, ap, inv, bp, s_qu,
                                              s_uu, s_qq);
                 }
             }
@@ -205,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
         } else if (lane_on) {
             const CsrArrays<TA> csr{p.ci, val};
             for (int row = r0 + wave * p.rpw + rw; row < r1; row += pass_rows)
-                slq_row<TA, false, kSlqG>(row, p.rp[row], p.rp[row + 1], csr, p, ldb, coffb, ap, inv, bp, s_qu,
+                slq_row<TA, false, kSlqG>(row, p.rp[row], p.rp[row + 1], csr, ps, ldb, coffb, ap, inv, bp, s_qu,
                                           s_uu, s_qq);
         }
     }
@@ -223,16 +248,17 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
         }
     }
     __syncthreads();
-    // layout [6][ld][grid]: the reduction reads each (quantity, column) row contiguously
-    const int nbk = gridDim.x;
+    // layout [S][6][ld][pstride], entry `local` of this slice: the reduction
+    // reads each (quantity, column) row contiguously
+    double* __restrict__ part = p.partial + (int64_t)slice * 6 * p.ld * p.pstride;
     for (int t = threadIdx.x; t < 3 * p.ld; t += kThreads) {
         const int d = t / p.ld;
         const int c = t - d * p.ld;
         Dd s = {0.0, 0.0};
         for (int sl = 0; sl < nslots; ++sl)
             s = dd_add(s, Dd{red[(sl * 6 + 2 * d) * p.ld + c], red[(sl * 6 + 2 * d + 1) * p.ld + c]});
-        p.partial[((int64_t)(2 * d) * p.ld + c) * nbk + blockIdx.x] = s.hi;
-        p.partial[((int64_t)(2 * d + 1) * p.ld + c) * nbk + blockIdx.x] = s.lo;
+        part[((int64_t)(2 * d) * p.ld + c) * p.pstride + local] = s.hi;
+        part[((int64_t)(2 * d + 1) * p.ld + c) * p.pstride + local] = s.lo;
     }
 }
 
@@ -240,15 +266,24 @@ __global__ __launch_bounds__(kThreads) void slq_step_kernel(SlqParams p) {
 // (pairs): each of the 256 threads adds a strided subset of the workgroup
 // partials in pair arithmetic, then a fixed tree combines them;
 // beta_k^2 = u.u - 2 alpha q.u + alpha^2 q.q is evaluated in pairs.
-__global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restrict__ partial, int nblocks, int ld,
-                                                         double* __restrict__ coef_next) {
+__global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restrict__ partial_all, int nb, int S,
+                                                         int pstride, int ld, double* __restrict__ coef_next_all,
+                                                         int64_t coef_stride) {
     __shared__ double sh[3][2][256];
     const int t = threadIdx.x;
     const int c = blockIdx.x;
+    const int slice = blockIdx.y;
+    int nblocks = nb;
+    if (nb >= 8) {  // workgroups of this slice (same count as slq_slice_of)
+        const int q = nb >> 3, r = nb & 7, gsz = 8 / S, x0 = slice * gsz;
+        nblocks = gsz * q + max(0, min(x0 + gsz, r) - min(x0, r));
+    }
+    const double* __restrict__ partial = partial_all + (int64_t)slice * 6 * ld * pstride;
+    double* __restrict__ coef_next = coef_next_all + slice * coef_stride;
     for (int kind = 0; kind < 3; ++kind) {
         Dd s = {0.0, 0.0};
-        const double* __restrict__ ph = partial + ((int64_t)(2 * kind) * ld + c) * nblocks;
-        const double* __restrict__ pl = partial + ((int64_t)(2 * kind + 1) * ld + c) * nblocks;
+        const double* __restrict__ ph = partial + ((int64_t)(2 * kind) * ld + c) * pstride;
+        const double* __restrict__ pl = partial + ((int64_t)(2 * kind + 1) * ld + c) * pstride;
         for (int b = t; b < nblocks; b += 256) s = dd_add(s, Dd{ph[b], pl[b]});
         sh[kind][0][t] = s.hi;
         sh[kind][1][t] = s.lo;
@@ -276,11 +311,18 @@ __global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restric
     }
 }
 
-// Z = (u_{-1}, q_{-1}) = (v, 0) for the ncols probe columns vec0.. of `seed`,
-// (0, 0) for padding columns; coef0 = (alpha_{-1} = 0, beta_{-1} = ||v|| =
-// sqrt(n)) for probe columns, (0, 0) for padding.
-__global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int ncols, int ld, int64_t n, double sqrt_n,
-                                double* __restrict__ Z, double* __restrict__ coef0) {
+// Slice s = blockIdx.y of a group: Z_s = (u_{-1}, q_{-1}) = (v, 0) for its
+// probe columns vec0_s .. (vec0_s = vec0 + s * ld, ncols_s of them), (0, 0)
+// for padding columns; coef_s = (alpha_{-1} = 0, beta_{-1} = ||v|| = sqrt(n))
+// for probe columns, (0, 0) for padding.
+__global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int nvec_left, int ld, int64_t n, double sqrt_n,
+                                double* __restrict__ Zall, int64_t zstride_d, double* __restrict__ coef_all,
+                                int64_t coef_stride) {
+    const int s = blockIdx.y;
+    const int64_t v0 = vec0 + (int64_t)s * ld;
+    const int ncols = (int)min<int64_t>(ld, max<int64_t>(0, nvec_left - (int64_t)s * ld));
+    double* __restrict__ Z = Zall + s * zstride_d;
+    double* __restrict__ coef0 = coef_all + s * coef_stride;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i0 < ld) {
         coef0[i0] = 0.0;
@@ -290,7 +332,7 @@ __global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int ncols, int ld, 
     for (int64_t idx = i0; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / ld;
         const int c = (int)(idx - i * ld);
-        const double v = c < ncols ? (double)rademacher_sign(seed, (uint64_t)(vec0 + c), (uint64_t)i) : 0.0;
+        const double v = c < ncols ? (double)rademacher_sign(seed, (uint64_t)(v0 + c), (uint64_t)i) : 0.0;
         Z[2 * idx] = v;
         Z[2 * idx + 1] = 0.0;
     }
@@ -325,7 +367,7 @@ __global__ __launch_bounds__(256) void slq_dos_kernel(const double* __restrict__
 
 // Probe-block geometry: one lane per probe column (ld = columns <= 64),
 // rpw = 64 / ld rows per wavefront, row panels of about 8 KB of (u, q) rows.
-constexpr int kSlqDefaultBlock = 32;
+constexpr int kSlqDefaultBlock = 16;
 struct SlqGeom {
     int ld = 0, rpw = 0, rows_per_block = 0, nblocks = 0;
 };
@@ -482,26 +524,37 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
         return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "probe blocks of the Lanczos method must be smaller than 4 GiB");
     const SlqGeom g = slq_geom(A.n, b, o->rows_per_block);
     const int grid = slq_grid(A.val_f64 != 0, g.nblocks);
+    const int nblk_vec = (nvec + b - 1) / b;
+    // Slices per launch: up to 8 probe blocks at once, one group of XCDs each
+    // (a grid of at least 8 workgroups and 64 panels per XCD of a slice).
+    int Smax = 1;
+    while (Smax < 8 && Smax * 2 <= nblk_vec && grid >= 8 && g.nblocks >= 64 * Smax * 2 &&
+           (uint64_t)A.n * g.ld * 16 * (Smax * 2) <= (32ull << 30))
+        Smax *= 2;
     const size_t zbytes = (size_t)A.n * g.ld * 16;
     void *Z0, *Z1, *part, *coef;
-    if ((st = kpm_ws(ctx, "X0", zbytes, &Z0)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "X1", zbytes, &Z1)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "partial", (size_t)grid * 6 * g.ld * 8, &part)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "slq_coef", (size_t)(M + 1) * 2 * g.ld * 8, &coef)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X0", zbytes * Smax, &Z0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X1", zbytes * Smax, &Z1)) != KPM_OK) return st;
+    // S * pstride <= 8 * (grid / 8 + 1) for every S
+    const int pmax = grid >= 8 ? 8 * (grid / 8 + 1) : grid;
+    if ((st = kpm_ws(ctx, "partial", (size_t)6 * g.ld * pmax * 8, &part)) != KPM_OK) return st;
+    const int64_t cstride = (int64_t)(M + 1) * 2 * g.ld;
+    if ((st = kpm_ws(ctx, "slq_coef", (size_t)Smax * cstride * 8, &coef)) != KPM_OK) return st;
 
-    std::vector<double> hc((size_t)(M + 1) * 2 * g.ld);
+    std::vector<double> hc((size_t)Smax * cstride);
     std::vector<double> al((size_t)nvec * M), be((size_t)nvec * M);
-    const int nblk_vec = (nvec + b - 1) / b;
     kpm_prof_begin(ctx, "slq_step");
-    for (int blk = 0; blk < nblk_vec; ++blk) {
-        const int ncols = std::min(b, nvec - blk * b);
-        const SlqGeom gb = ncols == b ? g : slq_geom(A.n, ncols, o->rows_per_block);
-        const int gridb = ncols == b ? grid : slq_grid(A.val_f64 != 0, gb.nblocks);
+    int launches = 0;
+    for (int blk = 0; blk < nblk_vec;) {
+        int S = Smax;
+        while (S > nblk_vec - blk) S /= 2;
+        const int ps = grid >= 8 ? (8 / S) * (grid / 8 + 1) : grid;
         const int64_t vec0 = (int64_t)blk * b;
-        const int64_t total = (int64_t)A.n * gb.ld;
+        const int64_t total = (int64_t)A.n * g.ld;
         const int ib = (int)std::min<int64_t>(4096, (total + 255) / 256);
-        slq_init_kernel<<<std::max(ib, 1), 256, 0, ctx->stream>>>(o->seed, vec0, ncols, gb.ld, A.n,
-                                                                   sqrt((double)A.n), (double*)Z0, (double*)coef);
+        slq_init_kernel<<<dim3(std::max(ib, 1), S), 256, 0, ctx->stream>>>(
+            o->seed, vec0, (int)(nvec - vec0), g.ld, A.n, sqrt((double)A.n), (double*)Z0, (int64_t)(zbytes / 8),
+            (double*)coef, cstride);
         KPM_HIP(ctx, hipGetLastError());
         char* Z[2] = {(char*)Z0, (char*)Z1};
         SlqParams p;
@@ -511,34 +564,44 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
         p.partial = (double*)part;
         p.sA = 1.0 / d;
         p.sI = -c / d;
+        p.zstride = (int64_t)zbytes;
+        p.coef_stride = cstride;
         p.n = A.n;
-        p.ld = gb.ld;
-        p.rpw = gb.rpw;
-        p.rows_per_block = gb.rows_per_block;
-        p.npanels = gb.nblocks;
+        p.ld = g.ld;
+        p.rpw = g.rpw;
+        p.rows_per_block = g.rows_per_block;
+        p.npanels = g.nblocks;
         p.stage = 1;
+        p.slices = S;
+        p.pstride = ps;
         for (int k = 0; k < M; ++k) {
             p.Zp = Z[k & 1];
             p.Zn = Z[(k + 1) & 1];
-            p.coef = (const double*)coef + (size_t)k * 2 * gb.ld;
+            p.coef = (const double*)coef + (size_t)k * 2 * g.ld;
             p.reverse = k & 1;  // start on the rows the previous step ended with
-            if (A.val_f64) slq_step_kernel<double><<<gridb, kThreads, 0, ctx->stream>>>(p);
-            else slq_step_kernel<float><<<gridb, kThreads, 0, ctx->stream>>>(p);
+            if (A.val_f64) slq_step_kernel<double><<<grid, kThreads, 0, ctx->stream>>>(p);
+            else slq_step_kernel<float><<<grid, kThreads, 0, ctx->stream>>>(p);
             KPM_HIP(ctx, hipGetLastError());
-            slq_reduce_kernel<<<gb.ld, 256, 0, ctx->stream>>>(
-                (double*)part, gridb, gb.ld, (double*)coef + (size_t)(k + 1) * 2 * gb.ld);
+            slq_reduce_kernel<<<dim3(g.ld, S), 256, 0, ctx->stream>>>(
+                (double*)part, grid, S, ps, g.ld, (double*)coef + (size_t)(k + 1) * 2 * g.ld, cstride);
             KPM_HIP(ctx, hipGetLastError());
+            ++launches;
         }
-        KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, (size_t)(M + 1) * 2 * gb.ld * 8, hipMemcpyDeviceToHost,
-                                    ctx->stream));
+        KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, (size_t)S * cstride * 8, hipMemcpyDeviceToHost, ctx->stream));
         KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        for (int col = 0; col < ncols; ++col)
-            for (int k = 0; k < M; ++k) {
-                al[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + col];
-                be[(size_t)(vec0 + col) * M + k] = hc[(size_t)(k + 1) * 2 * gb.ld + gb.ld + col];
-            }
+        for (int sl = 0; sl < S; ++sl) {
+            const int64_t v0 = vec0 + (int64_t)sl * b;
+            const int ncols = (int)std::min<int64_t>(b, nvec - v0);
+            const double* h = hc.data() + (size_t)sl * cstride;
+            for (int col = 0; col < ncols; ++col)
+                for (int k = 0; k < M; ++k) {
+                    al[(size_t)(v0 + col) * M + k] = h[(size_t)(k + 1) * 2 * g.ld + col];
+                    be[(size_t)(v0 + col) * M + k] = h[(size_t)(k + 1) * 2 * g.ld + g.ld + col];
+                }
+        }
+        blk += S;
     }
-    kpm_prof_end(ctx, "slq_step", M * nblk_vec);
+    kpm_prof_end(ctx, "slq_step", launches);
     KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     kpm_prof_collect(ctx);
     if (alpha_out) memcpy(alpha_out, al.data(), al.size() * 8);
