@@ -85,8 +85,13 @@ typedef struct {
 } kpm_moment_opts;
 
 enum {
-    KPM_FLAG_NO_GRAPH = 1 /* kpm_moments_batched: launch directly instead of
-                             replaying the captured HIP graph                */
+    KPM_FLAG_NO_GRAPH = 1, /* kpm_moments_batched: launch directly instead of
+                              replaying the captured HIP graph                */
+    KPM_FLAG_GATHER4 = 2,  /* kpm_moments: gather a row's CSR entries in
+                              batches of 4 instead of 8 (fewer registers,
+                              one more memory round trip for rows of 5-8)     */
+    KPM_FLAG_GATHER8 = 4   /* kpm_moments: batches of 8 (overrides the
+                              KPM_TUNE environment default)                  */
 };
 
 typedef enum {
@@ -143,6 +148,24 @@ kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
                        const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
 
 /*
+ * kpm_autotune -- choose the device geometry of kpm_moments for A by
+ * measurement: for each candidate probe-block width (opts->block if set,
+ * else 32/64/128 for KPM_FP32, 16/32/64 for KPM_FP64, capped at nvec), row
+ * panel height (opts->rows_per_block if set, else the library's choice and
+ * half and twice it) and gather batch (4 or 8 CSR entries), time 6 fused
+ * recurrence steps (section 3.1.1, eq. (3term)) on the context's stream and
+ * keep the fastest per probe.  *best = *opts with block, rows_per_block and
+ * the KPM_FLAG_GATHER4 / KPM_FLAG_GATHER8 bit set to the winner (pass it to
+ * kpm_moments; results depend on the geometry only through rounding, and are
+ * bitwise reproducible for a fixed geometry).  *us_per_step (nullable): the
+ * winner's time per recurrence step for all nvec probes, in microseconds.
+ * The choice is a measurement: repeated calls may pick different winners
+ * among near-equal candidates.
+ */
+kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub, const kpm_moment_opts* opts,
+                        kpm_moment_opts* best, double* us_per_step);
+
+/*
  * kpm_moments_robust -- bounds and moments with escape recovery.  The
  * Lanczos bound of kpm_bounds can miss an extreme eigenvalue whose
  * eigenvector barely overlaps the start vector (e.g. localised edge states
@@ -177,6 +200,21 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
 kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
                                const double* ub, const kpm_moment_opts* opts, double* mu,
                                double* max_abs_mu);
+
+/*
+ * kpm_autotune_batched -- the same measurement for kpm_moments_batched: for
+ * each candidate probe-block width (opts->block if set, else 16/32/64 for
+ * KPM_FP32, 8/16/32 for KPM_FP64, capped at nvec) and row-panel height
+ * (opts->rows_per_block if set, else the library's choice for the largest
+ * matrix and half and twice it), build and capture the plan, then take the
+ * device time of the batched launch sequence at degrees 15 and 47 (best of
+ * two each) and divide the difference by the 16 extra steps.  *best = *opts with block and rows_per_block of the fastest
+ * per probe; *us_per_step (nullable): its time per step for all nvec probes
+ * of all matrices, in microseconds.  Leaves the last candidate's plan
+ * cached (the next call with *best builds its own).
+ */
+kpm_status kpm_autotune_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb, const double* ub,
+                                const kpm_moment_opts* opts, kpm_moment_opts* best, double* us_per_step);
 
 /*
  * kpm_damping_factors -- damping factors g[0..M] (host, written).

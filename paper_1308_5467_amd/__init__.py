@@ -29,7 +29,7 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
-    "kpm_slq", "kpm_slq_dos", "kpm_tridiag_eig",
+    "kpm_slq", "kpm_slq_dos", "kpm_tridiag_eig", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH):
         "kpm_moments_robust": ([P, P, I32, U64, D, P, P, P, P, P, P], I32),
         "kpm_damping_factors": ([P, I32, I32, P, P], I32),
         "kpm_slq": ([P, P, D, D, P, P, P, P, P, P], I32),
+        "kpm_autotune": ([P, P, D, D, P, P, P], I32),
+        "kpm_autotune_batched": ([P, I32, P, P, P, P, P, P], I32),
         "kpm_slq_dos": ([P, P, P, I32, I32, D, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
@@ -224,7 +226,7 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
     return lb.value, ub.value
 
 
-KPM_FLAG_NO_GRAPH = 1
+KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8 = 1, 2, 4
 
 
 def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
@@ -233,11 +235,17 @@ def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) ->
                            flags)
 
 
+def _gather_flags(gather: int) -> int:
+    if gather not in (0, 4, 8):
+        raise ValueError("gather must be 0 (library default), 4 or 8")
+    return {0: 0, 4: KPM_FLAG_GATHER4, 8: KPM_FLAG_GATHER8}[gather]
+
+
 def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
                 precision="f32", block: int = 0, validate: bool = True, per_vector: bool = False,
-                rows_per_block: int = 0):
+                rows_per_block: int = 0, gather: int = 0):
     """Normalised moments mu[0..M]; with per_vector=True also [nvec, M+1] per-probe moments."""
-    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block)
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, _gather_flags(gather))
     mu = np.zeros(M + 1)
     pv = np.zeros((nvec, M + 1)) if per_vector else None
     c = A.as_c()
@@ -310,6 +318,32 @@ def kpm_tridiag_eig(alpha, beta):
     if st != 0:
         raise KpmError(st, "kpm_tridiag_eig failed")
     return th, w
+
+
+def kpm_autotune(ctx: Context, A, lb: float, ub: float, nvec: int, seed: int = 0, precision="f32",
+                 block: int = 0, rows_per_block: int = 0) -> dict:
+    """Measured choice of block, rows_per_block and gather for kpm_moments on A."""
+    o = _opts(16, nvec, seed, precision, block, False, rows_per_block)
+    best = kpm_moment_opts()
+    us = ctypes.c_double()
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_autotune(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), ctypes.byref(best),
+                                   ctypes.byref(us)))
+    return {"block": best.block, "rows_per_block": best.rows_per_block,
+            "gather": 4 if best.flags & KPM_FLAG_GATHER4 else 8, "us_per_step": us.value}
+
+
+def kpm_autotune_batched(ctx: Context, mats, lb, ub, nvec: int, seed: int = 0, precision="f32",
+                         block: int = 0, rows_per_block: int = 0) -> dict:
+    """Measured choice of block and rows_per_block for kpm_moments_batched."""
+    o = _opts(16, nvec, seed, precision, block, False, rows_per_block)
+    arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+    lbv, ubv = _f64(lb), _f64(ub)
+    best = kpm_moment_opts()
+    us = ctypes.c_double()
+    ctx.check(ctx.lib.kpm_autotune_batched(ctx.handle, len(mats), arr, _p(lbv), _p(ubv), ctypes.byref(o),
+                                           ctypes.byref(best), ctypes.byref(us)))
+    return {"block": best.block, "rows_per_block": best.rows_per_block, "us_per_step": us.value}
 
 
 def kpm_gershgorin(ctx: Context, A):

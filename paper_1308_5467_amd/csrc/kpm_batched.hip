@@ -27,6 +27,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -540,5 +541,84 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
                      maxabs[m]);
             return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
         }
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Times kpm_moments_batched for candidate (probe-block width, row-panel
+// height) pairs: per candidate one call to build and capture the plan, then
+// two calls each of degree 15 and 47 (8 and 24 steps); the difference of the
+// faster device times over the 16 extra steps is the time per step, free of
+// the fixed costs.
+extern "C" kpm_status kpm_autotune_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
+                                           const double* ub, const kpm_moment_opts* o, kpm_moment_opts* best,
+                                           double* us_per_step) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!o || !best || nmat < 1 || !A) return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (o->precision != KPM_FP32 && o->precision != KPM_FP64)
+        return kpm_fail(ctx, KPM_ERR_ARG, "precision must be KPM_FP32 or KPM_FP64");
+    const int maxb = o->precision == KPM_FP64 ? 128 : 256;
+    if (o->nvec < 1 || o->block < 0 || o->block > maxb || o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
+        return kpm_fail(ctx, KPM_ERR_ARG, "nvec, block or rows_per_block out of range");
+    int64_t nmax = 0;
+    for (int m = 0; m < nmat; ++m) nmax = std::max<int64_t>(nmax, A[m].n);
+    std::vector<int> blocks;
+    if (o->block > 0) {
+        blocks.push_back(std::min(o->block, o->nvec));
+    } else {
+        const int c32[] = {16, 32, 64}, c64[] = {8, 16, 32};
+        for (int c : (o->precision == KPM_FP64 ? c64 : c32))
+            if (c <= o->nvec) blocks.push_back(c);
+        if (blocks.empty()) blocks.push_back(o->nvec);
+    }
+    std::vector<double> mu;
+    // device time of one call, from the event pair the call records around
+    // its launch sequence when profiling is on
+    const bool prof_was = ctx->prof;
+    ctx->prof = true;
+    auto timed = [&](kpm_moment_opts t, int M, double* sec) -> kpm_status {
+        t.M = M;
+        mu.resize((size_t)nmat * (M + 1));
+        kpm_prof_entry& pe = ctx->prof_map["batched"];
+        const double before = pe.total_ms;
+        const kpm_status r = kpm_moments_batched(ctx, nmat, A, lb, ub, &t, mu.data(), nullptr);
+        *sec = (ctx->prof_map["batched"].total_ms - before) * 1e-3;
+        return r == KPM_ERR_SPECTRUM ? KPM_OK : r;  // values do not matter here
+    };
+    double best_t = 1e300;
+    kpm_moment_opts bo = *o;
+    for (int b : blocks) {
+        const int r0 = make_geom(nmax, b, o->precision, o->rows_per_block).rows_per_block;
+        std::vector<int> rows;
+        if (o->rows_per_block > 0) rows.push_back(r0);
+        else rows = {std::max(1, r0 / 2), r0, 2 * r0};
+        for (int r : rows) {
+            kpm_moment_opts t = *o;
+            t.block = b;
+            t.rows_per_block = r;
+            t.validate = 0;
+            double s0, s1, s2, s3, s4;
+            kpm_status st = timed(t, 47, &s0);  // plan and graph for this shape
+            if (st == KPM_OK) st = timed(t, 15, &s1);
+            if (st == KPM_OK) st = timed(t, 47, &s2);
+            if (st == KPM_OK) st = timed(t, 15, &s3);
+            if (st == KPM_OK) st = timed(t, 47, &s4);
+            if (st != KPM_OK) {
+                ctx->prof = prof_was;
+                return st;
+            }
+            (void)s0;
+            const double per_step = std::max(1e-12, (std::min(s2, s4) - std::min(s1, s3)) / 16.0) / b;
+            if (per_step < best_t) {
+                best_t = per_step;
+                bo.block = b;
+                bo.rows_per_block = make_geom(nmax, b, o->precision, r).rows_per_block;
+            }
+        }
+    }
+    ctx->prof = prof_was;
+    *best = bo;
+    if (us_per_step) *us_per_step = best_t * 1e6 * o->nvec;
     return KPM_OK;
 }

@@ -410,6 +410,8 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     const int K = (M + 1) / 2;  // ceil(M/2) sparse products per block
     const int esz = o->precision == KPM_FP64 ? 8 : 4;
     BlockGeom g = make_geom(A.n, b, o->precision, o->rows_per_block);
+    if (o->flags & KPM_FLAG_GATHER4) g.gather = 4;
+    if (o->flags & KPM_FLAG_GATHER8) g.gather = 8;
 
     void *X0, *X1, *part, *dots, *zeta, *mud;
     const int grid = cheb_step_grid(A, o->precision, g);
@@ -424,7 +426,11 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     const int nblk_vec = (nvec + b - 1) / b;
     for (int blk = 0; blk < nblk_vec; ++blk) {
         const int ncols = std::min(b, nvec - blk * b);
-        const BlockGeom gb = ncols == b ? g : make_geom(A.n, ncols, o->precision, o->rows_per_block);
+        BlockGeom gb = g;
+        if (ncols != b) {
+            gb = make_geom(A.n, ncols, o->precision, o->rows_per_block);
+            gb.gather = g.gather;
+        }
         const int gridb = ncols == b ? grid : cheb_step_grid(A, o->precision, gb);
         const int64_t vec0 = (int64_t)blk * b;
         KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
@@ -464,6 +470,101 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
             return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
         }
     }
+    return KPM_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Times the fused step on A for candidate (probe-block width, row-panel
+// height, gather batch) triples and returns the fastest per probe.  Each
+// candidate runs the first step and 2 warm-up steps, then kTuneSteps timed
+// steps between two events on the context's stream.
+extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
+                                   const kpm_moment_opts* o, kpm_moment_opts* best, double* us_per_step) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!o || !best) return kpm_fail(ctx, KPM_ERR_ARG, "opts or best is NULL");
+    if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
+    if (o->precision != KPM_FP32 && o->precision != KPM_FP64)
+        return kpm_fail(ctx, KPM_ERR_ARG, "precision must be KPM_FP32 or KPM_FP64");
+    const int maxb = o->precision == KPM_FP64 ? 128 : 256;
+    if (o->block < 0 || o->block > maxb) return kpm_fail(ctx, KPM_ERR_ARG, "block out of range");
+    if (o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
+        return kpm_fail(ctx, KPM_ERR_ARG, "rows_per_block out of range");
+    if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    CsrDev A;
+    kpm_status st = kpm_prepare_csr(ctx, Ain, o->precision, &A, "");
+    if (st != KPM_OK) return st;
+    if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
+
+    const int nvec = o->nvec;
+    std::vector<int> blocks;
+    if (o->block > 0) {
+        blocks.push_back(std::min(o->block, nvec));
+    } else {
+        const int cand32[] = {32, 64, 128}, cand64[] = {16, 32, 64};
+        for (int c : (o->precision == KPM_FP64 ? cand64 : cand32))
+            if (c <= nvec) blocks.push_back(c);
+        if (blocks.empty()) blocks.push_back(nvec);
+    }
+    const int esz = o->precision == KPM_FP64 ? 8 : 4;
+    int ldmax = 0;
+    for (int b : blocks) ldmax = std::max(ldmax, make_geom(A.n, b, o->precision, 0).ld);
+    constexpr int kTuneSteps = 6;
+    void *X0, *X1, *part;
+    if ((st = kpm_ws(ctx, "X0", (size_t)A.n * ldmax * esz, &X0)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "X1", (size_t)A.n * ldmax * esz, &X1)) != KPM_OK) return st;
+    hipEvent_t e0, e1;
+    KPM_HIP(ctx, hipEventCreate(&e0));
+    KPM_HIP(ctx, hipEventCreate(&e1));
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    const double alpha = 2.0 / d, beta = -2.0 * c / d;
+    double best_t = 1e300;
+    kpm_moment_opts bo = *o;
+    kpm_status rs = KPM_OK;
+    for (int b : blocks) {
+        const BlockGeom g0 = make_geom(A.n, b, o->precision, o->rows_per_block);
+        std::vector<int> rows;
+        if (o->rows_per_block > 0) rows.push_back(g0.rows_per_block);
+        else rows = {std::max(1, g0.rows_per_block / 2), g0.rows_per_block, 2 * g0.rows_per_block};
+        for (int r : rows)
+            for (int G : {4, 8}) {
+                BlockGeom g = make_geom(A.n, b, o->precision, r);
+                g.gather = G;
+                const int grid = cheb_step_grid(A, o->precision, g);
+                if ((rs = kpm_ws(ctx, "partial", (size_t)grid * 2 * g.ld * 8, &part)) != KPM_OK) break;
+                hipError_t he = launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A.n, o->precision, 1, X0);
+                void* X[2] = {X0, X1};
+                for (int k = 0; he == hipSuccess && k < 3 + kTuneSteps; ++k) {
+                    if (k == 3) he = hipEventRecord(e0, ctx->stream);
+                    if (he == hipSuccess)
+                        he = launch_cheb_step(ctx->stream, A, o->precision, k == 0, g, grid, X[k & 1], X[(k + 1) & 1],
+                                              alpha, beta, (double*)part, (k & 1) != 0);
+                }
+                if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) {
+                    rs = kpm_hip_fail(ctx, he, "autotune candidate");
+                    break;
+                }
+                const double t = (double)ms / kTuneSteps / b;  // per step and probe
+                if (t < best_t) {
+                    best_t = t;
+                    bo.block = b;
+                    bo.rows_per_block = g.rows_per_block;
+                    bo.flags = (o->flags & ~(KPM_FLAG_GATHER4 | KPM_FLAG_GATHER8)) |
+                               (G == 4 ? KPM_FLAG_GATHER4 : KPM_FLAG_GATHER8);
+                }
+            }
+        if (rs != KPM_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rs != KPM_OK) return rs;
+    *best = bo;
+    if (us_per_step) *us_per_step = best_t * 1000.0 * nvec;
     return KPM_OK;
 }
 

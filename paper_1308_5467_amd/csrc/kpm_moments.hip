@@ -33,6 +33,10 @@
 
 namespace kpm {
 
+struct StepTune;
+static const StepTune& tune();
+static int tune_gather();
+
 BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint) {
     BlockGeom g;
     const int vpl = precision == KPM_FP64 ? 2 : 4;
@@ -56,6 +60,7 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
     }
     g.rows_per_block = rows;
     g.nblocks = (int)((n + rows - 1) / rows);
+    g.gather = tune_gather();
     return g;
 }
 
@@ -212,6 +217,7 @@ static const StepTune& tune() {
     static StepTune t = read_tune();
     return t;
 }
+static int tune_gather() { return tune().gather; }
 
 // Workgroups of `kernel` that fit on the current device at once (0 if unknown).
 static int resident_blocks(const void* kernel) {
@@ -251,7 +257,7 @@ static bool step_off32(const CsrDev& A, const BlockGeom& g, int precision) {
 
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
     const bool off32 = step_off32(A, g, precision);
-    const bool g4 = tune().gather == 4;
+    const bool g4 = g.gather == 4;
 #define KPM_GRID_V(TA, TV, O) return g4 ? grid_of<TA, TV, O, 4>(g.nblocks) : grid_of<TA, TV, O, 8>(g.nblocks)
 #define KPM_GRID(TA, TV)          \
     if (off32) {                  \
@@ -288,7 +294,7 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.stage = tune().stage;
     p.reverse = reverse && tune().rev;
     const bool off32 = step_off32(A, g, precision);
-    const bool g4 = tune().gather == 4;
+    const bool g4 = g.gather == 4;
 #define KPM_STEP_G(TA, TV, GG)                                                                   \
     return off32 ? (first ? launch_step_variant<TA, TV, true, true, GG>(s, p, grid)              \
                           : launch_step_variant<TA, TV, false, true, GG>(s, p, grid))            \
