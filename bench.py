@@ -168,6 +168,7 @@ def main():
         out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A, D, x)
         out["batched_uneven_48"] = batched_leg(kpm, ctx, synth)
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A, D, x)
+        out["autotune"] = autotune_leg(kpm, ctx, D, lb, ub, args, roof)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -283,6 +284,15 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
             "sparse_products_per_probe": M_SLQ}
 
 
+def autotune_leg(kpm, ctx, D, lb, ub, args, roof):
+    """The measured geometry choice for this workload next to the fixed
+    default the timed steps use (block 64, library panel height, gather 8)."""
+    t = kpm.kpm_autotune(ctx, D, lb, ub, args.nvec, seed=2002, precision=args.precision)
+    return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")},
+            "us_per_step_chosen": round(t["us_per_step"], 2),
+            "us_per_step_default": roof.get("avg_launch_us")}
+
+
 def batched_leg(kpm, ctx, synth, reps=5):
     """48 uneven matrices (2D Dirichlet 64..512, 3D periodic 16..64, disorder
     W in {2, 8, 16}), M = 200, 32 probes each, FP32, one launch per step,
@@ -309,6 +319,13 @@ def batched_leg(kpm, ctx, synth, reps=5):
     ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003), reps)
     kpm.kpm_profile_enable(ctx, False)
     n_dev, dev_ms = kpm.kpm_profile_query(ctx, "batched")
+    tuned = kpm.kpm_autotune_batched(ctx, D, lb, ub, 32, seed=2003)
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    ms_t = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003, block=tuned["block"],
+                                                    rows_per_block=tuned["rows_per_block"]), reps)
+    kpm.kpm_profile_enable(ctx, False)
+    n_dev_t, dev_ms_t = kpm.kpm_profile_query(ctx, "batched")
     nnz = sum(A.nnz for A in mats)
     n = sum(A.n for A in mats)
     byts = 100 * (8 * nnz + 4 * (n + len(mats)) + 3 * 4 * n * 32)
@@ -317,7 +334,9 @@ def batched_leg(kpm, ctx, synth, reps=5):
             "ms_per_call": round(ms, 3), "device_ms_per_call": round(dev_avg, 3),
             "units_per_s": nnz * 200 * 32 / (ms * 1e-3),
             "algorithmic_gbs_device": round(byts / (dev_avg * 1e-3) / 1e9, 1),
-            "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub))}
+            "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
+            "autotuned": {"block": tuned["block"], "rows_per_block": tuned["rows_per_block"],
+                          "ms_per_call": round(ms_t, 3), "device_ms_per_call": round(dev_ms_t / max(n_dev_t, 1), 3)}}
 
 
 if __name__ == "__main__":
