@@ -88,10 +88,12 @@ enum {
     KPM_FLAG_NO_GRAPH = 1, /* kpm_moments_batched: launch directly instead of
                               replaying the captured HIP graph                */
     KPM_FLAG_GATHER4 = 2,  /* kpm_moments: gather a row's CSR entries in
-                              batches of 4 instead of 8 (fewer registers,
-                              one more memory round trip for rows of 5-8)     */
-    KPM_FLAG_GATHER8 = 4   /* kpm_moments: batches of 8 (overrides the
-                              KPM_TUNE environment default)                  */
+                              batches of 4 (fewest registers)                */
+    KPM_FLAG_GATHER8 = 4,  /* kpm_moments: batches of 8                      */
+    KPM_FLAG_GATHER7 = 8   /* kpm_moments: batches of 7 (the default: one
+                              round trip per 7-point stencil row at 5
+                              wavefronts per SIMD); the GATHER flags override
+                              the KPM_TUNE environment default               */
 };
 
 typedef enum {
@@ -152,10 +154,10 @@ kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
  * measurement: for each candidate probe-block width (opts->block if set,
  * else 32/64/128 for KPM_FP32, 16/32/64 for KPM_FP64, capped at nvec), row
  * panel height (opts->rows_per_block if set, else the library's choice and
- * half and twice it) and gather batch (4 or 8 CSR entries), time 6 fused
+ * half and twice it) and gather batch (4, 7 or 8 CSR entries), time 6 fused
  * recurrence steps (section 3.1.1, eq. (3term)) on the context's stream and
  * keep the fastest per probe.  *best = *opts with block, rows_per_block and
- * the KPM_FLAG_GATHER4 / KPM_FLAG_GATHER8 bit set to the winner (pass it to
+ * the KPM_FLAG_GATHER4 / 7 / 8 bit set to the winner (pass it to
  * kpm_moments; results depend on the geometry only through rounding, and are
  * bitwise reproducible for a fixed geometry).  *us_per_step (nullable): the
  * winner's time per recurrence step for all nvec probes, in microseconds.

@@ -226,7 +226,7 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
     return lb.value, ub.value
 
 
-KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8 = 1, 2, 4
+KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8, KPM_FLAG_GATHER7 = 1, 2, 4, 8
 
 
 def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
@@ -236,9 +236,9 @@ def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) ->
 
 
 def _gather_flags(gather: int) -> int:
-    if gather not in (0, 4, 8):
-        raise ValueError("gather must be 0 (library default), 4 or 8")
-    return {0: 0, 4: KPM_FLAG_GATHER4, 8: KPM_FLAG_GATHER8}[gather]
+    if gather not in (0, 4, 7, 8):
+        raise ValueError("gather must be 0 (library default), 4, 7 or 8")
+    return {0: 0, 4: KPM_FLAG_GATHER4, 7: KPM_FLAG_GATHER7, 8: KPM_FLAG_GATHER8}[gather]
 
 
 def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
@@ -330,7 +330,8 @@ def kpm_autotune(ctx: Context, A, lb: float, ub: float, nvec: int, seed: int = 0
     ctx.check(ctx.lib.kpm_autotune(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), ctypes.byref(best),
                                    ctypes.byref(us)))
     return {"block": best.block, "rows_per_block": best.rows_per_block,
-            "gather": 4 if best.flags & KPM_FLAG_GATHER4 else 8, "us_per_step": us.value}
+            "gather": 4 if best.flags & KPM_FLAG_GATHER4 else (7 if best.flags & KPM_FLAG_GATHER7 else 8),
+            "us_per_step": us.value}
 
 
 def kpm_autotune_batched(ctx: Context, mats, lb, ub, nvec: int, seed: int = 0, precision="f32",

@@ -233,7 +233,7 @@ int batched_resident() {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(batched_step_kernel<TA, TV, false, 8>), kThreads, 0) !=
+            &per_cu, reinterpret_cast<const void*>(batched_step_kernel<TA, TV, false, 7>), kThreads, 0) !=
         hipSuccess)
         return 0;
     return per_cu * prop.multiProcessorCount;
@@ -246,10 +246,10 @@ hipError_t enqueue_batched(hipStream_t s, const BatchPlan& P) {
     for (int k = 0; k < P.K; ++k) {
         double* pk = P.d_partial + (size_t)k * P.nentries * 2 * P.ld;
         if (k == 0)
-            batched_step_kernel<TA, TV, true, 8><<<P.nentries, kThreads, 0, s>>>(
+            batched_step_kernel<TA, TV, true, 7><<<P.nentries, kThreads, 0, s>>>(
                 P.d_entries, P.d_mvs, 0, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk);
         else
-            batched_step_kernel<TA, TV, false, 8><<<P.nentries, kThreads, 0, s>>>(
+            batched_step_kernel<TA, TV, false, 7><<<P.nentries, kThreads, 0, s>>>(
                 P.d_entries, P.d_mvs, k & 1, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk);
     }
     if (P.K > 0) {

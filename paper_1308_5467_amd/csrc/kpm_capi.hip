@@ -411,6 +411,7 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     const int esz = o->precision == KPM_FP64 ? 8 : 4;
     BlockGeom g = make_geom(A.n, b, o->precision, o->rows_per_block);
     if (o->flags & KPM_FLAG_GATHER4) g.gather = 4;
+    if (o->flags & KPM_FLAG_GATHER7) g.gather = 7;
     if (o->flags & KPM_FLAG_GATHER8) g.gather = 8;
 
     void *X0, *X1, *part, *dots, *zeta, *mud;
@@ -528,7 +529,7 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
         if (o->rows_per_block > 0) rows.push_back(g0.rows_per_block);
         else rows = {std::max(1, g0.rows_per_block / 2), g0.rows_per_block, 2 * g0.rows_per_block};
         for (int r : rows)
-            for (int G : {4, 8}) {
+            for (int G : {4, 7, 8}) {
                 BlockGeom g = make_geom(A.n, b, o->precision, r);
                 g.gather = G;
                 const int grid = cheb_step_grid(A, o->precision, g);
@@ -554,8 +555,8 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
                     best_t = t;
                     bo.block = b;
                     bo.rows_per_block = g.rows_per_block;
-                    bo.flags = (o->flags & ~(KPM_FLAG_GATHER4 | KPM_FLAG_GATHER8)) |
-                               (G == 4 ? KPM_FLAG_GATHER4 : KPM_FLAG_GATHER8);
+                    bo.flags = (o->flags & ~(KPM_FLAG_GATHER4 | KPM_FLAG_GATHER7 | KPM_FLAG_GATHER8)) |
+                               (G == 4 ? KPM_FLAG_GATHER4 : (G == 7 ? KPM_FLAG_GATHER7 : KPM_FLAG_GATHER8));
                 }
             }
         if (rs != KPM_OK) break;

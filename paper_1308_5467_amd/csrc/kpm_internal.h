@@ -29,7 +29,7 @@ struct CsrDev {
 // the 4 * rpw rows one workgroup pass covers), `nblocks` workgroups.
 struct BlockGeom {
     int ld = 0, lpr = 0, rpw = 0, rows_per_block = 0, nblocks = 0;
-    int gather = 8;  // single-matrix step: CSR entries per gather batch (4 or 8)
+    int gather = 7;  // single-matrix step: CSR entries per gather batch (4, 7 or 8)
 };
 
 constexpr int kWaves = 4;        // wavefronts per workgroup of the step kernels

@@ -194,11 +194,13 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     }
 }
 
-// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|8,rev=0|1").
+// Tuning knobs, read once from KPM_TUNE ("stage=0|1,persist=0|1,gather=4|7|8,rev=0|1").
+// Gather batches of 7 fit a 7-point stencil row in one memory round trip and
+// keep the FP32 step at 93 VGPRs (5 waves per SIMD; 8 needs 98, 4 waves).
 struct StepTune {
     int stage = 1;
     int persist = 1;
-    int gather = 8;
+    int gather = 7;
     int rev = 1;
 };
 static StepTune read_tune() {
@@ -208,7 +210,10 @@ static StepTune read_tune() {
         const char* s;
         if ((s = strstr(e, "stage="))) t.stage = atoi(s + 6);
         if ((s = strstr(e, "persist="))) t.persist = atoi(s + 8);
-        if ((s = strstr(e, "gather="))) t.gather = atoi(s + 7) == 4 ? 4 : 8;
+        if ((s = strstr(e, "gather="))) {
+            const int gv = atoi(s + 7);
+            t.gather = gv == 4 || gv == 8 ? gv : 7;
+        }
         if ((s = strstr(e, "rev="))) t.rev = atoi(s + 4);
     }
     return t;
@@ -257,8 +262,9 @@ static bool step_off32(const CsrDev& A, const BlockGeom& g, int precision) {
 
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
     const bool off32 = step_off32(A, g, precision);
-    const bool g4 = g.gather == 4;
-#define KPM_GRID_V(TA, TV, O) return g4 ? grid_of<TA, TV, O, 4>(g.nblocks) : grid_of<TA, TV, O, 8>(g.nblocks)
+#define KPM_GRID_V(TA, TV, O)                                                              \
+    return g.gather == 4 ? grid_of<TA, TV, O, 4>(g.nblocks)                                \
+                         : (g.gather == 8 ? grid_of<TA, TV, O, 8>(g.nblocks) : grid_of<TA, TV, O, 7>(g.nblocks))
 #define KPM_GRID(TA, TV)          \
     if (off32) {                  \
         KPM_GRID_V(TA, TV, true); \
@@ -294,17 +300,18 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.stage = tune().stage;
     p.reverse = reverse && tune().rev;
     const bool off32 = step_off32(A, g, precision);
-    const bool g4 = g.gather == 4;
 #define KPM_STEP_G(TA, TV, GG)                                                                   \
     return off32 ? (first ? launch_step_variant<TA, TV, true, true, GG>(s, p, grid)              \
                           : launch_step_variant<TA, TV, false, true, GG>(s, p, grid))            \
                  : (first ? launch_step_variant<TA, TV, true, false, GG>(s, p, grid)             \
                           : launch_step_variant<TA, TV, false, false, GG>(s, p, grid))
-#define KPM_STEP_DISPATCH(TA, TV) \
-    if (g4) {                     \
-        KPM_STEP_G(TA, TV, 4);    \
-    } else {                      \
-        KPM_STEP_G(TA, TV, 8);    \
+#define KPM_STEP_DISPATCH(TA, TV)    \
+    if (g.gather == 4) {             \
+        KPM_STEP_G(TA, TV, 4);       \
+    } else if (g.gather == 8) {      \
+        KPM_STEP_G(TA, TV, 8);       \
+    } else {                         \
+        KPM_STEP_G(TA, TV, 7);       \
     }
     if (precision == KPM_FP64) {
         if (A.val_f64) KPM_STEP_DISPATCH(double, double);
