@@ -58,6 +58,8 @@ def parse():
                     help="only run the stochastic Lanczos leg on the workload (profiling)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 48-matrix batched leg (profiling)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner measurements (profiling one geometry)")
     ap.add_argument("--cpu-sample-vectors", type=int, default=0,
                     help="probes in the oracle sample (0 = all cores' worth)")
     return ap.parse_args()
@@ -74,7 +76,7 @@ def main():
 
     if args.batched_only:
         ctx = kpm.Context(0)
-        print(json.dumps({"batched_uneven_48": batched_leg(kpm, ctx, synth)}))
+        print(json.dumps({"batched_uneven_48": batched_leg(kpm, ctx, synth, tune=not args.no_autotune)}))
         return
 
     if args.copy_probe_only:
@@ -166,9 +168,10 @@ def main():
 
     if not args.no_extras:
         out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A, D, x)
-        out["batched_uneven_48"] = batched_leg(kpm, ctx, synth)
+        out["batched_uneven_48"] = batched_leg(kpm, ctx, synth, tune=not args.no_autotune)
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A, D, x)
-        out["autotune"] = autotune_leg(kpm, ctx, D, lb, ub, args, roof)
+        if not args.no_autotune:
+            out["autotune"] = autotune_leg(kpm, ctx, D, lb, ub, args, roof)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -293,7 +296,7 @@ def autotune_leg(kpm, ctx, D, lb, ub, args, roof):
             "us_per_step_default": roof.get("avg_launch_us")}
 
 
-def batched_leg(kpm, ctx, synth, reps=5):
+def batched_leg(kpm, ctx, synth, reps=5, tune=True):
     """48 uneven matrices (2D Dirichlet 64..512, 3D periodic 16..64, disorder
     W in {2, 8, 16}), M = 200, 32 probes each, FP32, one launch per step,
     graph replay.  Bounds: Lanczos with escape recovery (margin x4, then the
@@ -319,13 +322,17 @@ def batched_leg(kpm, ctx, synth, reps=5):
     ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003), reps)
     kpm.kpm_profile_enable(ctx, False)
     n_dev, dev_ms = kpm.kpm_profile_query(ctx, "batched")
-    tuned = kpm.kpm_autotune_batched(ctx, D, lb, ub, 32, seed=2003)
-    kpm.kpm_profile_reset(ctx)
-    kpm.kpm_profile_enable(ctx, True)
-    ms_t = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003, block=tuned["block"],
-                                                    rows_per_block=tuned["rows_per_block"]), reps)
-    kpm.kpm_profile_enable(ctx, False)
-    n_dev_t, dev_ms_t = kpm.kpm_profile_query(ctx, "batched")
+    tuned_out = None
+    if tune:
+        tuned = kpm.kpm_autotune_batched(ctx, D, lb, ub, 32, seed=2003)
+        kpm.kpm_profile_reset(ctx)
+        kpm.kpm_profile_enable(ctx, True)
+        ms_t = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003, block=tuned["block"],
+                                                        rows_per_block=tuned["rows_per_block"]), reps)
+        kpm.kpm_profile_enable(ctx, False)
+        n_dev_t, dev_ms_t = kpm.kpm_profile_query(ctx, "batched")
+        tuned_out = {"block": tuned["block"], "rows_per_block": tuned["rows_per_block"],
+                     "ms_per_call": round(ms_t, 3), "device_ms_per_call": round(dev_ms_t / max(n_dev_t, 1), 3)}
     nnz = sum(A.nnz for A in mats)
     n = sum(A.n for A in mats)
     byts = 100 * (8 * nnz + 4 * (n + len(mats)) + 3 * 4 * n * 32)
@@ -335,8 +342,7 @@ def batched_leg(kpm, ctx, synth, reps=5):
             "units_per_s": nnz * 200 * 32 / (ms * 1e-3),
             "algorithmic_gbs_device": round(byts / (dev_avg * 1e-3) / 1e9, 1),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
-            "autotuned": {"block": tuned["block"], "rows_per_block": tuned["rows_per_block"],
-                          "ms_per_call": round(ms_t, 3), "device_ms_per_call": round(dev_ms_t / max(n_dev_t, 1), 3)}}
+            "autotuned": tuned_out}
 
 
 if __name__ == "__main__":
