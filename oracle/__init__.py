@@ -22,7 +22,9 @@ densities of large matrices" in plain numpy / C, in the paper's order:
   for comparisons in section 4;
 * ``mlp_*``           -- FP64 forward/backward of the damping network;
 * ``lanczos_*``       -- the stochastic Lanczos method of section 3.2.1
-  (``slq.py``).
+  (``slq.py``);
+* ``haydock_dos``     -- Haydock's method of section 3.2.2 from the same
+  Lanczos matrices (``slq.py``).
 
 Moments are normalised as mu_hat_k = zeta_k / n (so mu_hat_0 = 1); the
 paper's (2 - delta_k0)/pi factor is applied when the density is evaluated.
@@ -335,4 +337,4 @@ def scaled_eigenvalues(A, lb: float, ub: float) -> np.ndarray:
 from .mlp import (mlp_init, mlp_forward, mlp_backward, mlp_loss_and_grads,  # noqa: E402
                   blur_operator, gelu)
 from .slq import (lanczos_tridiag, lanczos_nodes, lanczos_dos, quadrature_moments,  # noqa: E402
-                  steps_used as lanczos_steps_used)
+                  steps_used as lanczos_steps_used, haydock_dos, lorentz)

@@ -11,7 +11,12 @@ order:
 * ``lanczos_nodes``    -- eigenvalues theta_k of T_M and the squared first
   components tau_k^2 of its normalised eigenvectors (eq. (landist));
 * ``lanczos_dos``      -- the Gaussian-blurred average over probes, eq.
-  (landos).
+  (landos);
+* ``haydock_dos``      -- Haydock's method (section 3.2.2): the
+  Lorentzian-regularised density -(1/pi) Im e_1^T (z - T_M)^{-1} e_1 of
+  each probe's tridiagonal matrix, averaged over probes.  The paper's
+  second form of phi_eta writes +Im; the imaginary part of the resolvent is
+  negative there, so the density takes -Im (a reading).
 
 Normalisation (the paper's eq. (lanapprox) carries a 1/n whose matching
 factor is the squared norm of the start vector): a Rademacher probe has
@@ -114,3 +119,38 @@ def lanczos_dos(theta: np.ndarray, tau2: np.ndarray, t: np.ndarray, sigma: float
 def quadrature_moments(theta: np.ndarray, tau2: np.ndarray, qmax: int) -> np.ndarray:
     """sum_k tau2[l, k] theta[l, k]^q for q = 0..qmax (per probe)."""
     return np.stack([np.sum(tau2 * theta ** q, axis=1) for q in range(qmax + 1)], axis=1)
+
+
+def haydock_dos(alpha: np.ndarray, beta: np.ndarray, m: np.ndarray, x: np.ndarray, eta: float,
+                c: float, d: float) -> np.ndarray:
+    """Haydock's method (section 3.2.2): the Lorentzian-regularised density
+    at points x (A's units) from the Lanczos matrices alone, no Ritz values:
+
+        phi_eta(x) = (1/nvec) sum_l -(1/pi) Im e_1^T ((x + i eta) I - T_l)^{-1} e_1,
+
+    T_l = c I + d tridiag(beta, alpha, beta)[:m_l, :m_l] the probe's
+    tridiagonal matrix in A's units (alpha, beta are those of B).  Written
+    from the definition: one dense complex solve per probe and point (the
+    continued fraction of eq. (cfHaydock) is the same quantity).  The minus
+    sign makes the density non-negative: Im 1/(x + i eta - lambda) < 0.
+    Unit mass per probe, as in ``lanczos_dos``."""
+    x = np.asarray(x, dtype=np.float64)
+    nvec = alpha.shape[0]
+    out = np.zeros(x.size)
+    for l in range(nvec):
+        k = int(m[l])
+        T = np.diag(c + d * alpha[l, :k]).astype(complex)
+        if k > 1:
+            off = d * beta[l, :k - 1]
+            T += np.diag(off, 1) + np.diag(off, -1)
+        e1 = np.zeros((x.size, k, 1), dtype=complex)
+        e1[:, 0, 0] = 1.0
+        Z = (x + 1j * eta)[:, None, None] * np.eye(k) - T  # one matrix per point
+        g = np.linalg.solve(Z, e1)[:, 0, 0]
+        out += -g.imag / math.pi
+    return out / nvec
+
+
+def lorentz(t, eta: float):
+    """Lorentzian of half-width eta, unit mass: (eta/pi) / (t^2 + eta^2)."""
+    return (eta / math.pi) / (np.asarray(t) ** 2 + eta * eta)
