@@ -269,6 +269,18 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
         return kpm.kpm_slq_dos(ctx, th, t2, sigma, x)
 
     t_pipe = _time_ms(pipeline, reps)
+    # Haydock's method on the same Lanczos runs: the continued fraction of
+    # each probe's tridiagonal matrix at the 200 points, Lorentzian width
+    # eta = sigma, no eigenvalues (section 3.2.2).
+    _, _, used, al, be = kpm.kpm_slq(ctx, D32, lb, ub, M_SLQ, nvec, 2002, block=b, coefficients=True)
+    t_hay = _time_ms(lambda: kpm.kpm_haydock_dos(ctx, al, be, used, lb, ub, sigma, x), reps)
+
+    def pipeline_haydock():
+        l, u = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
+        _, _, us, a, bb = kpm.kpm_slq(ctx, D32, l, u, M_SLQ, nvec, 2002, block=b, coefficients=True)
+        return kpm.kpm_haydock_dos(ctx, a, bb, us, l, u, sigma, x)
+
+    t_pipe_hay = _time_ms(pipeline_haydock, reps)
     kpm.kpm_profile_reset(ctx)
     kpm.kpm_profile_enable(ctx, True)
     t_slq = _time_ms(lambda: kpm.kpm_slq(ctx, D32, lb, ub, M_SLQ, nvec, 2002, block=b), reps)
@@ -282,6 +294,7 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
             "lanczos_steps": M_SLQ, "nvec": nvec, "block": b, "blocks_per_launch": nblk,
             "accuracy_source": "tests/test_gpu_accuracy.py (L1 sigma=0.02 vs the FP64 oracle's degree-512 series)",
             "ms_pipeline": round(t_pipe, 3), "ms_lanczos": round(t_slq, 3),
+            "ms_pipeline_haydock": round(t_pipe_hay, 3), "ms_haydock_density": round(t_hay, 3),
             "us_per_step": round(us_step, 2), "algorithmic_bytes_per_step": bytes_step,
             "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / 8000.0, 4),
             "sparse_products_per_probe": M_SLQ}
@@ -289,7 +302,7 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
 
 def autotune_leg(kpm, ctx, D, lb, ub, args, roof):
     """The measured geometry choice for this workload next to the fixed
-    default the timed steps use (block 64, library panel height, gather 8)."""
+    default the timed steps use (block 64, library panel height, gather 7)."""
     t = kpm.kpm_autotune(ctx, D, lb, ub, args.nvec, seed=2002, precision=args.precision)
     return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")},
             "us_per_step_chosen": round(t["us_per_step"], 2),

@@ -283,6 +283,27 @@ kpm_status kpm_slq_dos(kpm_ctx* ctx, const double* theta, const double* tau2, in
                        const double* x, int npts, double* phi);
 
 /*
+ * kpm_haydock_dos -- Haydock's method (section 3.2.2): the density
+ * regularised by Lorentzians of half-width eta (eq. (lorentz)),
+ *   phi(x_i) = (1/nvec) sum_l -(1/pi) Im e_1^T ((x_i + i eta) I - T_l)^{-1} e_1,
+ * from the probes' Lanczos matrices without their eigenvalues: the (1,1)
+ * resolvent entry is the continued fraction of eq. (cfHaydock), evaluated
+ * from the bottom in FP64 on the device.  T_l = c I + d tridiag(beta, alpha,
+ * beta) restricted to its first steps_used[l] rows, with alpha, beta the
+ * coefficients of B written by kpm_slq (host, [nvec * M], row l for probe
+ * l; beta[l*M+k] couples steps k and k+1) and c = (lb+ub)/2, d = (ub-lb)/2
+ * the lb, ub given to kpm_slq.  x (host, npts points) and eta in A's units;
+ * phi (host, npts) in A's units, non-negative, unit mass per probe (the
+ * paper's second form of phi_eta writes +Im: the sign is taken so that the
+ * density is that of its first form).  KPM_ERR_ARG for eta <= 0, lb >= ub,
+ * a steps_used entry outside [1, M], a non-finite coefficient among those
+ * used, or nvec outside [1, 65535].
+ */
+kpm_status kpm_haydock_dos(kpm_ctx* ctx, const double* alpha, const double* beta, const int* steps_used,
+                           int nvec, int M, double lb, double ub, double eta, const double* x, int npts,
+                           double* phi);
+
+/*
  * kpm_tridiag_eig -- host-only helper (no device work): eigenvalues theta
  * (ascending) and squared first eigenvector components tau2 of the
  * symmetric tridiagonal matrix with diagonal alpha[0..m-1] and off-diagonal

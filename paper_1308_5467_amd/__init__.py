@@ -29,7 +29,7 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
-    "kpm_slq", "kpm_slq_dos", "kpm_tridiag_eig", "kpm_autotune", "kpm_autotune_batched",
+    "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_autotune": ([P, P, D, D, P, P, P], I32),
         "kpm_autotune_batched": ([P, I32, P, P, P, P, P, P], I32),
         "kpm_slq_dos": ([P, P, P, I32, I32, D, P, I32, P], I32),
+        "kpm_haydock_dos": ([P, P, P, P, I32, I32, D, D, D, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
@@ -304,6 +305,21 @@ def kpm_slq_dos(ctx: Context, theta, tau2, sigma: float, x) -> np.ndarray:
     phi = np.zeros(x.size)
     ctx.check(ctx.lib.kpm_slq_dos(ctx.handle, _p(th), _p(w), th.shape[0], th.shape[1], sigma, _p(x), x.size,
                                   _p(phi)))
+    return phi
+
+
+def kpm_haydock_dos(ctx: Context, alpha, beta, steps_used, lb: float, ub: float, eta: float, x) -> np.ndarray:
+    """Haydock's Lorentzian density at points x (A's units) from kpm_slq's
+    coefficients alpha, beta [nvec, M] (of B) and steps_used [nvec]."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    u = np.ascontiguousarray(steps_used, dtype=np.int32)
+    if a.ndim != 2 or a.shape != b.shape or u.shape != (a.shape[0],):
+        raise ValueError("alpha and beta must be [nvec, M] and steps_used [nvec]")
+    x = _f64(x)
+    phi = np.zeros(x.size)
+    ctx.check(ctx.lib.kpm_haydock_dos(ctx.handle, _p(a), _p(b), u.ctypes.data_as(ctypes.c_void_p), a.shape[0],
+                                      a.shape[1], lb, ub, eta, _p(x), x.size, _p(phi)))
     return phi
 
 
