@@ -24,7 +24,10 @@ densities of large matrices" in plain numpy / C, in the paper's order:
 * ``lanczos_*``       -- the stochastic Lanczos method of section 3.2.1
   (``slq.py``);
 * ``haydock_dos``     -- Haydock's method of section 3.2.2 from the same
-  Lanczos matrices (``slq.py``).
+  Lanczos matrices (``slq.py``);
+* ``legendre_*``, ``dgl_*`` -- Legendre moments, KPM with Legendre
+  polynomials and the Delta-Gauss-Legendre method (section 3.1.3,
+  Appendix B) (``dgl.py``).
 
 Moments are normalised as mu_hat_k = zeta_k / n (so mu_hat_0 = 1); the
 paper's (2 - delta_k0)/pi factor is applied when the density is evaluated.
@@ -338,3 +341,5 @@ from .mlp import (mlp_init, mlp_forward, mlp_backward, mlp_loss_and_grads,  # no
                   blur_operator, gelu)
 from .slq import (lanczos_tridiag, lanczos_nodes, lanczos_dos, quadrature_moments,  # noqa: E402
                   steps_used as lanczos_steps_used, haydock_dos, lorentz)
+from .dgl import (legendre_moments, legendre_moments_per_vector, dgl_gamma, dgl_dos,  # noqa: E402
+                  legendre_dos)
