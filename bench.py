@@ -56,6 +56,8 @@ def parse():
                     help="only run the streaming-copy bandwidth probe (counter calibration)")
     ap.add_argument("--slq-only", action="store_true",
                     help="only run the stochastic Lanczos leg on the workload (profiling)")
+    ap.add_argument("--legendre-only", action="store_true",
+                    help="only the Legendre / Delta-Gauss-Legendre leg")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 48-matrix batched leg (profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -91,6 +93,9 @@ def main():
     ctx = kpm.Context(0)
     M, nvec, block = args.M, args.nvec, args.block
     x = np.linspace(-10.0, 22.0, 200)
+    if args.legendre_only:
+        print(json.dumps({"legendre_dgl": legendre_leg(kpm, ctx, D, x, args)}))
+        return
     if args.slq_only:
         D32 = D if args.precision == "f32" else kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx,
                                                                          A.val.astype(np.float32), "f32")
@@ -170,6 +175,7 @@ def main():
         out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A, D, x)
         out["batched_uneven_48"] = batched_leg(kpm, ctx, synth, tune=not args.no_autotune)
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A, D, x)
+        out["legendre_dgl"] = legendre_leg(kpm, ctx, D, x, args)
         if not args.no_autotune:
             out["autotune"] = autotune_leg(kpm, ctx, D, lb, ub, args, roof)
 
@@ -298,6 +304,33 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
             "us_per_step": round(us_step, 2), "algorithmic_bytes_per_step": bytes_step,
             "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / 8000.0, 4),
             "sparse_products_per_probe": M_SLQ}
+
+
+def legendre_leg(kpm, ctx, D, x, args, reps=5):
+    """Legendre moments of the workload (degree M, the probes and precision
+    of the timed steps) by the two device routes -- Chebyshev moments
+    converted with non-negative weights (ceil(M/2) sparse products) and the
+    Legendre recurrence of Algorithm DGL (M sparse products) -- and the
+    Delta-Gauss-Legendre density at the 200 points (sigma = 0.02 of the
+    half-width, stopping tolerance 1e-6)."""
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
+    M, nvec = args.M, args.nvec
+
+    def run(rec):
+        return kpm.kpm_legendre_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision,
+                                        block=args.block, validate=False, recurrence=rec)
+
+    t_conv = _time_ms(lambda: run(False), reps)
+    t_rec = _time_ms(lambda: run(True), reps)
+    mu = run(False)
+    diff = float(np.max(np.abs(mu - run(True))))
+    sigma = 0.02 * 0.5 * (ub - lb)
+    t_dgl = _time_ms(lambda: kpm.kpm_dgl_dos(ctx, mu, lb, ub, sigma, x), reps)
+    _, deg = kpm.kpm_dgl_dos(ctx, mu, lb, ub, sigma, x)
+    return {"M": M, "nvec": nvec, "precision": args.precision,
+            "ms_moments_converted": round(t_conv, 3), "ms_moments_recurrence": round(t_rec, 3),
+            "speedup_converted": round(t_rec / t_conv, 2), "max_abs_diff_routes": diff,
+            "ms_dgl_density": round(t_dgl, 3), "dgl_degree_min_max": [int(deg.min()), int(deg.max())]}
 
 
 def autotune_leg(kpm, ctx, D, lb, ub, args, roof):

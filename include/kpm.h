@@ -90,10 +90,14 @@ enum {
     KPM_FLAG_GATHER4 = 2,  /* kpm_moments: gather a row's CSR entries in
                               batches of 4 (fewest registers)                */
     KPM_FLAG_GATHER8 = 4,  /* kpm_moments: batches of 8                      */
-    KPM_FLAG_GATHER7 = 8   /* kpm_moments: batches of 7 (the default: one
+    KPM_FLAG_GATHER7 = 8,  /* kpm_moments: batches of 7 (the default: one
                               round trip per 7-point stencil row at 5
                               wavefronts per SIMD); the GATHER flags override
                               the KPM_TUNE environment default               */
+    KPM_FLAG_LEGENDRE_RECURRENCE = 16 /* kpm_legendre_moments: run the
+                              Legendre three-term recurrence of Algorithm DGL
+                              (M sparse products per block) instead of
+                              converting Chebyshev moments                    */
 };
 
 typedef enum {
@@ -148,6 +152,22 @@ kpm_status kpm_gershgorin(kpm_ctx* ctx, const kpm_csr* A, double* lo, double* hi
  */
 kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
                        const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
+
+/*
+ * kpm_legendre_moments -- the stochastic Legendre moments of Algorithm DGL
+ * (section 3.1.3) and of KPM with Legendre polynomials (Appendix A):
+ *   mu[k] = (1/nvec) sum_l v_l^T L_k(B) v_l / n,   k = 0..M,
+ * for the same probes, bounds, options, layouts and errors as kpm_moments
+ * (mu_per_vec nullable, [nvec x (M+1)]).  They are computed from the
+ * Chebyshev moments of the fused step (ceil(M/2) sparse products per
+ * probe block) through L_n = sum_{k <= n/2} (2 - [n = 2k]) a_k a_{n-k} T_{n-2k},
+ * a_m = (2m)!/(4^m (m!)^2): non-negative weights summing to 1, so the
+ * result carries the Chebyshev moments' accuracy (FP32 path 1e-5, FP64 path
+ * 1e-12).  The paper's Legendre recurrence, one sparse product per moment,
+ * runs in the fused step instead with KPM_FLAG_LEGENDRE_RECURRENCE.
+ */
+kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
+                                const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
 
 /*
  * kpm_autotune -- choose the device geometry of kpm_moments for A by
@@ -243,6 +263,36 @@ kpm_status kpm_dos(kpm_ctx* ctx, const double* mu, const double* g, int M, doubl
  */
 kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb,
                         double ub, const double* edges, int nbins, double* mass);
+
+/*
+ * kpm_dgl_dos -- the Delta-Gauss-Legendre density (section 3.1.3, eq.
+ * (dglexpansion)): at each point x_i (host, A's units),
+ *   phi(x_i) = sum_{k <= m_i} (k + 1/2) gamma_k(t_i) mu_k / sqrt(2 pi s^2) / d,
+ * t_i = (x_i - c)/d, s = sigma/d, with gamma_k(t) = int_{-1}^{1} L_k(u)
+ * exp(-((u - t)/s)^2 / 2) du (eq. (DGLcoeff)) from the recurrence of eq.
+ * (Leg3) started at gamma_0 of eq. (gam0), and m_i the first k >= 1 with
+ * |gamma_{k-1}| + |gamma_k| <= k tol (eq. (StopRecur); the paper suggests
+ * tol = 1e-6), at most M.  mu: host [M+1] Legendre moments from
+ * kpm_legendre_moments; sigma: Gaussian width in A's units (the density
+ * approximated is the Gaussian-regularised one of eq. (blurphi)); phi host
+ * [npts]; degree_used (nullable) host int [npts] = m_i.  The recurrence
+ * amplifies rounding noise once the coefficients have decayed; since
+ * |gamma_k| <= gamma_0 holds exactly, a computed coefficient beyond it is
+ * reported as KPM_ERR_NOCONV (tol too small).  KPM_ERR_ARG for sigma <= 0,
+ * tol < 0, lb >= ub.
+ */
+kpm_status kpm_dgl_dos(kpm_ctx* ctx, const double* mu, int M, double lb, double ub, double sigma, double tol,
+                       const double* x, int npts, double* phi, int* degree_used);
+
+/*
+ * kpm_legendre_dos -- KPM with Legendre polynomials (Appendix A): the
+ * expansion of the density in the basis orthogonal for the unit weight,
+ *   phi(x) = sum_{k <= M} (k + 1/2) g_k mu_k L_k(t) / d,   t = (x - c)/d,
+ * 0 for |t| > 1.  mu: host [M+1] Legendre moments; g: host [M+1] damping
+ * factors or NULL (none); x, phi host [npts], A's units.
+ */
+kpm_status kpm_legendre_dos(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb, double ub,
+                            const double* x, int npts, double* phi);
 
 /*
  * kpm_slq -- the stochastic Lanczos method of section 3.2.1.  For every probe

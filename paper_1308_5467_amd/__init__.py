@@ -29,7 +29,8 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
-    "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_autotune", "kpm_autotune_batched",
+    "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
+    "kpm_legendre_dos", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -84,6 +85,9 @@ def load_library(path: str = LIB_PATH):
         "kpm_autotune_batched": ([P, I32, P, P, P, P, P, P], I32),
         "kpm_slq_dos": ([P, P, P, I32, I32, D, P, I32, P], I32),
         "kpm_haydock_dos": ([P, P, P, P, I32, I32, D, D, D, P, I32, P], I32),
+        "kpm_legendre_moments": ([P, P, D, D, P, P, P], I32),
+        "kpm_dgl_dos": ([P, P, I32, D, D, D, D, P, I32, P, P], I32),
+        "kpm_legendre_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
@@ -228,6 +232,7 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
 
 
 KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8, KPM_FLAG_GATHER7 = 1, 2, 4, 8
+KPM_FLAG_LEGENDRE_RECURRENCE = 16
 
 
 def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
@@ -254,6 +259,46 @@ def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: 
                              _p(pv) if pv is not None else None)
     ctx.check(st)
     return (mu, pv) if per_vector else mu
+
+
+def kpm_legendre_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
+                         precision="f32", block: int = 0, validate: bool = True, per_vector: bool = False,
+                         rows_per_block: int = 0, recurrence: bool = False):
+    """Normalised Legendre moments mu[0..M] (tr L_k(B)/n estimates); with
+    recurrence=True by the Legendre three-term recurrence in the fused step."""
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block,
+              KPM_FLAG_LEGENDRE_RECURRENCE if recurrence else 0)
+    mu = np.zeros(M + 1)
+    pv = np.zeros((nvec, M + 1)) if per_vector else None
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_legendre_moments(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), _p(mu),
+                                           _p(pv) if pv is not None else None))
+    return (mu, pv) if per_vector else mu
+
+
+def kpm_dgl_dos(ctx: Context, mu, lb: float, ub: float, sigma: float, x, tol: float = 1e-6):
+    """Delta-Gauss-Legendre density at x (A's units) from Legendre moments;
+    returns (phi, degree used per point)."""
+    m = _f64(mu)
+    x = _f64(x)
+    phi = np.zeros(x.size)
+    deg = np.zeros(x.size, dtype=np.int32)
+    ctx.check(ctx.lib.kpm_dgl_dos(ctx.handle, _p(m), m.size - 1, lb, ub, sigma, tol, _p(x), x.size, _p(phi),
+                                  deg.ctypes.data_as(ctypes.c_void_p)))
+    return phi, deg
+
+
+def kpm_legendre_dos(ctx: Context, mu, lb: float, ub: float, x, g=None) -> np.ndarray:
+    """KPM-Legendre density at x (A's units); g = damping factors or None."""
+    m = _f64(mu)
+    gg = None if g is None else _f64(g)
+    if gg is not None and gg.size != m.size:
+        raise ValueError("g must have the length of mu")
+    x = _f64(x)
+    phi = np.zeros(x.size)
+    ctx.check(ctx.lib.kpm_legendre_dos(ctx.handle, _p(m), _p(gg) if gg is not None else None, m.size - 1, lb, ub,
+                                       _p(x), x.size, _p(phi)))
+    return phi
 
 
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",

@@ -383,8 +383,10 @@ static int default_block(int nvec, int precision) {
     return std::min(nvec, std::min(maxb, 64));
 }
 
-extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
-                                  const kpm_moment_opts* o, double* mu, double* mu_per_vec) {
+// Chebyshev moments, or (legendre) the Legendre moments obtained from them
+// by the non-negative Chebyshev-to-Legendre weights on the device.
+static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
+                               const kpm_moment_opts* o, double* mu, double* mu_per_vec, bool legendre) {
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
     if (!o || !mu) return kpm_fail(ctx, KPM_ERR_ARG, "opts or mu is NULL");
@@ -407,7 +409,10 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     const double alpha = 2.0 / d, beta = -2.0 * c / d;
     const int M = o->M, nvec = o->nvec;
     const int b = o->block > 0 ? std::min(o->block, nvec) : default_block(nvec, o->precision);
-    const int K = (M + 1) / 2;  // ceil(M/2) sparse products per block
+    // ceil(M/2) sparse products per block with the product identity; M for
+    // the Legendre recurrence, which has none.
+    const bool leg_rec = legendre && (o->flags & KPM_FLAG_LEGENDRE_RECURRENCE);
+    const int K = leg_rec ? M : (M + 1) / 2;
     const int esz = o->precision == KPM_FP64 ? 8 : 4;
     BlockGeom g = make_geom(A.n, b, o->precision, o->rows_per_block);
     if (o->flags & KPM_FLAG_GATHER4) g.gather = 4;
@@ -423,6 +428,9 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
     if ((st = kpm_ws(ctx, "dots", (size_t)std::max(K, 1) * 2 * g.ld * 8, &dots)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "zeta", (size_t)nvec * (M + 1) * 8, &zeta)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "mu", (size_t)(M + 1) * 8, &mud)) != KPM_OK) return st;
+    void* sgn = nullptr;
+    const int sw = (g.ld + 31) / 32;
+    if (leg_rec && (st = kpm_ws(ctx, "sign_bits", (size_t)A.n * sw * 4, &sgn)) != KPM_OK) return st;
 
     const int nblk_vec = (nvec + b - 1) / b;
     for (int blk = 0; blk < nblk_vec; ++blk) {
@@ -435,6 +443,9 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
         const int gridb = ncols == b ? grid : cheb_step_grid(A, o->precision, gb);
         const int64_t vec0 = (int64_t)blk * b;
         KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
+        const int swb = (gb.ld + 31) / 32;
+        if (leg_rec)
+            KPM_HIP(ctx, launch_sign_pack(ctx->stream, X0, o->precision, A.n, gb.ld, swb, (uint32_t*)sgn));
         void* X[2] = {X0, X1};
         for (int s = 0; s < K; ++s) {
             double* ps = (double*)part + (size_t)s * gridb * 2 * gb.ld;
@@ -444,23 +455,49 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
             if (s == 1) kpm_prof_begin(ctx, "cheb_step");
             // Odd steps walk the panels backwards: they start on the rows
             // the previous step finished with, still in the XCD's L2.
-            KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, gridb, X[s & 1],
-                                          X[(s + 1) & 1], alpha, beta, ps, (s & 1) != 0));
+            if (leg_rec && s > 0) {
+                // v_{s+1} = (2s+1)/(s+1) B v_s - s/(s+1) v_{s-1}, B = (A - cI)/d
+                const double r = (double)(2 * s + 1) / (double)(s + 1);
+                const LegStep ls{-(double)s / (double)(s + 1), (const uint32_t*)sgn, swb};
+                KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, false, gb, gridb, X[s & 1],
+                                              X[(s + 1) & 1], r / d, -r * c / d, ps, (s & 1) != 0, &ls));
+            } else {
+                KPM_HIP(ctx, launch_cheb_step(ctx->stream, A, o->precision, s == 0, gb, gridb, X[s & 1],
+                                              X[(s + 1) & 1], alpha, beta, ps, (s & 1) != 0));
+            }
             if (s == 0) kpm_prof_end(ctx, "cheb_first", 1);
             if (s == K - 1 && K > 1) kpm_prof_end(ctx, "cheb_step", K - 1);
         }
         KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gridb, 2 * gb.ld, K, (double*)dots));
-        KPM_HIP(ctx, launch_assemble(ctx->stream, (double*)dots, K, gb.ld, ncols, M, (double)A.n, vec0,
-                                     (double*)zeta));
+        if (leg_rec)
+            KPM_HIP(ctx, launch_legendre_assemble(ctx->stream, (double*)dots, gb.ld, ncols, M, (double)A.n, vec0,
+                                                  (double*)zeta));
+        else
+            KPM_HIP(ctx, launch_assemble(ctx->stream, (double*)dots, K, gb.ld, ncols, M, (double)A.n, vec0,
+                                         (double*)zeta));
     }
-    KPM_HIP(ctx, launch_mean_moments(ctx->stream, (double*)zeta, nvec, M, (double*)mud));
+    void* zout = zeta;
+    std::vector<double> aw;
+    if (legendre && !leg_rec) {
+        void *zl, *ad;
+        if ((st = kpm_ws(ctx, "zeta_leg", (size_t)nvec * (M + 1) * 8, &zl)) != KPM_OK) return st;
+        if ((st = kpm_ws(ctx, "leg_a", (size_t)(M + 1) * 8, &ad)) != KPM_OK) return st;
+        aw.resize((size_t)M + 1);
+        legendre_connection_weights(M, aw.data());
+        KPM_HIP(ctx, hipMemcpyAsync(ad, aw.data(), aw.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+        KPM_HIP(ctx, launch_cheb_to_legendre(ctx->stream, (const double*)zeta, nvec, M, (const double*)ad,
+                                             (double*)zl));
+        zout = zl;
+    }
+    KPM_HIP(ctx, launch_mean_moments(ctx->stream, (double*)zout, nvec, M, (double*)mud));
     KPM_HIP(ctx, hipMemcpyAsync(mu, mud, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
     std::vector<double>& hz = ctx->host_scratch;
     hz.resize((size_t)nvec * (M + 1));
-    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), zeta, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), zout, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;
     if (mu_per_vec) memcpy(mu_per_vec, hz.data(), hz.size() * 8);
-    // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1].
+    // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1]
+    // (and so |v^T L_k(B) v| <= n, a convex combination of those).
     const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
     for (size_t i = 0; i < hz.size(); ++i) {
         if (!isfinite(hz[i]) || fabs(hz[i]) > 1.0 + tol) {
@@ -472,6 +509,16 @@ extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* Ain, double lb, d
         }
     }
     return KPM_OK;
+}
+
+extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
+                                  const kpm_moment_opts* o, double* mu, double* mu_per_vec) {
+    return moments_impl(ctx, A, lb, ub, o, mu, mu_per_vec, false);
+}
+
+extern "C" kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
+                                           const kpm_moment_opts* o, double* mu, double* mu_per_vec) {
+    return moments_impl(ctx, A, lb, ub, o, mu, mu_per_vec, true);
 }
 
 // ---------------------------------------------------------------- autotuner

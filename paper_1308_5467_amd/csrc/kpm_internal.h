@@ -42,9 +42,31 @@ hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int nco
                              int64_t n, int precision, int zero_pad, void* out);
 // Workgroups every step launch of this geometry uses (= partial rows per step).
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g);
+// Legendre moments from Chebyshev moments: a[0..M] connection weights
+// (host), then per probe row zetaL[n] = sum_k (2 - [n = 2k]) a_k a_{n-k} zeta[n-2k].
+void legendre_connection_weights(int M, double* a);
+hipError_t launch_cheb_to_legendre(hipStream_t s, const double* zeta, int nvec, int M, const double* a,
+                                   double* out);
+// Sign bits of a probe block v_0 (FP32 or FP64 values, [n][ld]) into
+// [n][sw] words, sw = (ld + 31) / 32.
+hipError_t launch_sign_pack(hipStream_t s, const void* V0, int precision, int64_t n, int ld, int sw,
+                            uint32_t* out);
+// Per-probe normalised Legendre moments of one probe block from the reduced
+// dots of the Legendre recurrence: zeta[(vec0 + j) * (M+1) + k] = 1 for
+// k = 0, dots[(k-1) * 2 ld + j] / n for k = 1..M.
+hipError_t launch_legendre_assemble(hipStream_t s, const double* dots, int ld, int ncols, int M, double n,
+                                    int64_t vec0, double* zeta);
+// Legendre step of Algorithm DGL (with a non-null LegStep and first ==
+// false): U <- alpha A V + beta V + gam U, first dot against v_0 given by
+// its sign bits sgn ([n][sw] words).
+struct LegStep {
+    double gam;
+    const uint32_t* sgn;
+    int sw;
+};
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
                             const BlockGeom& g, int grid, const void* V, void* U, double alpha,
-                            double beta, double* partial, bool reverse);
+                            double beta, double* partial, bool reverse, const LegStep* leg = nullptr);
 hipError_t launch_reduce_partials(hipStream_t s, const double* partial, int nblocks, int width,
                                   int K, double* dots);
 hipError_t launch_assemble(hipStream_t s, const double* dots, int K, int ld, int ncols, int M,

@@ -108,6 +108,10 @@ struct StepParams {
     double alpha, beta;
     int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
     int32_t reverse;  // walk each XCD's panel range from its end
+    // Legendre step only: coefficient of v_{k-1}, sign bits of v_0
+    double gam;
+    const uint32_t* sgn;
+    int32_t sw;
 };
 
 // Fused step.  The grid is sized to the number of workgroups that fit on
@@ -124,7 +128,10 @@ struct StepParams {
 // probe column at the end; the grid size and the panel-to-workgroup map are
 // fixed for a device and direction, so results are bitwise reproducible run
 // to run.
-template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
+//
+// LEG: the Legendre step of Algorithm DGL, U <- alpha A V + beta V + gam U,
+// whose first dot is taken against v_0 (its sign bits) instead of V.
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G, bool LEG = false>
 __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     constexpr int N = Pack<TV>::N;
     constexpr int kLdsDoubles = kWaves * 64 * 2 * N;
@@ -165,13 +172,15 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
     double sx[N], ss[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) sx[e] = ss[e] = 0.0;
+    const LegArgs leg{p.sgn, p.sw, coff >> 5, coff & 31, p.gam};
 
     for (int q = first; q < p_end; q += p_stride) {
         const int panel = p.reverse ? p_begin + p_end - 1 - q : q;
         const int r0 = panel * p.rows_per_block;
         const int r1 = min(p.n, r0 + p.rows_per_block);
-        process_panel<TA, TV, FIRST, OFF32, G>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha, p.beta, p.stage,
-                                               smem, lane_on, wave, rw, p.rpw, sx, ss);
+        process_panel<TA, TV, FIRST, OFF32, G, kLdsDoubles, LEG>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha,
+                                                                 p.beta, p.stage, smem, lane_on, wave, rw, p.rpw, sx,
+                                                                 ss, &leg);
     }
 
     // One partial per workgroup: the lanes' sums over every row they
@@ -264,9 +273,9 @@ static int grid_of(int npanels) {
     return grid;
 }
 
-template <typename TA, typename TV, bool FIRST, bool OFF32, int G>
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G, bool LEG = false>
 static hipError_t launch_step_variant(hipStream_t s, const StepParams& p, int grid) {
-    cheb_step_kernel<TA, TV, FIRST, OFF32, G><<<grid, kThreads, 0, s>>>(p);
+    cheb_step_kernel<TA, TV, FIRST, OFF32, G, LEG><<<grid, kThreads, 0, s>>>(p);
     return hipGetLastError();
 }
 
@@ -296,7 +305,7 @@ int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g) {
 
 hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool first,
                             const BlockGeom& g, int grid, const void* V, void* U, double alpha,
-                            double beta, double* partial, bool reverse) {
+                            double beta, double* partial, bool reverse, const LegStep* leg) {
     StepParams p;
     p.rp = A.rp;
     p.ci = A.ci;
@@ -314,11 +323,18 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.npanels = g.nblocks;
     p.stage = tune().stage;
     p.reverse = reverse && tune().rev;
+    p.gam = leg ? leg->gam : 0.0;
+    p.sgn = leg ? leg->sgn : nullptr;
+    p.sw = leg ? leg->sw : 0;
+    const bool lg = leg != nullptr && !first;
     const bool off32 = step_off32(A, g, precision);
-#define KPM_STEP_G(TA, TV, GG)                                                                   \
-    return off32 ? (first ? launch_step_variant<TA, TV, true, true, GG>(s, p, grid)              \
-                          : launch_step_variant<TA, TV, false, true, GG>(s, p, grid))            \
-                 : (first ? launch_step_variant<TA, TV, true, false, GG>(s, p, grid)             \
+#define KPM_STEP_G(TA, TV, GG)                                                                             \
+    if (lg)                                                                                                \
+        return off32 ? launch_step_variant<TA, TV, false, true, GG, true>(s, p, grid)                      \
+                     : launch_step_variant<TA, TV, false, false, GG, true>(s, p, grid);                    \
+    return off32 ? (first ? launch_step_variant<TA, TV, true, true, GG>(s, p, grid)                        \
+                          : launch_step_variant<TA, TV, false, true, GG>(s, p, grid))                      \
+                 : (first ? launch_step_variant<TA, TV, true, false, GG>(s, p, grid)                       \
                           : launch_step_variant<TA, TV, false, false, GG>(s, p, grid))
 #define KPM_STEP_DISPATCH(TA, TV)    \
     if (g.gather == 4) {             \

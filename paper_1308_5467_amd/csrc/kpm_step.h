@@ -1,7 +1,8 @@
 // Device code shared by the single-matrix and the batched step kernels:
 // probe signs, the XCD-aware workgroup map, vector packs, and the fused
 // per-row / per-panel Chebyshev step (Lin, Saad & Yang, eq. (3term) with
-// the product identity of Appendix A).  Included by .hip sources only.
+// the product identity of Appendix A; the Legendre recurrence of Algorithm
+// DGL as a variant).  Included by .hip sources only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -114,6 +115,17 @@ struct CsrPairs {
     }
 };
 
+// Extra arguments of the Legendre step (Algorithm DGL's recurrence
+// v_{k+1} = alpha A v_k + beta v_k + gam v_{k-1}): the coefficient of
+// v_{k-1} and the sign bits of the probe block v_0 ([n][sw] 32-bit words,
+// bit j of word w set when column 32 w + j of the row is -1), against which
+// the moment v_0^T v_{k+1} is accumulated.
+struct LegArgs {
+    const uint32_t* __restrict__ sgn;
+    int sw, sword, sshift;
+    double gam;
+};
+
 // One matrix row of the fused step for the lanes of one row group: gather
 // the CSR row in batches of G entries (one memory round trip for rows of up
 // to G entries), combine, store, and accumulate the two dot products.
@@ -128,17 +140,22 @@ struct CsrPairs {
 // the gathers.  Without staging the index loads share the in-order vector
 // memory counter with them, so the own-row and U loads are issued after the
 // gathers instead.
-template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G, typename E>
+//
+// LEG (not FIRST): the Legendre step; the first dot is then taken against
+// v_0 (from its sign bits) instead of v_k.
+template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G, typename E, bool LEG = false>
 __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, const char* __restrict__ Vb,
                                          char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
                                          double alpha, double beta, double (&sx)[Pack<TV>::N],
-                                         double (&ss)[Pack<TV>::N]) {
+                                         double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr) {
     constexpr int N = Pack<TV>::N;
     const uint64_t orow = voff<OFF32>(row, ldb, coffb);
     TV own[N], u[N];
+    uint32_t bits = 0;
     if (EARLY) {
         Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
         if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        if (LEG) bits = leg->sgn[(int64_t)row * leg->sw + leg->sword] >> leg->sshift;
     }
     TV acc[N];
 #pragma unroll
@@ -168,6 +185,7 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, 
     if (!EARLY) {
         Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
         if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        if (LEG) bits = leg->sgn[(int64_t)row * leg->sw + leg->sword] >> leg->sshift;
     }
     TV out[N];
     if (FIRST) {
@@ -175,6 +193,10 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, 
 #pragma unroll
         for (int e = 0; e < N; ++e)
             out[e] = (TV)fma(0.5 * alpha, (double)acc[e], 0.5 * beta * (double)own[e]);
+    } else if (LEG) {
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], leg->gam * (double)u[e]));
     } else {
 #pragma unroll
         for (int e = 0; e < N; ++e)
@@ -186,7 +208,10 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, 
 #pragma unroll
     for (int e = 0; e < N; ++e) {
         const double o = (double)out[e];
-        sx[e] = fma(o, (double)own[e], sx[e]);
+        if (LEG)
+            sx[e] += ((bits >> e) & 1u) ? -o : o;
+        else
+            sx[e] = fma(o, (double)own[e], sx[e]);
         ss[e] = fma(o, o, ss[e]);
     }
 }
@@ -196,14 +221,14 @@ __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, 
 // and the column indices and values as interleaved pairs) is first copied
 // to LDS with coalesced loads, so each row costs one round of independent
 // gathers.  The dots are added to the caller's per-lane accumulators sx/ss.
-template <typename TA, typename TV, bool FIRST, bool OFF32, int G, int LDS_DOUBLES>
+template <typename TA, typename TV, bool FIRST, bool OFF32, int G, int LDS_DOUBLES, bool LEG = false>
 __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __restrict__ rp,
                                               const int32_t* __restrict__ ci, const TA* __restrict__ val,
                                               const char* __restrict__ Vb, char* __restrict__ Ub, uint32_t ldb,
                                               uint32_t coffb, double alpha, double beta, int stage,
                                               double (&smem)[LDS_DOUBLES], bool lane_on, int wave, int rw,
                                               int rpw, double (&sx)[Pack<TV>::N],
-                                              double (&ss)[Pack<TV>::N]) {
+                                              double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr) {
     const int pass_rows = kWaves * rpw;
     // Staging layout in LDS: [row offsets (R+1) x 4 bytes, padded to 16]
     // [(index, value) pairs pnnz x sizeof(CsrPair<TA>)].
@@ -226,16 +251,16 @@ __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __r
             const CsrPairs<TA> csr{s_e};
             for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows) {
                 const int lr = row - r0;
-                step_row<TA, TV, FIRST, true, OFF32, G>(row, s_rp[lr], s_rp[lr + 1], csr, Vb, Ub, ldb, coffb, alpha,
-                                                        beta, sx, ss);
+                step_row<TA, TV, FIRST, true, OFF32, G, CsrPairs<TA>, LEG>(row, s_rp[lr], s_rp[lr + 1], csr, Vb, Ub,
+                                                                           ldb, coffb, alpha, beta, sx, ss, leg);
             }
         }
         __syncthreads();  // before the LDS is restaged or reused
     } else if (lane_on) {
         const CsrArrays<TA> csr{ci, val};
         for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows)
-            step_row<TA, TV, FIRST, false, OFF32, G>(row, rp[row], rp[row + 1], csr, Vb, Ub, ldb, coffb, alpha,
-                                                     beta, sx, ss);
+            step_row<TA, TV, FIRST, false, OFF32, G, CsrArrays<TA>, LEG>(row, rp[row], rp[row + 1], csr, Vb, Ub,
+                                                                         ldb, coffb, alpha, beta, sx, ss, leg);
     }
 }
 
