@@ -27,7 +27,10 @@ densities of large matrices" in plain numpy / C, in the paper's order:
   Lanczos matrices (``slq.py``);
 * ``legendre_*``, ``dgl_*`` -- Legendre moments, KPM with Legendre
   polynomials and the Delta-Gauss-Legendre method (section 3.1.3,
-  Appendix B) (``dgl.py``).
+  Appendix B) (``dgl.py``);
+* ``functional_*``, ``heat_capacity_g`` -- functionals <phi~, g> of the
+  approximate densities (eq. (errormetric_g)) and the heat capacity of
+  section 4.3 (``functional.py``).
 
 Moments are normalised as mu_hat_k = zeta_k / n (so mu_hat_0 = 1); the
 paper's (2 - delta_k0)/pi factor is applied when the density is evaluated.
@@ -343,3 +346,5 @@ from .slq import (lanczos_tridiag, lanczos_nodes, lanczos_dos, quadrature_moment
                   steps_used as lanczos_steps_used, haydock_dos, lorentz)
 from .dgl import (legendre_moments, legendre_moments_per_vector, dgl_gamma, dgl_dos,  # noqa: E402
                   legendre_dos)
+from .functional import (heat_capacity_g, functional_exact, functional_kpm,  # noqa: E402
+                         functional_lanczos)
