@@ -327,10 +327,18 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
     sigma = 0.02 * 0.5 * (ub - lb)
     t_dgl = _time_ms(lambda: kpm.kpm_dgl_dos(ctx, mu, lb, ub, sigma, x), reps)
     _, deg = kpm.kpm_dgl_dos(ctx, mu, lb, ub, sigma, x)
+    # heat capacity of section 4.3 (eq. (gfunc)) at 50 temperatures from the
+    # Chebyshev moments of the same run, Jackson-damped
+    muT = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision, block=args.block,
+                          validate=False)
+    gJ = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
+    temps = np.geomspace(0.05, 5.0, 50)
+    t_cv = _time_ms(lambda: kpm.kpm_heat_capacity(ctx, muT, lb, ub, temps, g=gJ), reps)
     return {"M": M, "nvec": nvec, "precision": args.precision,
             "ms_moments_converted": round(t_conv, 3), "ms_moments_recurrence": round(t_rec, 3),
             "speedup_converted": round(t_rec / t_conv, 2), "max_abs_diff_routes": diff,
-            "ms_dgl_density": round(t_dgl, 3), "dgl_degree_min_max": [int(deg.min()), int(deg.max())]}
+            "ms_dgl_density": round(t_dgl, 3), "dgl_degree_min_max": [int(deg.min()), int(deg.max())],
+            "ms_heat_capacity_50_temperatures": round(t_cv, 3)}
 
 
 def autotune_leg(kpm, ctx, D, lb, ub, args, roof):

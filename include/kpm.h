@@ -354,6 +354,43 @@ kpm_status kpm_haydock_dos(kpm_ctx* ctx, const double* alpha, const double* beta
                            double* phi);
 
 /*
+ * kpm_functional -- <phi~, f> = int f(lambda) phi~(lambda) dlambda for the
+ * KPM density of eq. (tdosFinal) with damping g (host [M+1] or NULL = none)
+ * and normalised Chebyshev moments mu (host [M+1]), the quantity compared
+ * in the functional error of eq. (errormetric_g).  The integral is taken
+ * in theta = arccos t by Gauss-Chebyshev quadrature on Q nodes:
+ *   out = (1/Q) sum_q fvals[q] D(theta_q),  theta_q = (q + 1/2) pi / Q,
+ *   D(theta) = sum_k (2 - [k = 0]) g_k mu_k cos(k theta),
+ * where fvals[q] = f(c + d cos theta_q) (host [Q], A's units, c = (lb+ub)/2,
+ * d = (ub-lb)/2) are the caller's samples of f.  Exact for polynomial f of
+ * degree < 2Q - M; geometric convergence in Q for f analytic on [lb, ub].
+ * out: one double (host).
+ */
+kpm_status kpm_functional(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb, double ub,
+                          const double* fvals, int Q, double* out);
+
+/*
+ * kpm_heat_capacity -- section 4.3: C_v(T_j) = <phi~, g_T> for the KPM
+ * density as in kpm_functional, with g_T of eq. (gfunc) in units where
+ * k_B = 1 and hbar c / k_B = 1, as a function of lambda = omega^2:
+ *   g_T(lambda) = x^2 e^{-x} / (1 - e^{-x})^2 = (x / (2 sinh(x/2)))^2,
+ *   x = sqrt(lambda) / T,   g_T = 1 for lambda <= 0,
+ * evaluated on the device at the Q nodes (Q = 0: max(1024, 4(M+1))).
+ * T host [nT] (> 0), cv host [nT].
+ */
+kpm_status kpm_heat_capacity(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb, double ub,
+                             const double* T, int nT, int Q, double* cv);
+
+/*
+ * kpm_slq_heat_capacity -- the same heat capacity for the Lanczos density,
+ * with g_T in place of the Gaussian of eq. (landos) (section 4.3):
+ *   cv[j] = (1/nvec) sum_l sum_k tau2[l*M+k] g_T(theta[l*M+k]),
+ * theta, tau2 host [nvec * M] as written by kpm_slq.
+ */
+kpm_status kpm_slq_heat_capacity(kpm_ctx* ctx, const double* theta, const double* tau2, int nvec, int M,
+                                 const double* T, int nT, double* cv);
+
+/*
  * kpm_tridiag_eig -- host-only helper (no device work): eigenvalues theta
  * (ascending) and squared first eigenvector components tau2 of the
  * symmetric tridiagonal matrix with diagonal alpha[0..m-1] and off-diagonal

@@ -30,7 +30,7 @@ EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
-    "kpm_legendre_dos", "kpm_autotune", "kpm_autotune_batched",
+    "kpm_legendre_dos", "kpm_functional", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -88,6 +88,9 @@ def load_library(path: str = LIB_PATH):
         "kpm_legendre_moments": ([P, P, D, D, P, P, P], I32),
         "kpm_dgl_dos": ([P, P, I32, D, D, D, D, P, I32, P, P], I32),
         "kpm_legendre_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_functional": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_heat_capacity": ([P, P, P, I32, D, D, P, I32, I32, P], I32),
+        "kpm_slq_heat_capacity": ([P, P, P, I32, I32, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
@@ -299,6 +302,50 @@ def kpm_legendre_dos(ctx: Context, mu, lb: float, ub: float, x, g=None) -> np.nd
     ctx.check(ctx.lib.kpm_legendre_dos(ctx.handle, _p(m), _p(gg) if gg is not None else None, m.size - 1, lb, ub,
                                        _p(x), x.size, _p(phi)))
     return phi
+
+
+def chebyshev_nodes(Q: int, lb: float, ub: float) -> np.ndarray:
+    """The Q quadrature nodes of kpm_functional on A's axis: c + d cos((q + 1/2) pi / Q)."""
+    c, d = 0.5 * (lb + ub), 0.5 * (ub - lb)
+    return c + d * np.cos((np.arange(Q) + 0.5) * np.pi / Q)
+
+
+def kpm_functional(ctx: Context, mu, lb: float, ub: float, f, Q: int = 1024, g=None) -> float:
+    """<phi~, f> of the KPM density; f is a callable evaluated (on the host)
+    at the Q quadrature nodes, or an array of its values there."""
+    m = _f64(mu)
+    fv = _f64(f(chebyshev_nodes(Q, lb, ub)) if callable(f) else f)
+    if fv.size != Q:
+        raise ValueError("need one value of f per node")
+    gg = None if g is None else _f64(g)
+    out = np.zeros(1)
+    ctx.check(ctx.lib.kpm_functional(ctx.handle, _p(m), _p(gg) if gg is not None else None, m.size - 1, lb, ub,
+                                     _p(fv), Q, _p(out)))
+    return float(out[0])
+
+
+def kpm_heat_capacity(ctx: Context, mu, lb: float, ub: float, T, g=None, Q: int = 0) -> np.ndarray:
+    """C_v(T) = <phi~, g_T> of the KPM density (section 4.3)."""
+    m = _f64(mu)
+    t = _f64(T)
+    gg = None if g is None else _f64(g)
+    cv = np.zeros(t.size)
+    ctx.check(ctx.lib.kpm_heat_capacity(ctx.handle, _p(m), _p(gg) if gg is not None else None, m.size - 1, lb, ub,
+                                        _p(t), t.size, Q, _p(cv)))
+    return cv
+
+
+def kpm_slq_heat_capacity(ctx: Context, theta, tau2, T) -> np.ndarray:
+    """C_v(T) for the Lanczos density from kpm_slq's nodes and weights."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    w = np.ascontiguousarray(tau2, dtype=np.float64)
+    if th.ndim != 2 or th.shape != w.shape:
+        raise ValueError("theta and tau2 must be [nvec, M] arrays of the same shape")
+    t = _f64(T)
+    cv = np.zeros(t.size)
+    ctx.check(ctx.lib.kpm_slq_heat_capacity(ctx.handle, _p(th), _p(w), th.shape[0], th.shape[1], _p(t), t.size,
+                                            _p(cv)))
+    return cv
 
 
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",
