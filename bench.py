@@ -322,6 +322,18 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
 
     t_conv = _time_ms(lambda: run(False), reps)
     t_rec = _time_ms(lambda: run(True), reps)
+    # the Legendre step kernel (the recurrence route) against the HBM roofline:
+    # the Chebyshev step's algorithmic bytes plus the probe block's sign bits
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    run(True)
+    kpm.kpm_profile_enable(ctx, False)
+    nl, ms_steps = kpm.kpm_profile_query(ctx, "cheb_step")
+    s_v = 4 if args.precision == "f32" else 8
+    b = min(args.block, nvec)
+    leg_bytes = (s_v + 4) * D.nnz + 4 * (D.n + 1) + 3 * s_v * D.n * b + 4 * D.n * ((b + 31) // 32)
+    us_leg = ms_steps / max(nl, 1) * 1000.0
+    leg_gbs = leg_bytes / (us_leg * 1e-6) / 1e9
     mu = run(False)
     diff = float(np.max(np.abs(mu - run(True))))
     sigma = 0.02 * 0.5 * (ub - lb)
@@ -337,6 +349,8 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
     return {"M": M, "nvec": nvec, "precision": args.precision,
             "ms_moments_converted": round(t_conv, 3), "ms_moments_recurrence": round(t_rec, 3),
             "speedup_converted": round(t_rec / t_conv, 2), "max_abs_diff_routes": diff,
+            "legendre_step_us": round(us_leg, 2), "legendre_step_algorithmic_bytes": int(leg_bytes),
+            "legendre_step_frac_of_hbm_peak": round(leg_gbs / HBM_PEAK_GBS, 4),
             "ms_dgl_density": round(t_dgl, 3), "dgl_degree_min_max": [int(deg.min()), int(deg.max())],
             "ms_heat_capacity_50_temperatures": round(t_cv, 3)}
 

@@ -445,7 +445,7 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
         KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
         const int swb = (gb.ld + 31) / 32;
         if (leg_rec)
-            KPM_HIP(ctx, launch_sign_pack(ctx->stream, X0, o->precision, A.n, gb.ld, swb, (uint32_t*)sgn));
+            KPM_HIP(ctx, launch_sign_bits(ctx->stream, o->seed, vec0, ncols, A.n, swb, (uint32_t*)sgn));
         void* X[2] = {X0, X1};
         for (int s = 0; s < K; ++s) {
             double* ps = (double*)part + (size_t)s * gridb * 2 * gb.ld;

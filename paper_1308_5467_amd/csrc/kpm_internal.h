@@ -47,9 +47,9 @@ int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g);
 void legendre_connection_weights(int M, double* a);
 hipError_t launch_cheb_to_legendre(hipStream_t s, const double* zeta, int nvec, int M, const double* a,
                                    double* out);
-// Sign bits of a probe block v_0 (FP32 or FP64 values, [n][ld]) into
-// [n][sw] words, sw = (ld + 31) / 32.
-hipError_t launch_sign_pack(hipStream_t s, const void* V0, int precision, int64_t n, int ld, int sw,
+// Sign bits of probes vec0 .. vec0+ncols-1 of `seed` into [n][sw] words
+// (bit j of word w: entry of probe vec0 + 32 w + j is -1).
+hipError_t launch_sign_bits(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t n, int sw,
                             uint32_t* out);
 // Per-probe normalised Legendre moments of one probe block from the reduced
 // dots of the Legendre recurrence: zeta[(vec0 + j) * (M+1) + k] = 1 for

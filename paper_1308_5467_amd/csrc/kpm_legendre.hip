@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "kpm_internal.h"
+#include "kpm_step.h"
 
 namespace kpm {
 namespace {
@@ -121,19 +122,19 @@ __global__ __launch_bounds__(256) void legendre_dos_kernel(const double* __restr
     phi[i] = acc / d;
 }
 
-// One thread per (row, word): bit j of word w is set when column 32 w + j
-// of the row is negative.
-template <typename TV>
-__global__ __launch_bounds__(256) void sign_pack_kernel(const TV* __restrict__ V0, int64_t n, int ld, int sw,
+// One thread per (row, word): bit j of word w is set when entry `row` of
+// probe vec0 + 32 w + j is -1, from the probes' generator itself (the same
+// signs the block fill writes), so the block is not read back.
+__global__ __launch_bounds__(256) void sign_bits_kernel(uint64_t seed, int64_t vec0, int ncols, int64_t n, int sw,
                                                         uint32_t* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= n * sw) return;
     const int64_t row = t / sw;
     const int w = (int)(t - row * sw);
-    const int c0 = w * 32, c1 = std::min(ld, c0 + 32);
+    const int c0 = w * 32, c1 = std::min(ncols, c0 + 32);
     uint32_t bits = 0;
     for (int cidx = c0; cidx < c1; ++cidx)
-        if (V0[row * ld + cidx] < (TV)0) bits |= 1u << (cidx - c0);
+        if (rademacher_sign(seed, (uint64_t)(vec0 + cidx), (uint64_t)row) < 0.0f) bits |= 1u << (cidx - c0);
     out[t] = bits;
 }
 
@@ -147,15 +148,11 @@ __global__ __launch_bounds__(256) void legendre_assemble_kernel(const double* __
 
 }  // namespace
 
-hipError_t launch_sign_pack(hipStream_t s, const void* V0, int precision, int64_t n, int ld, int sw,
+hipError_t launch_sign_bits(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t n, int sw,
                             uint32_t* out) {
     const int64_t tot = n * sw;
-    const unsigned grid = (unsigned)((tot + 255) / 256);
     if (tot == 0) return hipSuccess;
-    if (precision == KPM_FP64)
-        sign_pack_kernel<double><<<grid, 256, 0, s>>>((const double*)V0, n, ld, sw, out);
-    else
-        sign_pack_kernel<float><<<grid, 256, 0, s>>>((const float*)V0, n, ld, sw, out);
+    sign_bits_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(seed, vec0, ncols, n, sw, out);
     return hipGetLastError();
 }
 
