@@ -112,13 +112,13 @@ template <typename T>
 __global__ void batched_fill_kernel(const BatchMvDev* __restrict__ mvs, int ld) {
     const BatchMvDev& mv = mvs[blockIdx.y];
     T* out = reinterpret_cast<T*>(mv.X0);
-    const int64_t total = (int64_t)mv.n * ld;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx / ld;
-        const int64_t j = idx - i * ld;
-        out[idx] = j < mv.ncols ? (T)rademacher_sign(mv.seed, (uint64_t)(mv.vec0 + j), (uint64_t)i) : (T)0;
-    }
+    // thread t: column t % ld of rows t / ld + k (256 / ld) (ld <= 256)
+    const int rpp = 256 / ld;
+    const int r_in = (int)threadIdx.x / ld;
+    const int j = (int)threadIdx.x - r_in * ld;
+    if (r_in >= rpp) return;
+    for (int64_t i = (int64_t)blockIdx.x * rpp + r_in; i < mv.n; i += (int64_t)gridDim.x * rpp)
+        out[i * ld + j] = j < mv.ncols ? (T)rademacher_sign(mv.seed, (uint64_t)(mv.vec0 + j), (uint64_t)i) : (T)0;
 }
 
 __device__ __forceinline__ void bneumaier(double& s, double& c, double x) {

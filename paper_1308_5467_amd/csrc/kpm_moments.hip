@@ -67,12 +67,28 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
 }
 
 // ---------------------------------------------------------------- probe fill
+// Thread t of a workgroup owns column t % ld of rows t / ld, t / ld + rpp,
+// ... (rpp = 256 / ld rows per pass, ld <= 256): stores are coalesced and
+// no 64-bit division is needed per element.
 template <typename T>
-__global__ void rademacher_fill_kernel(uint64_t seed, int64_t vec0, int ncols, int64_t ld,
-                                       int64_t n, int zero_pad, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void rademacher_fill_kernel(uint64_t seed, int64_t vec0, int ncols, int ld,
+                                                              int64_t n, int zero_pad, T* __restrict__ out) {
+    const int rpp = 256 / ld;
+    const int r_in = (int)threadIdx.x / ld;
+    const int j = (int)threadIdx.x - r_in * ld;
+    if (r_in >= rpp || (j >= ncols && !zero_pad)) return;
+    for (int64_t i = (int64_t)blockIdx.x * rpp + r_in; i < n; i += (int64_t)gridDim.x * rpp)
+        out[i * ld + j] = j < ncols ? (T)rademacher_sign(seed, (uint64_t)(vec0 + j), (uint64_t)i) : (T)0;
+}
+
+// Any leading dimension (the public fill allows ld > 256): one element per
+// thread and pass.
+template <typename T>
+__global__ __launch_bounds__(256) void rademacher_fill_wide_kernel(uint64_t seed, int64_t vec0, int ncols,
+                                                                   int64_t ld, int64_t n, int zero_pad,
+                                                                   T* __restrict__ out) {
     const int64_t total = n * ld;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
         const int64_t i = idx / ld;
         const int64_t j = idx - i * ld;
         if (j < ncols)
@@ -84,15 +100,26 @@ __global__ void rademacher_fill_kernel(uint64_t seed, int64_t vec0, int ncols, i
 
 hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
                              int64_t n, int precision, int zero_pad, void* out) {
-    const int64_t total = n * ld;
-    int64_t blocks = (total + 255) / 256;
+    if (ld < 1) return hipErrorInvalidValue;
+    if (ld > 256) {
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(16384, (n * ld + 255) / 256));
+        if (precision == KPM_FP64)
+            rademacher_fill_wide_kernel<double><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
+                                                                            (double*)out);
+        else
+            rademacher_fill_wide_kernel<float><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
+                                                                           (float*)out);
+        return hipGetLastError();
+    }
+    const int64_t rpp = 256 / ld;
+    int64_t blocks = (n + rpp - 1) / rpp;
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     if (precision == KPM_FP64)
-        rademacher_fill_kernel<double><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
+        rademacher_fill_kernel<double><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, (int)ld, n, zero_pad,
                                                                    (double*)out);
     else
-        rademacher_fill_kernel<float><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
+        rademacher_fill_kernel<float><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, (int)ld, n, zero_pad,
                                                                   (float*)out);
     return hipGetLastError();
 }

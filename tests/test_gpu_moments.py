@@ -48,9 +48,11 @@ def oracle_per_vec(A, lb, ub, M, nvec, seed, vec0=0, dtype="f64"):
 
 # ---------------------------------------------------------------- probe vectors
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_rademacher_bit_exact(ctx, prec):
+@pytest.mark.parametrize("n,nvec,ld", [(1000, 7, 9), (1001, 64, 64), (333, 5, 300)])
+def test_rademacher_bit_exact(ctx, prec, n, nvec, ld):
+    """Leading dimensions below, at and above the 256 columns one fill
+    workgroup covers per row pass."""
     import torch
-    n, nvec, ld = 1000, 7, 9
     out = torch.full((n, ld), 5.0, dtype=torch.float32 if prec == "f32" else torch.float64, device="cuda")
     kpm.kpm_rademacher(ctx, 12345, 3, nvec, n, ld, prec, out)
     got = out.cpu().numpy().astype(np.float64)
