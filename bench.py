@@ -106,6 +106,14 @@ def main():
     kpm.kpm_moments(ctx, D, lb, ub, 2, 1, 2002, precision=args.precision, validate=True)
 
     def step():
+        # bounds -> moments -> Jackson damping -> density, one library call
+        phi, mu, _, _ = kpm.kpm_dos_pipeline(ctx, D, M, nvec, 2002, x, precision=args.precision, block=block,
+                                             damping=kpm.KPM_DAMP_JACKSON, lanczos_steps=20, lanczos_seed=3002,
+                                             margin=0.01, rows_per_block=args.rows_per_block)
+        return mu, phi
+
+    def step_separate():
+        # the same four steps as separate calls (one wait each)
         lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
         mu = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision, block=block,
                              validate=False, rows_per_block=args.rows_per_block)
@@ -124,6 +132,13 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kpm.kpm_profile_enable(ctx, False)
+    step_separate()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step_separate()
+    torch.cuda.synchronize()
+    ms_separate = (time.perf_counter() - t2) * 1000.0 / args.steps
     copy_gbs = kpm.kpm_hbm_copy_probe(ctx, 1 << 30, 10)
     nl, step_ms_total = kpm.kpm_profile_query(ctx, "cheb_step")
     nf, first_ms_total = kpm.kpm_profile_query(ctx, "cheb_first")
@@ -168,6 +183,7 @@ def main():
         "breakdown_ms_per_step": {"cheb_step_total": step_ms_total / args.steps,
                                   "cheb_first": first_ms_total / args.steps,
                                   "lanczos_enqueue_to_done": lz_ms_total / args.steps},
+        "ms_per_step_separate_calls": round(ms_separate, 4),
         "hbm_gbs_whole_step": round(bytes_per_launch * (M + 1) // 2 * nblocks_vec / (ms_per_step * 1e-3) / 1e9, 1),
     }
 

@@ -265,6 +265,21 @@ kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, 
                         double ub, const double* edges, int nbins, double* mass);
 
 /*
+ * kpm_dos_pipeline -- the whole path of section 3.1.1 in one call: the
+ * Lanczos bounds of kpm_bounds (lanczos_steps, lanczos_seed, margin), the
+ * moments of kpm_moments on [lb, ub] (opts), the damping factors of
+ * kpm_damping_factors (damping; KPM_DAMP_LEARNED needs M = 127 and a
+ * loaded network) and the density of kpm_dos at the npts points x (host),
+ * with the results of those calls: phi (host [npts]), mu (host [M+1],
+ * nullable), lb, ub (host).  After the bounds (whose Ritz values are found
+ * on the host) the work is enqueued back to back and waited for once.
+ * Errors as for the four calls.
+ */
+kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lanczos_steps, uint64_t lanczos_seed,
+                            double margin, const kpm_moment_opts* opts, kpm_damping damping, const double* x,
+                            int npts, double* phi, double* mu, double* lb, double* ub);
+
+/*
  * kpm_dgl_dos -- the Delta-Gauss-Legendre density (section 3.1.3, eq.
  * (dglexpansion)): at each point x_i (host, A's units),
  *   phi(x_i) = sum_{k <= m_i} (k + 1/2) gamma_k(t_i) mu_k / sqrt(2 pi s^2) / d,

@@ -30,7 +30,7 @@ EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
-    "kpm_legendre_dos", "kpm_functional", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_autotune", "kpm_autotune_batched",
+    "kpm_legendre_dos", "kpm_functional", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_dos_pipeline", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_dgl_dos": ([P, P, I32, D, D, D, D, P, I32, P, P], I32),
         "kpm_legendre_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_functional": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_dos_pipeline": ([P, P, I32, U64, D, P, I32, P, I32, P, P, P, P], I32),
         "kpm_heat_capacity": ([P, P, P, I32, D, D, P, I32, I32, P], I32),
         "kpm_slq_heat_capacity": ([P, P, P, I32, I32, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
@@ -302,6 +303,23 @@ def kpm_legendre_dos(ctx: Context, mu, lb: float, ub: float, x, g=None) -> np.nd
     ctx.check(ctx.lib.kpm_legendre_dos(ctx.handle, _p(m), _p(gg) if gg is not None else None, m.size - 1, lb, ub,
                                        _p(x), x.size, _p(phi)))
     return phi
+
+
+def kpm_dos_pipeline(ctx: Context, A, M: int, nvec: int, seed: int, x, precision="f32", block: int = 0,
+                     damping: int = KPM_DAMP_JACKSON, lanczos_steps: int = 20, lanczos_seed: int = 3002,
+                     margin: float = 0.01, validate: bool = False, rows_per_block: int = 0):
+    """Bounds, moments, damping and density in one call: (phi, mu, lb, ub)."""
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block)
+    x = _f64(x)
+    phi = np.zeros(x.size)
+    mu = np.zeros(M + 1)
+    lb = ctypes.c_double()
+    ub = ctypes.c_double()
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_dos_pipeline(ctx.handle, ctypes.byref(c), lanczos_steps, lanczos_seed, margin,
+                                       ctypes.byref(o), damping, _p(x), x.size, _p(phi), _p(mu), ctypes.byref(lb),
+                                       ctypes.byref(ub)))
+    return phi, mu, lb.value, ub.value
 
 
 def chebyshev_nodes(Q: int, lb: float, ub: float) -> np.ndarray:

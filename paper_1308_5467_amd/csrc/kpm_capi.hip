@@ -383,13 +383,52 @@ static int default_block(int nvec, int precision) {
     return std::min(nvec, std::min(maxb, 64));
 }
 
+// Device results of a moment computation still in flight on the context's
+// stream: mean moments mud [M+1] and per-probe normalised moments zout
+// [nvec x (M+1)].
+struct MomentsPending {
+    void* mud = nullptr;
+    void* zout = nullptr;
+    int M = 0, nvec = 0, precision = KPM_FP32;
+};
+
+// Copies the moments to the host (mu nullable, mu_per_vec nullable), waits
+// for the stream and checks |mu_k| <= 1 per probe.
+static kpm_status moments_collect(kpm_ctx* ctx, const MomentsPending& P, double* mu, double* mu_per_vec) {
+    const int M = P.M, nvec = P.nvec;
+    if (mu) KPM_HIP(ctx, hipMemcpyAsync(mu, P.mud, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<double>& hz = ctx->host_scratch;
+    hz.resize((size_t)nvec * (M + 1));
+    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), P.zout, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    kpm_status st;
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    if (mu_per_vec) memcpy(mu_per_vec, hz.data(), hz.size() * 8);
+    // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1]
+    // (and so |v^T L_k(B) v| <= n, a convex combination of those).
+    const double tol = P.precision == KPM_FP64 ? 1e-9 : 1e-4;
+    for (size_t i = 0; i < hz.size(); ++i) {
+        if (!isfinite(hz[i]) || fabs(hz[i]) > 1.0 + tol) {
+            char msg[200];
+            snprintf(msg, sizeof msg,
+                     "spectrum escaped [lb, ub]: probe %zu moment %zu = %g (|mu_k| must stay <= 1)",
+                     i / (M + 1), i % (M + 1), hz[i]);
+            return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
+        }
+    }
+    return KPM_OK;
+}
+
 // Chebyshev moments, or (legendre) the Legendre moments obtained from them
-// by the non-negative Chebyshev-to-Legendre weights on the device.
+// by the non-negative Chebyshev-to-Legendre weights on the device.  With
+// `pending` the work is only enqueued (Chebyshev moments only) and the
+// device results are described there; finish with moments_collect.
 static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
-                               const kpm_moment_opts* o, double* mu, double* mu_per_vec, bool legendre) {
+                               const kpm_moment_opts* o, double* mu, double* mu_per_vec, bool legendre,
+                               MomentsPending* pending = nullptr) {
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
-    if (!o || !mu) return kpm_fail(ctx, KPM_ERR_ARG, "opts or mu is NULL");
+    if (!o || (!mu && !pending)) return kpm_fail(ctx, KPM_ERR_ARG, "opts or mu is NULL");
+    if (pending && legendre) return kpm_fail(ctx, KPM_ERR_ARG, "internal: pending Legendre moments");
     if (o->M < 0 || o->M > (1 << 20)) return kpm_fail(ctx, KPM_ERR_ARG, "M must be in [0, 2^20]");
     if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
     if (o->precision != KPM_FP32 && o->precision != KPM_FP64)
@@ -490,25 +529,17 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
         zout = zl;
     }
     KPM_HIP(ctx, launch_mean_moments(ctx->stream, (double*)zout, nvec, M, (double*)mud));
-    KPM_HIP(ctx, hipMemcpyAsync(mu, mud, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
-    std::vector<double>& hz = ctx->host_scratch;
-    hz.resize((size_t)nvec * (M + 1));
-    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), zout, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if ((st = sync(ctx)) != KPM_OK) return st;
-    if (mu_per_vec) memcpy(mu_per_vec, hz.data(), hz.size() * 8);
-    // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1]
-    // (and so |v^T L_k(B) v| <= n, a convex combination of those).
-    const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
-    for (size_t i = 0; i < hz.size(); ++i) {
-        if (!isfinite(hz[i]) || fabs(hz[i]) > 1.0 + tol) {
-            char msg[200];
-            snprintf(msg, sizeof msg,
-                     "spectrum escaped [lb, ub]: probe %zu moment %zu = %g (|mu_k| must stay <= 1)",
-                     i / (M + 1), i % (M + 1), hz[i]);
-            return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
-        }
+    MomentsPending P;
+    P.mud = mud;
+    P.zout = zout;
+    P.M = M;
+    P.nvec = nvec;
+    P.precision = o->precision;
+    if (pending) {
+        *pending = P;
+        return KPM_OK;
     }
-    return KPM_OK;
+    return moments_collect(ctx, P, mu, mu_per_vec);
 }
 
 extern "C" kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
@@ -734,6 +765,51 @@ extern "C" kpm_status kpm_rademacher(kpm_ctx* ctx, uint64_t seed, int64_t vec0, 
     KPM_HIP(ctx, hipSetDevice(ctx->device));
     KPM_HIP(ctx, launch_rademacher(ctx->stream, seed, vec0, nvec, ld, n, precision, 0, out_device));
     return sync(ctx);
+}
+
+// ---------------------------------------------------------------- whole path
+// Bounds, moments, damping and density in one call: the Lanczos bounds need
+// one wait (their Ritz values are found on the host); everything after them
+// is enqueued back to back and waited for once.
+extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lanczos_steps, uint64_t lanczos_seed,
+                                       double margin, const kpm_moment_opts* o, kpm_damping damping,
+                                       const double* x, int npts, double* phi, double* mu, double* lb,
+                                       double* ub) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!o || !x || !phi || !lb || !ub || npts < 0) return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (damping != KPM_DAMP_NONE && damping != KPM_DAMP_JACKSON && damping != KPM_DAMP_LEARNED)
+        return kpm_fail(ctx, KPM_ERR_ARG, "unknown damping kind");
+    kpm_status st = kpm_bounds(ctx, A, lanczos_steps, lanczos_seed, margin, lb, ub);
+    if (st != KPM_OK) return st;
+    MomentsPending P;
+    if ((st = moments_impl(ctx, A, *lb, *ub, o, nullptr, nullptr, false, &P)) != KPM_OK) return st;
+    const int M = P.M;
+    void *gd, *xd, *pd;
+    if ((st = kpm_ws(ctx, "pipe_g", (size_t)(M + 1) * 8, &gd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_x", (size_t)std::max(npts, 1) * 8, &xd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dos_phi", (size_t)std::max(npts, 1) * 8, &pd)) != KPM_OK) return st;
+    std::vector<double> hg;  // host damping factors (none, learned); alive until the final wait
+    if (damping == KPM_DAMP_JACKSON) {
+        KPM_HIP(ctx, launch_jackson(ctx->stream, M, (double*)gd));
+    } else {
+        hg.assign((size_t)M + 1, 1.0);
+        if (damping == KPM_DAMP_LEARNED) {
+            // the network reads the moments: finish them first
+            std::vector<double> hm((size_t)M + 1);
+            if ((st = moments_collect(ctx, P, hm.data(), nullptr)) != KPM_OK) return st;
+            if ((st = kpm_learned_damping(ctx, M, hm.data(), hg.data())) != KPM_OK) return st;
+        }
+        KPM_HIP(ctx, hipMemcpyAsync(gd, hg.data(), hg.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    }
+    const double c = 0.5 * (*lb + *ub), d = 0.5 * (*ub - *lb);
+    if (npts > 0) {
+        KPM_HIP(ctx, hipMemcpyAsync(xd, x, (size_t)npts * 8, hipMemcpyHostToDevice, ctx->stream));
+        KPM_HIP(ctx, launch_dos(ctx->stream, (const double*)P.mud, (const double*)gd, M, c, d, (const double*)xd,
+                                npts, (double*)pd));
+        KPM_HIP(ctx, hipMemcpyAsync(phi, pd, (size_t)npts * 8, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    return moments_collect(ctx, P, mu, nullptr);
 }
 
 // ---------------------------------------------------------------- profiling

@@ -1,0 +1,72 @@
+"""The whole path in one call (kpm_dos_pipeline: bounds, moments, damping,
+density) against the same four steps called one by one -- bitwise, since
+the same kernels run in the same order -- and its moments against the CPU
+oracle at the bounds it chose."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1308_5467_amd as kpm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = kpm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(A, dtype):
+    vals = A.val if dtype == "f64" else A.val.astype(np.float32)
+    return kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, dtype)
+
+
+def _separate(ctx, D, M, nvec, seed, x, dtype, damping):
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
+    mu = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, seed, precision=dtype, validate=False)
+    g = kpm.kpm_damping_factors(ctx, damping, M, mu)
+    return kpm.kpm_dos(ctx, mu, g, lb, ub, x), mu, lb, ub
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("damping", [kpm.KPM_DAMP_NONE, kpm.KPM_DAMP_JACKSON])
+def test_pipeline_equals_separate_calls(ctx, dtype, damping):
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(20), 16.0, 4)
+    D = dev(A, dtype)
+    x = np.linspace(-9.0, 15.0, 201)
+    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, D, 96, 24, 11, x, precision=dtype, damping=damping)
+    rphi, rmu, rlb, rub = _separate(ctx, D, 96, 24, 11, x, dtype, damping)
+    assert (lb, ub) == (rlb, rub)
+    assert np.array_equal(mu, rmu) and np.array_equal(phi, rphi)
+    Ao = A if dtype == "f64" else A.rounded_f32()
+    ref = oracle.moments(Ao, lb, ub, 96, 24, 11)
+    assert np.max(np.abs(mu - ref)) < (1e-12 if dtype == "f64" else 1e-5)
+
+
+def test_pipeline_learned_damping(ctx):
+    kpm.kpm_mlp_init(ctx, 5)
+    A = synth.random_sparse_symmetric(2048, 4.5, 9)
+    D = dev(A, "f32")
+    x = np.linspace(-6.0, 6.0, 64)
+    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, D, 127, 32, 3, x, damping=kpm.KPM_DAMP_LEARNED)
+    rphi, rmu, rlb, rub = _separate(ctx, D, 127, 32, 3, x, "f32", kpm.KPM_DAMP_LEARNED)
+    assert (lb, ub) == (rlb, rub)
+    assert np.array_equal(mu, rmu) and np.array_equal(phi, rphi)
+
+
+def test_pipeline_errors_and_empty(ctx):
+    A = synth.laplacian2d_dirichlet(16)
+    D = dev(A, "f32")
+    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, D, 10, 4, 1, np.zeros(0))
+    assert phi.size == 0 and mu[0] == 1.0 and lb < ub
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_dos_pipeline(ctx, D, 10, 4, 1, np.zeros(3), damping=7)
+    assert e.value.status == -1
+    with pytest.raises(kpm.KpmError) as e:  # the learned network is defined for M = 127 only
+        kpm.kpm_dos_pipeline(ctx, D, 10, 4, 1, np.zeros(3), damping=kpm.KPM_DAMP_LEARNED)
+    assert e.value.status == -1
