@@ -70,7 +70,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the KPM engine runs on one GPU per process here (probe blocks would shard across GPUs); --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_1308_5467_amd as kpm

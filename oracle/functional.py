@@ -2,7 +2,7 @@
 capacity of section 4.3 -- TEST INFRASTRUCTURE ONLY (see the package header).
 
 For a smooth g, <phi, g> = int g(lambda) phi(lambda) dlambda = (1/n) sum_j
-g(lambda_j), and an approximate density is judged by
+g(lambda_j), and an approximate density is measured by
 E[phi~; g] = |<phi, g> - <phi~, g>|.  Restated here in plain numpy/scipy:
 
 * ``functional_exact``   -- (1/n) sum_j g(lambda_j) from the eigenvalues;
