@@ -299,7 +299,7 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
 
     def pipeline_haydock():
         l, u = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
-        _, _, us, a, bb = kpm.kpm_slq(ctx, D32, l, u, M_SLQ, nvec, 2002, block=b, coefficients=True)
+        us, a, bb = kpm.kpm_slq(ctx, D32, l, u, M_SLQ, nvec, 2002, block=b, coefficients=True, nodes=False)
         return kpm.kpm_haydock_dos(ctx, a, bb, us, l, u, sigma, x)
 
     t_pipe_hay = _time_ms(pipeline_haydock, reps)

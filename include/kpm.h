@@ -328,6 +328,9 @@ kpm_status kpm_legendre_dos(kpm_ctx* ctx, const double* mu, const double* g, int
  *   alpha, beta (nullable): T of B, alpha[l*M+k] = q_k.B q_k (diagonal),
  *           beta[l*M+k] = ||r_k|| (coupling of q_k and q_{k+1}; the last one
  *           is ||f_M||).
+ * theta and tau2 may both be NULL when alpha and beta are given: the
+ * coefficients (and steps_used) alone, without the eigenvalue problems
+ * (Haydock's method, kpm_haydock_dos, needs no Ritz values).
  * opts: M = Lanczos steps in [1, 4096], nvec, block (probes per device
  * block, 0 = min(nvec, 16), <= 64; up to 8 blocks run concurrently, one
  * group of XCDs each), seed, validate, rows_per_block;

@@ -389,19 +389,26 @@ def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int
 
 
 def kpm_slq(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int, block: int = 0,
-            validate: bool = False, rows_per_block: int = 0, coefficients: bool = False):
+            validate: bool = False, rows_per_block: int = 0, coefficients: bool = False, nodes: bool = True):
     """Stochastic Lanczos nodes: theta [nvec, M] (A's units), tau2 [nvec, M],
-    steps_used [nvec]; with coefficients=True also alpha, beta [nvec, M] of B."""
+    steps_used [nvec]; with coefficients=True also alpha, beta [nvec, M] of B.
+    nodes=False (with coefficients=True) skips the eigenvalue problems and
+    returns (steps_used, alpha, beta)."""
+    if not nodes and not coefficients:
+        raise ValueError("nodes=False needs coefficients=True")
     o = _opts(M, nvec, seed, "f64", block, validate, rows_per_block)
-    theta = np.zeros((nvec, M))
-    tau2 = np.zeros((nvec, M))
+    theta = np.zeros((nvec, M)) if nodes else None
+    tau2 = np.zeros((nvec, M)) if nodes else None
     used = np.zeros(nvec, dtype=np.int32)
     al = np.zeros((nvec, M)) if coefficients else None
     be = np.zeros((nvec, M)) if coefficients else None
     c = A.as_c()
-    ctx.check(ctx.lib.kpm_slq(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o), _p(theta), _p(tau2),
+    ctx.check(ctx.lib.kpm_slq(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o),
+                              _p(theta) if nodes else None, _p(tau2) if nodes else None,
                               used.ctypes.data_as(ctypes.c_void_p), _p(al) if coefficients else None,
                               _p(be) if coefficients else None))
+    if not nodes:
+        return used, al, be
     return (theta, tau2, used, al, be) if coefficients else (theta, tau2, used)
 
 

@@ -42,6 +42,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "kpm_internal.h"
@@ -505,7 +506,9 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
                               double* beta_out) {
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
-    if (!o || !theta || !tau2) return kpm_fail(ctx, KPM_ERR_ARG, "opts, theta or tau2 is NULL");
+    if (!o) return kpm_fail(ctx, KPM_ERR_ARG, "opts is NULL");
+    if ((!theta || !tau2) && !(alpha_out && beta_out && !theta && !tau2))
+        return kpm_fail(ctx, KPM_ERR_ARG, "theta and tau2 are needed unless both are NULL and alpha, beta are given");
     if (o->M < 1 || o->M > 4096) return kpm_fail(ctx, KPM_ERR_ARG, "M (Lanczos steps) must be in [1, 4096]");
     if (o->nvec < 1 || o->nvec > (1 << 24)) return kpm_fail(ctx, KPM_ERR_ARG, "nvec must be in [1, 2^24]");
     if (o->precision != KPM_FP64)
@@ -610,31 +613,79 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
     kpm_prof_collect(ctx);
     if (alpha_out) memcpy(alpha_out, al.data(), al.size() * 8);
     if (beta_out) memcpy(beta_out, be.data(), be.size() * 8);
-    // Per probe: breakdown rule, nodes and weights, Ritz values in A's units.
-    std::vector<double> th(M), w(M);
-    for (int l = 0; l < nvec; ++l) {
-        const double* a = &al[(size_t)l * M];
-        const double* bb = &be[(size_t)l * M];
-        int m = M;
-        double scale = 0.0;
-        for (int k = 0; k + 1 < M; ++k) {
-            if (!std::isfinite(a[k]) || !std::isfinite(bb[k]))
-                return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
-            scale = std::max(scale, std::max(fabs(a[k]), bb[k]));
-            if (bb[k] <= 1e-12 * scale) {
-                m = k + 1;
-                break;
+    if (!theta) {  // coefficients only (Haydock's method needs no Ritz values)
+        if (steps_used) {
+            for (int l = 0; l < nvec; ++l) {
+                const double* a = &al[(size_t)l * M];
+                const double* bb = &be[(size_t)l * M];
+                int m = M;
+                double scale = 0.0;
+                for (int k = 0; k + 1 < M; ++k) {
+                    if (!std::isfinite(a[k]) || !std::isfinite(bb[k]))
+                        return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
+                    scale = std::max(scale, std::max(fabs(a[k]), bb[k]));
+                    if (bb[k] <= 1e-12 * scale) {
+                        m = k + 1;
+                        break;
+                    }
+                }
+                steps_used[l] = m;
             }
         }
-        const kpm_status es = kpm_tridiag_eig(m, a, bb, th.data(), w.data());
-        if (es == KPM_ERR_NOCONV)
-            return kpm_fail(ctx, KPM_ERR_NOCONV, "tridiagonal eigenvalue iteration did not converge");
-        if (es != KPM_OK) return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient");
-        for (int k = 0; k < M; ++k) {
-            theta[(size_t)l * M + k] = k < m ? c + d * th[k] : 0.0;
-            tau2[(size_t)l * M + k] = k < m ? w[k] : 0.0;
+        return KPM_OK;
+    }
+    // Per probe: breakdown rule, nodes and weights, Ritz values in A's units.
+    // The probes are independent: up to 16 host threads take every T-th
+    // probe (each writes only its probes' rows); errors are reported for the
+    // lowest failing probe, as a serial loop would.
+    std::vector<kpm_status> pst((size_t)nvec, KPM_OK);
+    auto solve = [&](int t, int T) {
+        std::vector<double> th(M), w(M);
+        for (int l = t; l < nvec; l += T) {
+            const double* a = &al[(size_t)l * M];
+            const double* bb = &be[(size_t)l * M];
+            int m = M;
+            double scale = 0.0;
+            bool finite = true;
+            for (int k = 0; k + 1 < M; ++k) {
+                if (!std::isfinite(a[k]) || !std::isfinite(bb[k])) {
+                    finite = false;
+                    break;
+                }
+                scale = std::max(scale, std::max(fabs(a[k]), bb[k]));
+                if (bb[k] <= 1e-12 * scale) {
+                    m = k + 1;
+                    break;
+                }
+            }
+            const kpm_status es = finite ? kpm_tridiag_eig(m, a, bb, th.data(), w.data()) : KPM_ERR_ARG;
+            if (es != KPM_OK) {
+                pst[l] = es;
+                continue;
+            }
+            for (int k = 0; k < M; ++k) {
+                theta[(size_t)l * M + k] = k < m ? c + d * th[k] : 0.0;
+                tau2[(size_t)l * M + k] = k < m ? w[k] : 0.0;
+            }
+            if (steps_used) steps_used[l] = m;
         }
-        if (steps_used) steps_used[l] = m;
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::max(1, std::min(std::min((int)hw, 16), nvec / 4));
+    if (T == 1) {
+        solve(0, 1);
+    } else {
+        std::vector<std::thread> pool;
+        pool.reserve(T - 1);
+        for (int t = 1; t < T; ++t) pool.emplace_back(solve, t, T);
+        solve(0, T);
+        for (std::thread& th : pool) th.join();
+    }
+    for (int l = 0; l < nvec; ++l) {
+        if (pst[l] == KPM_ERR_NOCONV)
+            return kpm_fail(ctx, KPM_ERR_NOCONV, "tridiagonal eigenvalue iteration did not converge");
+        if (pst[l] != KPM_OK)
+            return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
     }
     return KPM_OK;
 }

@@ -68,6 +68,9 @@ def test_end_to_end_anderson3d(ctx, dtype):
     c, d = oracle.rescale(b["lb"], b["ub"])
     M, nvec, seed = 60, 10, 123
     _, _, used, al, be = kpm.kpm_slq(ctx, dev(A, dtype), b["lb"], b["ub"], M, nvec, seed, coefficients=True)
+    used2, al2, be2 = kpm.kpm_slq(ctx, dev(A, dtype), b["lb"], b["ub"], M, nvec, seed, coefficients=True,
+                                  nodes=False)  # coefficients only: the same bits
+    assert np.array_equal(used, used2) and np.array_equal(al, al2) and np.array_equal(be, be2)
     ra, rb = oracle.lanczos_tridiag(Ao, c, d, M, nvec, seed)
     rm = oracle.lanczos_steps_used(ra, rb)
     assert np.array_equal(used, rm)
