@@ -83,13 +83,37 @@ def _blur_l1(mu, g, ref):
     return oracle.l1_error(ref, oracle.blurred_kpm(mu, g, t, SIGMA, Q=8192))
 
 
-def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx):
+@pytest.fixture(scope="module")
+def trained(ctx):
+    """The damping network, trained once on device for this module."""
     _say("training set")
     X, T = _training_set(ctx)
     kpm.kpm_mlp_init(ctx, 7)
     _say(f"training on {len(X)} samples")
     losses = kpm.kpm_mlp_train(ctx, X, T, SIGMA, 150, 128, 1e-3, 3)
     assert losses[-1] < losses[0]
+    return losses
+
+
+def _degree_rows(ctx, mu32, mu64, ref):
+    rows = []
+    for M in DEGREES:
+        x = np.zeros(128)
+        x[:M + 1] = mu32[:M + 1]
+        g_learned = kpm.kpm_mlp_forward(ctx, x[None, :])[0].astype(np.float64)[:M + 1]
+        rows.append(dict(M=M,
+                         fp64_jackson=_blur_l1(mu64[:M + 1], oracle.jackson(M), ref),
+                         fp32_learned=_blur_l1(mu32[:M + 1], g_learned, ref),
+                         fp32_none=_blur_l1(mu32[:M + 1], np.ones(M + 1), ref),
+                         fp32_jackson=_blur_l1(mu32[:M + 1], oracle.jackson(M), ref)))
+    for r in rows:
+        _say("M=%3d  fp64+jackson %.4f  fp32+learned %.4f  fp32+none %.4f  fp32+jackson %.4f"
+             % (r["M"], r["fp64_jackson"], r["fp32_learned"], r["fp32_none"], r["fp32_jackson"]))
+    return rows
+
+
+def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
+    losses = trained
 
     _say("c2 workload")
     A = synth.config_matrix("c2")
@@ -108,19 +132,7 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx):
     t = oracle.midpoints(200)
     ref = oracle.blurred_kpm(mu_ref, np.ones(513), t, SIGMA, Q=8192)
 
-    rows = []
-    for M in DEGREES:
-        x = np.zeros(128)
-        x[:M + 1] = mu32[:M + 1]
-        g_learned = kpm.kpm_mlp_forward(ctx, x[None, :])[0].astype(np.float64)[:M + 1]
-        rows.append(dict(M=M,
-                         fp64_jackson=_blur_l1(mu64[:M + 1], oracle.jackson(M), ref),
-                         fp32_learned=_blur_l1(mu32[:M + 1], g_learned, ref),
-                         fp32_none=_blur_l1(mu32[:M + 1], np.ones(M + 1), ref),
-                         fp32_jackson=_blur_l1(mu32[:M + 1], oracle.jackson(M), ref)))
-    for r in rows:
-        _say("M=%3d  fp64+jackson %.4f  fp32+learned %.4f  fp32+none %.4f  fp32+jackson %.4f"
-             % (r["M"], r["fp64_jackson"], r["fp32_learned"], r["fp32_none"], r["fp32_jackson"]))
+    rows = _degree_rows(ctx, mu32, mu64, ref)
     M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
     M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
 
@@ -143,5 +155,38 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx):
     _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}; Lanczos steps {M_S}")
     assert M_L < M_J
     # the network must not be worse than Jackson at the same degree and precision
+    for r in rows:
+        assert r["fp32_learned"] <= r["fp32_jackson"] + 1e-3, r
+
+
+def test_fp32_learned_vs_fp64_jackson_on_large(ctx, trained):
+    """The large workload: 3D Anderson 128^3 + 2 random long-range pairs per
+    row (n = 2,097,152, nnz ~ 23.07M).  Same criterion, 4 probes (the
+    comparison is against the same probes' degree-512 series, so it measures
+    truncation and damping, not the probe count); the oracle's reference
+    costs about a minute of host time."""
+    _say("c5 workload")
+    A = synth.config_matrix("c5")
+    D32 = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32")
+    D64 = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64), "f64")
+    lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3005, 0.01)
+    nvec, seed = 4, 2005
+    mu32 = kpm.kpm_moments(ctx, D32, lb, ub, 127, nvec, seed, precision="f32")
+    mu64 = kpm.kpm_moments(ctx, D64, lb, ub, 127, nvec, seed, precision="f64")
+    _say("oracle reference (degree 512, same 4 probes)")
+    c, d = oracle.rescale(lb, ub)
+    zeta = oracle.moments_per_vector(A.rounded_f32(), c, d, 512, nvec, seed, nthreads=min(16, os.cpu_count() or 1))
+    mu_ref = oracle.normalize(zeta, A.n)
+    assert np.max(np.abs(mu64 - mu_ref[:128])) < 1e-12
+    assert np.max(np.abs(mu32 - mu_ref[:128])) < 1e-5
+    ref = oracle.blurred_kpm(mu_ref, np.ones(513), oracle.midpoints(200), SIGMA, Q=8192)
+    rows = _degree_rows(ctx, mu32, mu64, ref)
+    M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
+    M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "accuracy_study_large.json"), "w") as f:
+        json.dump(dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, nvec=nvec), f, indent=1)
+    _say(f"large workload, degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}")
+    assert M_L < M_J
     for r in rows:
         assert r["fp32_learned"] <= r["fp32_jackson"] + 1e-3, r
