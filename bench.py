@@ -274,13 +274,23 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
                                            validate=False), reps)
     m32 = _time_ms(lambda: kpm.kpm_moments(ctx, D32, lb, ub, M_FP32_LEARNED, nvec, 2002, precision="f32",
                                            validate=False), reps)
+    # the FP64 step kernel against the HBM roofline (values, V, U in FP64)
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", validate=False)
+    kpm.kpm_profile_enable(ctx, False)
+    nl, ms = kpm.kpm_profile_query(ctx, "cheb_step")
+    us64 = ms / max(nl, 1) * 1000.0
+    bytes64 = 12 * A.nnz + 4 * (A.n + 1) + 24 * A.n * nvec
     return {"criterion": "L1(sigma=0.02) <= 1e-2 against the FP64 oracle's degree-512 series, same probes",
             "accuracy_source": "tests/test_gpu_accuracy.py",
             "M_fp64_jackson": M_FP64_JACKSON, "M_fp32_learned": M_FP32_LEARNED,
             "ms_fp64_jackson_pipeline": round(t64, 3), "ms_fp32_learned_pipeline": round(t32, 3),
             "speedup_pipeline": round(t64 / t32, 2),
             "ms_fp64_moments": round(m64, 3), "ms_fp32_moments": round(m32, 3),
-            "speedup_moments": round(m64 / m32, 2)}
+            "speedup_moments": round(m64 / m32, 2),
+            "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
+            "fp64_step_frac_of_hbm_peak": round(bytes64 / (us64 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def slq_leg(kpm, ctx, A, D32, x, reps=5):
