@@ -212,9 +212,16 @@ def main():
         oracle.moments_per_vector(Ao, c, d, M, nv, 2002, nthreads=cores)
         te = time.perf_counter()
         cpu_units = float(A.nnz) * M * nv / (te - ts)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": cpu_units, "unit": "nnz*deg*vec/s", "cores": cores, "kind": "oracle",
                                "sample": f"{nv} of {nvec} probes, full matrix, full degree M={M}, "
-                                         f"FP64 plain recurrence (no doubling); {te - ts:.2f} s"}
+                                         f"FP64 plain recurrence (no doubling); {te - ts:.2f} s",
+                               "cpu_model": model, "host_cpus": os.cpu_count()}
     print(json.dumps(out))
 
 
