@@ -67,3 +67,34 @@ def test_rejects_bad_input():
         kpm.kpm_tridiag_eig(np.array([1.0, np.nan]), np.array([0.1]))
     with pytest.raises(kpm.KpmError):
         kpm.kpm_tridiag_eig(np.array([1.0, 2.0]), np.array([np.inf]))
+
+
+# Randomised cases (hypothesis): sizes 1..80, coefficients spanning several
+# orders of magnitude, including exact zeros in the off-diagonal (decoupled
+# blocks) -- the library's QR iteration against LAPACK.
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None)
+@given(m=st.integers(1, 80), seed=st.integers(0, 2**31 - 1), scale=st.sampled_from([1e-6, 1e-2, 1.0, 1e3]),
+       zeros=st.integers(0, 3))
+def test_random_tridiagonals_property(m, seed, scale, zeros):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(0.0, scale, m)
+    b = np.abs(rng.normal(0.0, scale, max(m - 1, 0)))
+    for _ in range(min(zeros, max(m - 1, 0))):
+        b[rng.integers(0, m - 1)] = 0.0
+    th, w = kpm.kpm_tridiag_eig(a, b)
+    rth, rw = _ref(a, b)
+    tol = 1e-12 * max(scale, np.max(np.abs(rth)))
+    assert np.max(np.abs(th - rth)) <= tol
+    assert abs(w.sum() - 1.0) < 1e-12 and np.all(w >= 0.0) and np.all(np.diff(th) >= 0)
+    # weights: compare where eigenvalues are well separated (otherwise only
+    # their sum over a cluster is determined)
+    gaps = np.diff(rth)
+    iso = np.ones(m, dtype=bool)
+    if m > 1:
+        small = gaps < 1e-6 * max(scale, 1e-300)
+        iso[:-1] &= ~small
+        iso[1:] &= ~small
+    assert np.max(np.abs(w[iso] - rw[iso]), initial=0.0) < 1e-9
