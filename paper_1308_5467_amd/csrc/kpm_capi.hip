@@ -51,6 +51,28 @@ kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out) {
     return KPM_OK;
 }
 
+kpm_status kpm_pinned(kpm_ctx* ctx, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 256;
+    if (ctx->pinned_cap < bytes) {
+        if (ctx->pinned) {
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return kpm_hip_fail(ctx, e, "hipStreamSynchronize (pinned staging)");
+            hipHostFree(ctx->pinned);
+            ctx->pinned = nullptr;
+            ctx->pinned_cap = 0;
+        }
+        const size_t cap = (bytes + 65535) / 65536 * 65536;
+        hipError_t e = hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            ctx->pinned = nullptr;
+            return kpm_fail(ctx, KPM_ERR_ALLOC, "hipHostMalloc of the host staging buffer failed");
+        }
+        ctx->pinned_cap = cap;
+    }
+    *out = ctx->pinned;
+    return KPM_OK;
+}
+
 void kpm_prof_begin(kpm_ctx* ctx, const char* kernel) { kpm_prof_begin_on(ctx, kernel, ctx->stream); }
 void kpm_prof_end(kpm_ctx* ctx, const char* kernel, int launches) {
     kpm_prof_end_on(ctx, kernel, ctx->stream, launches);
@@ -192,6 +214,7 @@ extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
     if (ctx->mlp_params.p) hipFree(ctx->mlp_params.p);
     for (auto& kv : ctx->prof_map)
         for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
     delete ctx;
     return KPM_OK;
 }
@@ -296,9 +319,11 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     kpm_prof_begin(ctx, "lanczos");
     KPM_HIP(ctx, launch_lanczos(ctx->stream, A, m, seed, W));
     kpm_prof_end(ctx, "lanczos", 1);
-    std::vector<double> hc(256);
-    KPM_HIP(ctx, hipMemcpyAsync(hc.data(), coef, 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
+    void* stage;
+    if ((st = kpm_pinned(ctx, 256 * 8, &stage)) != KPM_OK) return st;
+    KPM_HIP(ctx, hipMemcpyAsync(stage, coef, 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;
+    std::vector<double> hc((const double*)stage, (const double*)stage + 256);
     // Breakdown test in step order: stop at the first residual below 1e-12 of
     // the largest coefficient seen so far.
     double scale = 0.0, beta_last = 0.0;
@@ -394,14 +419,27 @@ struct MomentsPending {
 
 // Copies the moments to the host (mu nullable, mu_per_vec nullable), waits
 // for the stream and checks |mu_k| <= 1 per probe.
-static kpm_status moments_collect(kpm_ctx* ctx, const MomentsPending& P, double* mu, double* mu_per_vec) {
+// Copies go through the context's page-locked staging buffer; `extra`
+// (nullable) is one more device array of extra_n doubles copied to
+// extra_host in the same wait.
+static kpm_status moments_collect(kpm_ctx* ctx, const MomentsPending& P, double* mu, double* mu_per_vec,
+                                  const double* extra = nullptr, size_t extra_n = 0, double* extra_host = nullptr) {
     const int M = P.M, nvec = P.nvec;
-    if (mu) KPM_HIP(ctx, hipMemcpyAsync(mu, P.mud, (size_t)(M + 1) * 8, hipMemcpyDeviceToHost, ctx->stream));
-    std::vector<double>& hz = ctx->host_scratch;
-    hz.resize((size_t)nvec * (M + 1));
-    KPM_HIP(ctx, hipMemcpyAsync(hz.data(), P.zout, hz.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    const size_t nm = (size_t)M + 1, nz = (size_t)nvec * (M + 1);
+    void* stage;
     kpm_status st;
+    if ((st = kpm_pinned(ctx, (nm + nz + extra_n) * 8, &stage)) != KPM_OK) return st;
+    double* sm = (double*)stage;
+    double* sz = sm + nm;
+    double* sx = sz + nz;
+    KPM_HIP(ctx, hipMemcpyAsync(sm, P.mud, nm * 8, hipMemcpyDeviceToHost, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(sz, P.zout, nz * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (extra && extra_n) KPM_HIP(ctx, hipMemcpyAsync(sx, extra, extra_n * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;
+    if (mu) memcpy(mu, sm, nm * 8);
+    if (extra && extra_n) memcpy(extra_host, sx, extra_n * 8);
+    std::vector<double>& hz = ctx->host_scratch;
+    hz.assign(sz, sz + nz);
     if (mu_per_vec) memcpy(mu_per_vec, hz.data(), hz.size() * 8);
     // |v^T T_k(B) v| <= v^T v = n when the spectrum of B lies in [-1, 1]
     // (and so |v^T L_k(B) v| <= n, a convex combination of those).
@@ -807,9 +845,8 @@ extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lancz
         KPM_HIP(ctx, hipMemcpyAsync(xd, x, (size_t)npts * 8, hipMemcpyHostToDevice, ctx->stream));
         KPM_HIP(ctx, launch_dos(ctx->stream, (const double*)P.mud, (const double*)gd, M, c, d, (const double*)xd,
                                 npts, (double*)pd));
-        KPM_HIP(ctx, hipMemcpyAsync(phi, pd, (size_t)npts * 8, hipMemcpyDeviceToHost, ctx->stream));
     }
-    return moments_collect(ctx, P, mu, nullptr);
+    return moments_collect(ctx, P, mu, nullptr, (const double*)pd, (size_t)npts, phi);
 }
 
 // ---------------------------------------------------------------- profiling

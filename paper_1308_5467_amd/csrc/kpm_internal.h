@@ -132,6 +132,8 @@ struct kpm_ctx {
     std::string err;
     std::map<std::string, kpm_dev_buf> bufs;  // grow-only device workspace by role
     std::vector<double> host_scratch;
+    void* pinned = nullptr;  // grow-only page-locked host staging for device-to-host copies
+    size_t pinned_cap = 0;
     // damping network
     bool mlp_ready = false;
     kpm_dev_buf mlp_params;
@@ -152,6 +154,9 @@ kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g)
 
 // Grow-only workspace allocation by role name.
 kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out);
+// Grow-only page-locked host buffer of at least `bytes` (waits for the
+// context's stream before replacing a smaller one).
+kpm_status kpm_pinned(kpm_ctx* ctx, size_t bytes, void** out);
 kpm_status kpm_fail(kpm_ctx* ctx, kpm_status st, const std::string& msg);
 kpm_status kpm_hip_fail(kpm_ctx* ctx, hipError_t e, const char* what);
 // Profiling helpers: bracket a run of `launches` back-to-back launches of
