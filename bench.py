@@ -260,19 +260,14 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
     kpm.kpm_mlp_init(ctx, 1)
     nvec = 64
 
+    # both forms as one library call each (bounds, moments, damping, density)
     def fp64_jackson():
-        lb, ub = kpm.kpm_bounds(ctx, D64, 20, 3002, 0.01)
-        mu = kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", validate=False)
-        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M_FP64_JACKSON)
-        return kpm.kpm_dos(ctx, mu, g, lb, ub, x)
+        return kpm.kpm_dos_pipeline(ctx, D64, M_FP64_JACKSON, nvec, 2002, x, precision="f64",
+                                    damping=kpm.KPM_DAMP_JACKSON)[0]
 
     def fp32_learned():
-        lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
-        mu = kpm.kpm_moments(ctx, D32, lb, ub, M_FP32_LEARNED, nvec, 2002, precision="f32", validate=False)
-        xin = np.zeros(128)
-        xin[:M_FP32_LEARNED + 1] = mu
-        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 127, xin)[:M_FP32_LEARNED + 1]
-        return kpm.kpm_dos(ctx, mu, g, lb, ub, x)
+        return kpm.kpm_dos_pipeline(ctx, D32, M_FP32_LEARNED, nvec, 2002, x, precision="f32",
+                                    damping=kpm.KPM_DAMP_LEARNED)[0]
 
     lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
     t64 = _time_ms(fp64_jackson, reps)
@@ -381,12 +376,8 @@ def large_leg(kpm, ctx, synth, reps=3):
         return phi
 
     def fp32_learned():
-        l, u = kpm.kpm_bounds(ctx, D32, 20, 3005, 0.01)
-        mu = kpm.kpm_moments(ctx, D32, l, u, M_LARGE_FP32_LEARNED, nvec, 2005, validate=False)
-        xin = np.zeros(128)
-        xin[:M_LARGE_FP32_LEARNED + 1] = mu
-        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 127, xin)[:M_LARGE_FP32_LEARNED + 1]
-        return kpm.kpm_dos(ctx, mu, g, l, u, x)
+        return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_LEARNED, nvec, 2005, x, precision="f32",
+                                    damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005)[0]
 
     t64 = _time_ms(fp64_jackson, reps)
     t32 = _time_ms(fp32_learned, reps)

@@ -103,7 +103,7 @@ enum {
 typedef enum {
     KPM_DAMP_NONE = 0,    /* g_k = 1                                            */
     KPM_DAMP_JACKSON = 1, /* Jackson factors, Appendix A eq. (jackson)          */
-    KPM_DAMP_LEARNED = 2  /* damping network (requires weights, M = 127)        */
+    KPM_DAMP_LEARNED = 2  /* damping network (requires weights, M <= 127)       */
 } kpm_damping;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -241,8 +241,9 @@ kpm_status kpm_autotune_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const 
 /*
  * kpm_damping_factors -- damping factors g[0..M] (host, written).
  * KPM_DAMP_NONE: all ones.  KPM_DAMP_JACKSON: eq. (jackson) of Appendix A.
- * KPM_DAMP_LEARNED: the damping network applied to mu[0..127] (host, M must
- * be 127); g[0] = 1.
+ * KPM_DAMP_LEARNED: the damping network applied to mu[0..M] (host, M <=
+ * 127; the network reads zeros above degree M, the truncation it is trained
+ * with); g[0] = 1.
  */
 kpm_status kpm_damping_factors(kpm_ctx* ctx, kpm_damping kind, int M, const double* mu, double* g);
 
@@ -268,7 +269,7 @@ kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, 
  * kpm_dos_pipeline -- the whole path of section 3.1.1 in one call: the
  * Lanczos bounds of kpm_bounds (lanczos_steps, lanczos_seed, margin), the
  * moments of kpm_moments on [lb, ub] (opts), the damping factors of
- * kpm_damping_factors (damping; KPM_DAMP_LEARNED needs M = 127 and a
+ * kpm_damping_factors (damping; KPM_DAMP_LEARNED needs M <= 127 and a
  * loaded network) and the density of kpm_dos at the npts points x (host),
  * with the results of those calls: phi (host [npts]), mu (host [M+1],
  * nullable), lb, ub (host).  After the bounds (whose Ritz values are found

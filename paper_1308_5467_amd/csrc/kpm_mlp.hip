@@ -638,13 +638,15 @@ extern "C" kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path) {
     return kpm_mlp_set_params(ctx, p.data());
 }
 
+// Degree M <= 127: the network reads mu_0..mu_M with zeros above (the
+// truncation it is trained with) and g_0..g_M are returned.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g) {
-    if (M != NOUT - 1) return kpm_fail(ctx, KPM_ERR_ARG, "learned damping is defined for M = 127");
+    if (M < 0 || M > NOUT - 1) return kpm_fail(ctx, KPM_ERR_ARG, "learned damping is defined for M <= 127");
     float x[NIN], gf[NOUT];
-    for (int k = 0; k < NIN; ++k) x[k] = (float)mu[k];
+    for (int k = 0; k < NIN; ++k) x[k] = k <= M ? (float)mu[k] : 0.0f;
     kpm_status st = kpm_mlp_forward(ctx, 1, x, gf);
     if (st != KPM_OK) return st;
-    for (int k = 0; k < NOUT; ++k) g[k] = gf[k];
+    for (int k = 0; k <= M; ++k) g[k] = gf[k];
     g[0] = 1.0;
     return KPM_OK;
 }

@@ -111,8 +111,14 @@ def test_save_load_and_learned_damping_entry(ctx, tmp_path):
     g_fwd = kpm.kpm_mlp_forward(ctx, X)[0]
     g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 127, X[0])
     assert g[0] == 1.0 and np.allclose(g[1:], g_fwd[1:], rtol=0, atol=0)
+    # degree 100: the network reads zeros above it
+    xt = X[0].astype(np.float64).copy()
+    xt[101:] = 0.0
+    g100 = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 100, xt[:101])
+    assert g100.size == 101 and g100[0] == 1.0
+    assert np.array_equal(g100[1:], kpm.kpm_mlp_forward(ctx, xt[None, :].astype(np.float32))[0][1:101].astype(np.float64))
     with pytest.raises(kpm.KpmError):
-        kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 100, np.ones(101))
+        kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_LEARNED, 128, np.ones(129))
     with open(path, "r+b") as f:
         f.write(b"XXXX")
     with pytest.raises(kpm.KpmError):

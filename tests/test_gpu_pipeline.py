@@ -48,13 +48,14 @@ def test_pipeline_equals_separate_calls(ctx, dtype, damping):
     assert np.max(np.abs(mu - ref)) < (1e-12 if dtype == "f64" else 1e-5)
 
 
-def test_pipeline_learned_damping(ctx):
+@pytest.mark.parametrize("M", [127, 16])
+def test_pipeline_learned_damping(ctx, M):
     kpm.kpm_mlp_init(ctx, 5)
     A = synth.random_sparse_symmetric(2048, 4.5, 9)
     D = dev(A, "f32")
     x = np.linspace(-6.0, 6.0, 64)
-    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, D, 127, 32, 3, x, damping=kpm.KPM_DAMP_LEARNED)
-    rphi, rmu, rlb, rub = _separate(ctx, D, 127, 32, 3, x, "f32", kpm.KPM_DAMP_LEARNED)
+    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, D, M, 32, 3, x, damping=kpm.KPM_DAMP_LEARNED)
+    rphi, rmu, rlb, rub = _separate(ctx, D, M, 32, 3, x, "f32", kpm.KPM_DAMP_LEARNED)
     assert (lb, ub) == (rlb, rub)
     assert np.array_equal(mu, rmu) and np.array_equal(phi, rphi)
 
@@ -67,6 +68,6 @@ def test_pipeline_errors_and_empty(ctx):
     with pytest.raises(kpm.KpmError) as e:
         kpm.kpm_dos_pipeline(ctx, D, 10, 4, 1, np.zeros(3), damping=7)
     assert e.value.status == -1
-    with pytest.raises(kpm.KpmError) as e:  # the learned network is defined for M = 127 only
-        kpm.kpm_dos_pipeline(ctx, D, 10, 4, 1, np.zeros(3), damping=kpm.KPM_DAMP_LEARNED)
+    with pytest.raises(kpm.KpmError) as e:  # the learned network is defined up to degree 127
+        kpm.kpm_dos_pipeline(ctx, D, 200, 4, 1, np.zeros(3), damping=kpm.KPM_DAMP_LEARNED)
     assert e.value.status == -1
