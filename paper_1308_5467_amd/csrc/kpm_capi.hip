@@ -808,7 +808,8 @@ extern "C" kpm_status kpm_rademacher(kpm_ctx* ctx, uint64_t seed, int64_t vec0, 
 // ---------------------------------------------------------------- whole path
 // Bounds, moments, damping and density in one call: the Lanczos bounds need
 // one wait (their Ritz values are found on the host); everything after them
-// is enqueued back to back and waited for once.
+// -- the learned damping network included -- is enqueued back to back and
+// waited for once.
 extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lanczos_steps, uint64_t lanczos_seed,
                                        double margin, const kpm_moment_opts* o, kpm_damping damping,
                                        const double* x, int npts, double* phi, double* mu, double* lb,
@@ -827,17 +828,14 @@ extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lancz
     if ((st = kpm_ws(ctx, "pipe_g", (size_t)(M + 1) * 8, &gd)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "dos_x", (size_t)std::max(npts, 1) * 8, &xd)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "dos_phi", (size_t)std::max(npts, 1) * 8, &pd)) != KPM_OK) return st;
-    std::vector<double> hg;  // host damping factors (none, learned); alive until the final wait
+    std::vector<double> hg;  // host damping factors (none); alive until the final wait
     if (damping == KPM_DAMP_JACKSON) {
         KPM_HIP(ctx, launch_jackson(ctx->stream, M, (double*)gd));
+    } else if (damping == KPM_DAMP_LEARNED) {
+        // the network reads the device moments directly
+        if ((st = kpm_learned_damping_device(ctx, M, (const double*)P.mud, (double*)gd)) != KPM_OK) return st;
     } else {
         hg.assign((size_t)M + 1, 1.0);
-        if (damping == KPM_DAMP_LEARNED) {
-            // the network reads the moments: finish them first
-            std::vector<double> hm((size_t)M + 1);
-            if ((st = moments_collect(ctx, P, hm.data(), nullptr)) != KPM_OK) return st;
-            if ((st = kpm_learned_damping(ctx, M, hm.data(), hg.data())) != KPM_OK) return st;
-        }
         KPM_HIP(ctx, hipMemcpyAsync(gd, hg.data(), hg.size() * 8, hipMemcpyHostToDevice, ctx->stream));
     }
     const double c = 0.5 * (*lb + *ub), d = 0.5 * (*ub - *lb);

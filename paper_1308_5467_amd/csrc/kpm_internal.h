@@ -151,6 +151,8 @@ void kpm_batch_free(kpm_ctx* ctx);
 
 // Learned damping (damping network on the device); host mu/g arrays.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g);
+// The same from device moments into device factors, enqueued without a wait.
+kpm_status kpm_learned_damping_device(kpm_ctx* ctx, int M, const double* mu_dev, double* g_dev);
 
 // Grow-only workspace allocation by role name.
 kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out);

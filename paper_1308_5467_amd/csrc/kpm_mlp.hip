@@ -638,6 +638,40 @@ extern "C" kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path) {
     return kpm_mlp_set_params(ctx, p.data());
 }
 
+namespace {
+// x[k] = mu[k] as float for k <= M, 0 above (one row of network input).
+__global__ __launch_bounds__(NIN) void learned_input_kernel(const double* __restrict__ mu, int M,
+                                                            float* __restrict__ x) {
+    const int k = threadIdx.x;
+    x[k] = k <= M ? (float)mu[k] : 0.0f;
+}
+// g[k] = network output k (g[0] = 1) for k <= M.
+__global__ __launch_bounds__(NOUT) void learned_output_kernel(const float* __restrict__ gf, int M,
+                                                              double* __restrict__ g) {
+    const int k = threadIdx.x;
+    if (k <= M) g[k] = k == 0 ? 1.0 : (double)gf[k];
+}
+}  // namespace
+
+// The same damping factors as kpm_learned_damping from device moments into
+// device factors, enqueued on the context's stream without a wait.
+kpm_status kpm_learned_damping_device(kpm_ctx* ctx, int M, const double* mu_dev, double* g_dev) {
+    if (M < 0 || M > NOUT - 1) return kpm_fail(ctx, KPM_ERR_ARG, "learned damping is defined for M <= 127");
+    kpm_status st = need_model(ctx);
+    if (st != KPM_OK) return st;
+    MlpWork w;
+    void* xd;
+    if ((st = mlp_work(ctx, 1, &w)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "mlp_x", (size_t)NIN * sizeof(float), &xd)) != KPM_OK) return st;
+    learned_input_kernel<<<1, NIN, 0, ctx->stream>>>(mu_dev, M, (float*)xd);
+    KPM_HIP(ctx, hipGetLastError());
+    forward_small_kernel<<<1, NH, 0, ctx->stream>>>((const float*)xd, (const float*)ctx->mlp_params.p, w.b.g);
+    KPM_HIP(ctx, hipGetLastError());
+    learned_output_kernel<<<1, NOUT, 0, ctx->stream>>>(w.b.g, M, g_dev);
+    KPM_HIP(ctx, hipGetLastError());
+    return KPM_OK;
+}
+
 // Degree M <= 127: the network reads mu_0..mu_M with zeros above (the
 // truncation it is trained with) and g_0..g_M are returned.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g) {
