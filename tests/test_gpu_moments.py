@@ -76,10 +76,11 @@ def test_c1_fp64_parity(ctx):
 
 
 @pytest.mark.parametrize("L,nvec,block,M", [(16, 64, 64, 256), (13, 40, 16, 31), (11, 5, 0, 2),
-                                            (9, 3, 3, 1), (10, 17, 8, 0)])
+                                            (9, 3, 3, 1), (10, 17, 8, 0), (10, 300, 256, 20), (12, 130, 128, 9)])
 def test_anderson3d_fp32_parity_ragged(ctx, L, nvec, block, M):
     """3D Anderson model, FP32 path: several workgroups, ragged row tail,
-    ragged last probe block, odd/even/tiny M."""
+    ragged last probe block, odd/even/tiny M, the widest blocks (256 probes:
+    one row per wavefront; 128)."""
     _say(f"anderson3d fp32 L={L} nvec={nvec} block={block} M={M}")
     A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(L), 16.0, 7 + L)
     b = oracle.lanczos_bounds(A.rounded_f32(), 20, 3)
