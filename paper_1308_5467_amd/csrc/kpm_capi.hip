@@ -230,65 +230,6 @@ extern "C" const char* kpm_last_error(const kpm_ctx* ctx) {
     return ctx->err.c_str();
 }
 
-// ---------------------------------------------------------------- tridiagonal eigenproblem
-// Cyclic Jacobi rotations on the dense symmetric m x m matrix (m <= 32):
-// eigenvalues in w (ascending) and eigenvectors as columns of Z (row-major).
-static bool jacobi_eigen(int m, std::vector<double> A, std::vector<double>& w, std::vector<double>& Z) {
-    Z.assign((size_t)m * m, 0.0);
-    for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
-    double norm = 0.0;
-    for (double x : A) norm += x * x;
-    bool converged = false;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < m; ++p)
-            for (int q = p + 1; q < m; ++q) off += A[(size_t)p * m + q] * A[(size_t)p * m + q];
-        if (off <= 1e-34 * norm || off == 0.0) {
-            converged = true;
-            break;
-        }
-        for (int p = 0; p < m; ++p) {
-            for (int q = p + 1; q < m; ++q) {
-                const double apq = A[(size_t)p * m + q];
-                if (apq == 0.0) continue;
-                const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < m; ++k) {  // columns p, q
-                    const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
-                    A[(size_t)k * m + p] = c * akp - s * akq;
-                    A[(size_t)k * m + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < m; ++k) {  // rows p, q
-                    const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
-                    A[(size_t)p * m + k] = c * apk - s * aqk;
-                    A[(size_t)q * m + k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < m; ++k) {
-                    const double zkp = Z[(size_t)k * m + p], zkq = Z[(size_t)k * m + q];
-                    Z[(size_t)k * m + p] = c * zkp - s * zkq;
-                    Z[(size_t)k * m + q] = s * zkp + c * zkq;
-                }
-            }
-        }
-    }
-    w.resize(m);
-    for (int i = 0; i < m; ++i) w[i] = A[(size_t)i * m + i];
-    // sort ascending, permuting eigenvector columns
-    std::vector<int> idx(m);
-    for (int i = 0; i < m; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] < w[b]; });
-    std::vector<double> w2(m), Z2((size_t)m * m);
-    for (int j = 0; j < m; ++j) {
-        w2[j] = w[idx[j]];
-        for (int k = 0; k < m; ++k) Z2[(size_t)k * m + j] = Z[(size_t)k * m + idx[j]];
-    }
-    w.swap(w2);
-    Z.swap(Z2);
-    return converged;
-}
-
 // ---------------------------------------------------------------- bounds
 extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed,
                                  double margin, double* lb, double* ub) {
@@ -345,15 +286,20 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
             break;
         }
     }
-    std::vector<double> T((size_t)k * k, 0.0), theta, Z;
-    for (int j = 0; j < k; ++j) {
-        T[(size_t)j * k + j] = hc[j];
-        if (j + 1 < k) T[(size_t)j * k + j + 1] = T[(size_t)(j + 1) * k + j] = hc[64 + j];
-    }
-    if (!jacobi_eigen(k, T, theta, Z))
-        return kpm_fail(ctx, KPM_ERR_NOCONV, "Jacobi iteration on the Lanczos matrix did not converge");
-    const double rlo = beta_last * fabs(Z[(size_t)(k - 1) * k + 0]);
-    const double rhi = beta_last * fabs(Z[(size_t)(k - 1) * k + (k - 1)]);
+    // Ritz values and the last components s_k of the Ritz vectors: the last
+    // components of T's eigenvectors are the first components of those of
+    // the flipped matrix J T J (J the reversal), which the implicit QR solver
+    // accumulates in O(k^2) without forming eigenvectors.
+    std::vector<double> fa(k), fb(std::max(k - 1, 1), 0.0), theta(k), s2(k);
+    for (int j = 0; j < k; ++j) fa[j] = hc[k - 1 - j];
+    for (int j = 0; j + 1 < k; ++j) fb[j] = hc[64 + k - 2 - j];
+    const kpm_status es = kpm_tridiag_eig(k, fa.data(), fb.data(), theta.data(), s2.data());
+    if (es == KPM_ERR_NOCONV)
+        return kpm_fail(ctx, KPM_ERR_NOCONV, "QR iteration on the Lanczos matrix did not converge");
+    if (es != KPM_OK) return kpm_fail(ctx, es, "Lanczos matrix eigenproblem failed");
+    // residual norms beta_k |s_k| of the extreme Ritz pairs
+    const double rlo = beta_last * sqrt(s2[0]);
+    const double rhi = beta_last * sqrt(s2[k - 1]);
     double lb0 = theta[0] - rlo, ub0 = theta[k - 1] + rhi;
     if (breakdown) {
         const int gb = W.nblk;
