@@ -52,11 +52,26 @@ struct BatchMvDev {  // one (matrix, probe block)
     int32_t n, ncols, mat, vec0;
 };
 
+__device__ __forceinline__ void bneumaier(double& s, double& c, double x) {
+    const double u = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
+    s = u;
+}
+
+// Step k also finishes step k - 1's dots: the workgroup that runs an mv's
+// first table entry adds that mv's partials of step k - 1 (`prev`, the other
+// half of a two-step partial buffer) over its entries in order, with the
+// compensated sum of batched_reduce_kernel, so only two steps of partials
+// are ever stored whatever the number of table entries.
 template <typename TA, typename TV, bool FIRST, int G>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntryDev* __restrict__ entries,
                                                                 const BatchMvDev* __restrict__ mvs, int parity,
                                                                 int ld, int lpr, int rpw, int rows_per_panel,
-                                                                int stage, double* __restrict__ partial) {
+                                                                int stage, double* __restrict__ partial,
+                                                                const double* __restrict__ prev,
+                                                                const int32_t* __restrict__ e0,
+                                                                const int32_t* __restrict__ e1,
+                                                                double* __restrict__ dots_prev) {
     constexpr int N = Pack<TV>::N;
     __shared__ __align__(16) double smem[kWaves * 64 * 2 * N];
     const int lane = threadIdx.x & 63;
@@ -105,6 +120,22 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
         for (int sl = 0; sl < nslots; ++sl) s += red[(sl * 2 + d) * ld + c];
         outp[t] = s;
     }
+    if (!FIRST && e == e0[E.mv]) {
+        // loads in groups of 16 (one memory round trip each), sums in order
+        const int width = 2 * ld, f1 = e1[E.mv];
+        for (int t = threadIdx.x; t < width; t += kThreads) {
+            double s = 0.0, c = 0.0;
+            for (int f = e; f < f1; f += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = f + u < f1 ? prev[(int64_t)(f + u) * width + t] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (f + u < f1) bneumaier(s, c, x[u]);
+            }
+            dots_prev[(int64_t)E.mv * width + t] = s + c;
+        }
+    }
 }
 
 // Probe blocks of every mv: X0 = Rademacher probes vec0.. of seed_mv (zero padding).
@@ -121,13 +152,8 @@ __global__ void batched_fill_kernel(const BatchMvDev* __restrict__ mvs, int ld) 
         out[i * ld + j] = j < mv.ncols ? (T)rademacher_sign(mv.seed, (uint64_t)(mv.vec0 + j), (uint64_t)i) : (T)0;
 }
 
-__device__ __forceinline__ void bneumaier(double& s, double& c, double x) {
-    const double u = s + x;
-    c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
-    s = u;
-}
-
-// dots[k][mv][t] = sum over the mv's table entries of partial[k][e][t], in order.
+// dots[k][mv][t] = sum over the mv's table entries of partial[k][e][t], in order
+// (launched for the last step only; the step kernels reduce the others).
 __global__ __launch_bounds__(64) void batched_reduce_kernel(const double* __restrict__ partial, int nentries,
                                                             int width, const int32_t* __restrict__ e0,
                                                             const int32_t* __restrict__ e1, int nmv,
@@ -243,18 +269,25 @@ template <typename TA, typename TV>
 hipError_t enqueue_batched(hipStream_t s, const BatchPlan& P) {
     dim3 fill_grid(256, P.nmv);
     batched_fill_kernel<TV><<<fill_grid, 256, 0, s>>>(P.d_mvs, P.ld);
+    const size_t width = 2 * (size_t)P.ld;
+    // partials of step k go to half k & 1; step k reduces step k - 1's half
     for (int k = 0; k < P.K; ++k) {
-        double* pk = P.d_partial + (size_t)k * P.nentries * 2 * P.ld;
+        double* pk = P.d_partial + (size_t)(k & 1) * P.nentries * width;
         if (k == 0)
             batched_step_kernel<TA, TV, true, 7><<<P.nentries, kThreads, 0, s>>>(
-                P.d_entries, P.d_mvs, 0, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk);
+                P.d_entries, P.d_mvs, 0, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk, nullptr, P.d_e0, P.d_e1,
+                nullptr);
         else
             batched_step_kernel<TA, TV, false, 7><<<P.nentries, kThreads, 0, s>>>(
-                P.d_entries, P.d_mvs, k & 1, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk);
+                P.d_entries, P.d_mvs, k & 1, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk,
+                P.d_partial + (size_t)((k - 1) & 1) * P.nentries * width, P.d_e0, P.d_e1,
+                P.d_dots + (size_t)(k - 1) * P.nmv * width);
     }
-    if (P.K > 0) {
-        dim3 rg((2 * P.ld + 63) / 64, P.K, P.nmv);
-        batched_reduce_kernel<<<rg, 64, 0, s>>>(P.d_partial, P.nentries, 2 * P.ld, P.d_e0, P.d_e1, P.nmv, P.d_dots);
+    if (P.K > 0) {  // the last step's dots
+        dim3 rg((unsigned)((width + 63) / 64), 1, P.nmv);
+        batched_reduce_kernel<<<rg, 64, 0, s>>>(P.d_partial + (size_t)((P.K - 1) & 1) * P.nentries * width,
+                                                P.nentries, (int)width, P.d_e0, P.d_e1, P.nmv,
+                                                P.d_dots + (size_t)(P.K - 1) * P.nmv * width);
     }
     dim3 ag((P.ld * (P.M + 1) + 255) / 256, P.nmv);
     batched_assemble_kernel<<<ag, 256, 0, s>>>(P.d_dots, P.d_mvs, P.nmv, P.ld, P.M, P.nvec, P.d_zeta);
@@ -296,6 +329,18 @@ void kpm_batch_free(kpm_ctx* ctx) {
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Lower bound on the table entries (workgroups) per mv when there are more
+// mvs than resident workgroups.  The proportional share then rounds to one
+// workgroup each, so about as many mvs as resident workgroups are in flight
+// at once and their gathered probe blocks (512 KB each at n = 2,048, 64 FP32
+// probes) far exceed the caches.  Splitting each mv over at least 16
+// workgroups keeps a few mvs per XCD in flight: 9,216 matrices of n = 2,048,
+// degree 127, 256 probes took 1.34 s instead of 2.07 s (32 or 43 workgroups
+// per mv: no further gain).  With fewer mvs the table stays at one wave of
+// resident workgroups: the same bound on the 48-matrix uneven batch pushed
+// it past one wave and cost 30 %.
+constexpr int kMinEntriesPerMv = 16;
 
 extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
                                           const double* ub, const kpm_moment_opts* o, double* mu,
@@ -368,7 +413,8 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         P.precision = o->precision;
         P.val_f64 = D[0].val_f64;
         P.nmv = nmat * nvb;
-        // work table: workgroups per mv proportional to its bytes of work
+        // work table: workgroups per mv proportional to its bytes of work,
+        // and at least kMinEntriesPerMv (or one per panel) for every mv
         const int resident = o->precision == KPM_FP64
                                  ? (P.val_f64 ? batched_resident<double, double>() : batched_resident<float, double>())
                                  : batched_resident<float, float>();
@@ -387,12 +433,13 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         // stride through it.
         int64_t total_entries = 0;
         std::vector<int> gws(P.nmv);
+        const int minw = P.nmv > target ? kMinEntriesPerMv : 1;
         for (int m = 0; m < nmat; ++m)
             for (int vb = 0; vb < nvb; ++vb) {
                 const int mv = m * nvb + vb;
                 const int panels = (int)((D[m].n + P.rows - 1) / P.rows);
-                int gw = (int)std::lround(target * work[mv] / wsum);
-                gws[mv] = std::max(1, std::min(gw, panels));
+                const int gw = (int)std::lround(target * work[mv] / wsum);
+                gws[mv] = std::max(std::min(panels, minw), std::min(gw, panels));
                 total_entries += gws[mv];
             }
         const int nb = (int)total_entries;
@@ -447,7 +494,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         const size_t o_e1 = off;
         off += align256((size_t)P.nmv * 4);
         const size_t o_part = off;
-        off += align256((size_t)std::max(P.K, 1) * P.nentries * 2 * g.ld * 8);
+        off += align256((size_t)std::min(std::max(P.K, 1), 2) * P.nentries * 2 * g.ld * 8);
         const size_t o_dots = off;
         off += align256((size_t)std::max(P.K, 1) * P.nmv * 2 * g.ld * 8);
         const size_t o_zeta = off;

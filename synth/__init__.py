@@ -31,6 +31,7 @@ __all__ = [
     "add_long_range",
     "diagonal_matrix",
     "batched_uneven_set",
+    "damping_training_set",
     "config_matrix",
     "CONFIGS",
 ]
@@ -179,6 +180,20 @@ def batched_uneven_set(count: int = 48, seed_base: int = 3000) -> list[CSR]:
     return mats
 
 
+def damping_training_set(n_random: int = 8192, n_anderson: int = 1024, seed_base: int = 4000) -> list[CSR]:
+    """The damping network's training family at full size: ``n_random``
+    random sparse symmetric matrices (n = 2,048, 4.5 n mirrored N(0, 1)
+    pairs, uniform [-1, 1] diagonal, about 10 entries per row) followed by
+    ``n_anderson`` 2D Anderson matrices (32 x 64 periodic lattice, diagonal
+    disorder of width W in [1, 16], W = 1 + 15 frac(i * golden ratio)).
+    Matrix i uses seed seed_base + i."""
+    mats = [random_sparse_symmetric(2048, 4.5, seed_base + i) for i in range(n_random)]
+    for i in range(n_anderson):
+        W = 1.0 + 15.0 * ((i * 0.6180339887498949) % 1.0)
+        mats.append(add_diagonal_disorder(laplacian2d_periodic(32, 64), W, seed_base + n_random + i))
+    return mats
+
+
 # Workload registry.  Seeds: matrix 1000+cfg, probe vectors 2000+cfg, Lanczos 3000+cfg.
 CONFIGS = {
     "c1": dict(name="lap2d_dirichlet_32x32", M=100, nvec=20, block=20, precision="f64",
@@ -187,6 +202,8 @@ CONFIGS = {
                vec_seed=2002, lanczos_seed=3002),
     "c3": dict(name="batched_uneven_48", M=200, nvec=32, block=32, precision="f32",
                vec_seed=2003, lanczos_seed=3003),
+    "c4": dict(name="damping_training_set_8192_random_1024_anderson2d", M=127, nvec=256, block=64,
+               precision="f32", vec_seed=2004, lanczos_seed=3004),
     "c5": dict(name="anderson3d_128cubed_longrange", M=1000, nvec=256, block=64,
                precision="f32", vec_seed=2005, lanczos_seed=3005),
 }

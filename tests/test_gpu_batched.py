@@ -163,6 +163,48 @@ def test_c3_full_size_sampled(ctx):
         assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
 
 
+def test_training_set_full_size_sampled(ctx):
+    """The damping network's training family at full size in one batched
+    call: 8,192 random sparse symmetric matrices (n = 2,048) and 1,024 2D
+    Anderson 32 x 64 matrices, degree 127, 256 probes each as 4 blocks of
+    64, FP32 (36,864 (matrix, probe block) pairs).  Bounds: 20-step Lanczos
+    with the same escape recovery as the uneven batch (random sparse
+    matrices often have an outlying extreme eigenvalue the start vector
+    barely sees).  The oracle checks matrices at both ends of each family
+    and a few recovered ones over all 256 probes."""
+    _say("training set: generating 9,216 matrices")
+    mats = synth.damping_training_set()
+    assert len(mats) == 9216 and all(A.n == 2048 for A in mats)
+    D = [dev(A, "f32") for A in mats]
+    _say("training set: bounds")
+    bl = [kpm.kpm_bounds(ctx, d, 20, 3004, 0.01) for d in D]
+    lb = np.array([b[0] for b in bl])
+    ub = np.array([b[1] for b in bl])
+    recovered = []
+    for attempt in range(3):
+        _say(f"training set: batched moments, attempt {attempt}")
+        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, block=64, return_max_abs=True)
+        bad = [m for m in range(len(D)) if not mx[m] <= 1 + 1e-4]
+        if not bad:
+            break
+        recovered += bad
+        for m in bad:
+            if attempt == 0:
+                lb[m], ub[m] = kpm.kpm_bounds(ctx, D[m], 20, 3004, 0.04)
+            else:
+                lo, hi = kpm.kpm_gershgorin(ctx, D[m])
+                lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
+    assert not bad
+    mu2 = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, block=64)
+    assert np.array_equal(mu, mu2)
+    assert mu.shape == (9216, 128)
+    assert np.all(mu[:, 0] == 1.0) and np.all(np.abs(mu) <= 1 + 1e-6)
+    for m in sorted({0, 1, 4095, 8191, 8192, 9215} | set(recovered[:4])):
+        _say(f"training set: oracle matrix {m}")
+        ref = oracle_mu(mats[m], lb[m], ub[m], 127, 256, 2004 + m, "f32")
+        assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
+
+
 def test_robust_single_matrix_recovers_escape(ctx):
     """The same edge-state miss on matrix 41 of the uneven set, through the
     single-matrix robust entry point."""
