@@ -55,7 +55,8 @@ def oracle_mu(A, lb, ub, M, nvec, seed, dtype):
 
 
 @pytest.mark.parametrize("dtype,tol,M,nvec,block", [("f32", 1e-5, 40, 10, 4), ("f64", 1e-12, 33, 6, 0),
-                                                    ("f32", 1e-5, 1, 3, 0), ("f32", 1e-5, 0, 2, 0)])
+                                                    ("f32", 1e-5, 1, 3, 0), ("f32", 1e-5, 0, 2, 0),
+                                                    ("f32", 1e-5, 3, 5, 0), ("f64", 1e-12, 4, 3, 2)])
 def test_batched_parity_small(ctx, dtype, tol, M, nvec, block):
     _say(f"batched small {dtype} M={M} nvec={nvec} block={block}")
     mats = small_set()
@@ -161,6 +162,30 @@ def test_c3_full_size_sampled(ctx):
         _say(f"c3 oracle matrix {m} (n={mats[m].n})")
         ref = oracle_mu(mats[m], lb[m], ub[m], 200, 32, 2003 + m, "f32")
         assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_many_small_matrices_every_matrix(ctx, dtype, tol):
+    """More (matrix, probe block) pairs than resident workgroups (3,000
+    random sparse matrices, n = 150..349, 64 probes each): the work table
+    then splits every pair over up to 16 workgroups, and each step launch
+    reduces the previous step's partials.  Every matrix against the oracle."""
+    _say(f"many small matrices {dtype}")
+    mats = [synth.random_sparse_symmetric(150 + (i * 37) % 200, 4.5, 50_000 + i) for i in range(3000)]
+    D = [dev(A, dtype) for A in mats]
+    lo_hi = [kpm.kpm_gershgorin(ctx, d) for d in D]
+    lb = np.array([lo - 0.01 * (hi - lo) for lo, hi in lo_hi])
+    ub = np.array([hi + 0.01 * (hi - lo) for lo, hi in lo_hi])
+    M, nvec = 9, 64
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=64)
+    mu_direct = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=64, graph=False)
+    assert np.array_equal(mu, mu_direct)
+    worst = 0.0
+    for m, A in enumerate(mats):
+        ref = oracle_mu(A, lb[m], ub[m], M, nvec, 7000 + m, dtype)
+        worst = max(worst, float(np.max(np.abs(mu[m] - ref))))
+    _say(f"many small matrices {dtype}: worst |mu - oracle| = {worst:.3e}")
+    assert worst < tol
 
 
 def test_training_set_full_size_sampled(ctx):
