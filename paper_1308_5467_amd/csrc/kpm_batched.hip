@@ -8,7 +8,8 @@
 // share of the row panels of one mv, the number of workgroups per mv
 // proportional to its bytes of work and the total close to the number of
 // workgroups resident on the device, so small matrices never leave the GPU
-// idle and each workgroup writes exactly one dot partial per step.
+// idle and each workgroup writes exactly one dot partial per step (with more
+// mvs than resident workgroups, every mv gets at least kMinEntriesPerMv).
 // Workgroup b reads table entry xcd_panel(b), so consecutive entries run on
 // the same XCD; the entries of one mv on one XCD share a contiguous panel
 // range and stride through it together (one moving band of rows per mv and
