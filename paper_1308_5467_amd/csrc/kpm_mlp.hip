@@ -281,7 +281,8 @@ struct MlpBufs {  // activations for a batch of N rows
 // Forward pass of a few rows (inference on one moment vector): one
 // workgroup per row keeps the activations in LDS and runs the three layers
 // in one launch; thread t owns output column t of each layer and reads
-// column t of the weights (coalesced over the workgroup).  Each output is
+// column t of the weights (coalesced over the workgroup), 32 weights in
+// flight per thread ahead of the FMA chain.  Each output is
 // the same k-ordered FMA chain plus bias as in the tiled GEMM, so the
 // result is bitwise that of the batched path.
 constexpr int kSmallRows = 16;
@@ -296,18 +297,18 @@ __global__ __launch_bounds__(NH) void forward_small_kernel(const float* __restri
     const float* __restrict__ W2 = p + P_W2;
     const float* __restrict__ W3 = p + P_W3;
     float acc = 0.0f;
-#pragma unroll 8
+#pragma unroll 32
     for (int k = 0; k < NIN; ++k) acc = fmaf(xs[k], W1[k * NH + t], acc);
     h1[t] = gelu_f(acc + p[P_B1 + t]);
     __syncthreads();
     acc = 0.0f;
-#pragma unroll 8
+#pragma unroll 32
     for (int k = 0; k < NH; ++k) acc = fmaf(h1[k], W2[k * NH + t], acc);
     h2[t] = gelu_f(acc + p[P_B2 + t]);
     __syncthreads();
     if (t < NOUT) {
         acc = 0.0f;
-#pragma unroll 8
+#pragma unroll 32
         for (int k = 0; k < NH; ++k) acc = fmaf(h2[k], W3[k * NOUT + t], acc);
         g[row * NOUT + t] = t == 0 ? 1.0f : sigmoid_f(acc + p[P_B3 + t]);
     }
