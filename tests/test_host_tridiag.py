@@ -98,3 +98,22 @@ def test_random_tridiagonals_property(m, seed, scale, zeros):
         iso[:-1] &= ~small
         iso[1:] &= ~small
     assert np.max(np.abs(w[iso] - rw[iso]), initial=0.0) < 1e-9
+
+
+@pytest.mark.parametrize("m,seed", [(1, 10), (2, 11), (5, 12), (20, 13), (32, 14)])
+def test_flipped_matrix_gives_last_components(m, seed):
+    """The spectral bounds widen the extreme Ritz values by beta_m |s_m| with
+    s_m the last component of the Ritz vector (section 3.1.1): the library
+    takes it from the first-component weights of the reversed tridiagonal
+    J T J (J the reversal), whose eigenvectors are T's read backwards."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-2, 2, m)
+    b = rng.uniform(0.1, 1.0, max(m - 1, 0))
+    th, w = kpm.kpm_tridiag_eig(a[::-1].copy(), b[::-1].copy())
+    if m == 1:
+        rth, last = a.copy(), np.ones(1)
+    else:
+        rth, Z = sla.eigh_tridiagonal(a, b)
+        last = Z[-1] ** 2
+    assert np.max(np.abs(th - rth)) < 1e-13
+    assert np.max(np.abs(w - last)) < 1e-11
