@@ -134,6 +134,34 @@ def test_diagonal_and_one_by_one(ctx):
     assert np.max(np.abs(mu1 - np.array([[1.0, 0.0, -1.0, 0.0][k % 4] for k in range(41)]))) < 1e-15
 
 
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f64", TOL64)])
+def test_empty_rows_and_zero_matrix(ctx, prec, tol):
+    """Rows without stored entries.  The zero matrix (nnz = 0) on [-1, 1]:
+    B = 0, so mu_k = T_k(0) = cos(k pi / 2) exactly; its bounds fall back on
+    the Gershgorin hull (Lanczos breaks down at once) and enclose 0.  A
+    diagonal matrix with every other row empty against the oracle, and both
+    in one batch."""
+    n = 500
+    Z = synth.CSR(n, np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), np.zeros(0))
+    exact = np.array([[1.0, 0.0, -1.0, 0.0][k % 4] for k in range(21)])
+    mu = kpm.kpm_moments(ctx, dev(Z, prec), -1.0, 1.0, 20, 8, 5, precision=prec)
+    assert np.array_equal(mu, exact)
+    lb, ub = kpm.kpm_bounds(ctx, dev(Z, prec), 20, 1, 0.01)
+    assert np.isfinite(lb) and np.isfinite(ub) and lb < 0.0 < ub
+    d = np.random.default_rng(4).uniform(-2.0, 3.0, n)
+    keep = np.arange(n) % 2 == 0
+    rp = np.concatenate([[0], np.cumsum(keep)]).astype(np.int32)
+    H = synth.CSR(n, rp, np.nonzero(keep)[0].astype(np.int32), d[keep])
+    Ho = H if prec == "f64" else H.rounded_f32()
+    ref = oracle.moments(Ho, -2.5, 3.5, 30, 6, 11)
+    mu_h = kpm.kpm_moments(ctx, dev(H, prec), -2.5, 3.5, 30, 6, 11, precision=prec)
+    assert np.max(np.abs(mu_h - ref)) < tol
+    mub = kpm.kpm_moments_batched(ctx, [dev(Z, prec), dev(H, prec)], [-1.0, -2.5], [1.0, 3.5], 30, 6, 11,
+                                  precision=prec)
+    assert np.max(np.abs(mub[0] - np.array([[1.0, 0.0, -1.0, 0.0][k % 4] for k in range(31)]))) < 1e-15
+    assert np.max(np.abs(mub[1] - oracle.moments(Ho, -2.5, 3.5, 30, 6, 12))) < tol
+
+
 def test_deterministic_bitwise(ctx):
     A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(20), 8.0, 2)
     D = dev(A, "f32")
