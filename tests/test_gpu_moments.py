@@ -104,6 +104,33 @@ def test_random_sparse_fp64_parity(ctx, block):
     assert np.max(np.abs(pv - ref)) < TOL64
 
 
+def test_widest_fp64_block_ragged(ctx):
+    """FP64 path with the widest probe block (128 probes: 64 rows of 2-wide
+    packs per wavefront pass) and a ragged second block of 22, per probe."""
+    _say("random sparse fp64 block=128 nvec=150")
+    A = synth.random_sparse_symmetric(1001, 4.5, 23)
+    b = oracle.lanczos_bounds(A, 20, 4)
+    mu, pv = kpm.kpm_moments(ctx, dev(A, "f64"), b["lb"], b["ub"], 21, 150, 6, precision="f64", block=128,
+                             per_vector=True)
+    ref = oracle_per_vec(A, b["lb"], b["ub"], 21, 150, 6)
+    assert np.max(np.abs(pv - ref)) < TOL64
+    assert np.max(np.abs(mu - ref.mean(axis=0))) < TOL64
+
+
+def test_high_degree_fp64(ctx):
+    """Degree 2,048 (1,024 steps with the product identity) against the
+    oracle's plain three-term recurrence, per probe: the doubling's rounding
+    stays at the FP64 bar far out."""
+    _say("fp64 M=2048")
+    A = synth.add_diagonal_disorder(synth.laplacian2d_dirichlet(24), 4.0, 31)
+    lam = np.linalg.eigvalsh(A.dense())  # exact extremes: a 20-step bound can miss an edge state here
+    w = lam[-1] - lam[0]
+    lb, ub = lam[0] - 0.01 * w, lam[-1] + 0.01 * w
+    mu, pv = kpm.kpm_moments(ctx, dev(A, "f64"), lb, ub, 2048, 3, 8, precision="f64", per_vector=True)
+    ref = oracle_per_vec(A, lb, ub, 2048, 3, 8)
+    assert np.max(np.abs(pv - ref)) < TOL64
+
+
 def test_fp64_values_fp32_path_rounds_values(ctx):
     """FP64 values on the FP32 path are rounded to FP32 first."""
     A = synth.random_sparse_symmetric(1500, 3.0, 3)
