@@ -34,12 +34,21 @@ SIGMA = 0.02
 TRUNC = (15, 23, 31, 47, 63, 95, 127)
 DEGREES = (16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 127)
 SLQ_STEPS = (40, 50, 60, 65, 70, 80, 100)
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def _save_study(name, data):
+    """Write a study table as JSON into $KPM_STUDY_DIR (nothing when unset)."""
+    out = os.environ.get("KPM_STUDY_DIR")
+    if not out:
+        return
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, name), "w") as f:
+        json.dump(data, f, indent=1)
 
 
 @pytest.fixture(scope="module")
@@ -149,9 +158,7 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
     summary = dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L,
                    slq_rows=slq_rows, M_slq_fp64=M_S,
                    train_loss_first=float(losses[0]), train_loss_last=float(losses[-1]))
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "accuracy_study.json"), "w") as f:
-        json.dump(summary, f, indent=1)
+    _save_study("accuracy_study.json", summary)
     _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}; Lanczos steps {M_S}")
     assert M_L < M_J
     # the network must not be worse than Jackson at the same degree and precision
@@ -183,9 +190,8 @@ def test_fp32_learned_vs_fp64_jackson_on_large(ctx, trained):
     rows = _degree_rows(ctx, mu32, mu64, ref)
     M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
     M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "accuracy_study_large.json"), "w") as f:
-        json.dump(dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, nvec=nvec), f, indent=1)
+    _save_study("accuracy_study_large.json",
+                dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, nvec=nvec))
     _say(f"large workload, degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}")
     assert M_L < M_J
     for r in rows:
