@@ -271,37 +271,42 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
     nvec = 64
 
     # both forms as one library call each (bounds, moments, damping, density)
-    def fp64_jackson():
+    def fp64_jackson(block=0):
         return kpm.kpm_dos_pipeline(ctx, D64, M_FP64_JACKSON, nvec, 2002, x, precision="f64",
-                                    damping=kpm.KPM_DAMP_JACKSON)[0]
+                                    damping=kpm.KPM_DAMP_JACKSON, block=block)[0]
 
     def fp32_learned():
         return kpm.kpm_dos_pipeline(ctx, D32, M_FP32_LEARNED, nvec, 2002, x, precision="f32",
                                     damping=kpm.KPM_DAMP_LEARNED)[0]
 
     lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
-    t64 = _time_ms(fp64_jackson, reps)
+    # the FP64 baseline at its faster probe block (32 is the default; 64 wins on
+    # matrices whose gathers miss the caches anyway)
+    t64_by_block = {b: _time_ms(lambda: fp64_jackson(b), reps) for b in (32, 64)}
+    b64 = min(t64_by_block, key=t64_by_block.get)
+    t64 = t64_by_block[b64]
     t32 = _time_ms(fp32_learned, reps)
     m64 = _time_ms(lambda: kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64",
-                                           validate=False), reps)
+                                           block=b64, validate=False), reps)
     m32 = _time_ms(lambda: kpm.kpm_moments(ctx, D32, lb, ub, M_FP32_LEARNED, nvec, 2002, precision="f32",
                                            validate=False), reps)
     # the FP64 step kernel against the HBM roofline (values, V, U in FP64)
     kpm.kpm_profile_reset(ctx)
     kpm.kpm_profile_enable(ctx, True)
-    kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", validate=False)
+    kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", block=b64, validate=False)
     kpm.kpm_profile_enable(ctx, False)
     nl, ms = kpm.kpm_profile_query(ctx, "cheb_step")
-    us64 = ms / max(nl, 1) * 1000.0
-    bytes64 = 12 * A.nnz + 4 * (A.n + 1) + 24 * A.n * nvec
+    us64 = ms / max(nl, 1) * 1000.0  # one launch per probe block of b64 probes
+    bytes64 = 12 * A.nnz + 4 * (A.n + 1) + 24 * A.n * b64
     return {"criterion": "L1(sigma=0.02) <= 1e-2 against the FP64 oracle's degree-512 series, same probes",
             "accuracy_source": "tests/test_gpu_accuracy.py",
             "M_fp64_jackson": M_FP64_JACKSON, "M_fp32_learned": M_FP32_LEARNED,
             "ms_fp64_jackson_pipeline": round(t64, 3), "ms_fp32_learned_pipeline": round(t32, 3),
+            "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 3) for b, t in t64_by_block.items()},
             "speedup_pipeline": round(t64 / t32, 2),
             "ms_fp64_moments": round(m64, 3), "ms_fp32_moments": round(m32, 3),
             "speedup_moments": round(m64 / m32, 2),
-            "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
+            "fp64_block": b64, "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
             "fp64_step_frac_of_hbm_peak": round(bytes64 / (us64 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
@@ -380,16 +385,17 @@ def large_leg(kpm, ctx, synth, reps=3):
     byts_uncached = byts + (A.nnz - 7 * A.n) * 4 * 64
     kpm.kpm_mlp_init(ctx, 1)
 
-    def fp64_jackson():
+    def fp64_jackson(block=0):
         phi, _, _, _ = kpm.kpm_dos_pipeline(ctx, D64, M_LARGE_FP64_JACKSON, nvec, 2005, x, precision="f64",
-                                            damping=kpm.KPM_DAMP_JACKSON, lanczos_seed=3005)
+                                            damping=kpm.KPM_DAMP_JACKSON, lanczos_seed=3005, block=block)
         return phi
 
     def fp32_learned():
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_LEARNED, nvec, 2005, x, precision="f32",
                                     damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005)[0]
 
-    t64 = _time_ms(fp64_jackson, reps)
+    t64_by_block = {b: _time_ms(lambda: fp64_jackson(b), reps) for b in (32, 64)}  # the faster is the baseline
+    t64 = min(t64_by_block.values())
     t32 = _time_ms(fp32_learned, reps)
     return {"workload": "anderson3d_128^3_W16_plus_2_longrange_pairs_per_row", "n": A.n, "nnz": A.nnz,
             "M": M, "nvec": nvec, "block": 64, "ms_moments": round(t_mom, 2),
@@ -401,6 +407,7 @@ def large_leg(kpm, ctx, synth, reps=3):
                                "accuracy_source": "tests/test_gpu_accuracy.py::test_fp32_learned_vs_fp64_jackson_on_large",
                                "M_fp64_jackson": M_LARGE_FP64_JACKSON, "M_fp32_learned": M_LARGE_FP32_LEARNED,
                                "ms_fp64_jackson_pipeline": round(t64, 2), "ms_fp32_learned_pipeline": round(t32, 2),
+                               "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 2) for b, t in t64_by_block.items()},
                                "speedup_pipeline": round(t64 / t32, 2)}}
 
 

@@ -75,7 +75,8 @@ enum {
 typedef struct {
     int32_t M;          /* degree: moments mu_0 .. mu_M are returned, M >= 0   */
     int32_t nvec;       /* number of probe vectors, >= 1                       */
-    int32_t block;      /* probe vectors per device block, 0 = library choice;
+    int32_t block;      /* probe vectors per device block, 0 = library choice
+                           (64 FP32 or 32 FP64: 256-byte probe rows);
                            at most 256 (FP32) or 128 (FP64)                    */
     int32_t precision;  /* KPM_FP32 or KPM_FP64                                */
     uint64_t seed;      /* probe-vector seed                                   */

@@ -373,7 +373,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         if (o->validate && (st = kpm_validate_csr(ctx, D[m])) != KPM_OK) return st;
     }
     const int M = o->M, nvec = o->nvec;
-    const int b = o->block > 0 ? std::min(o->block, nvec) : std::min(nvec, 64);
+    const int b = o->block > 0 ? std::min(o->block, nvec) : kpm_default_block(nvec, o->precision);
     int64_t nmax = 0;
     for (int m = 0; m < nmat; ++m) nmax = std::max<int64_t>(nmax, D[m].n);
     const BlockGeom g = make_geom(nmax, b, o->precision, o->rows_per_block);

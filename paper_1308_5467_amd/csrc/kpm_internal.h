@@ -36,6 +36,9 @@ constexpr int kWaves = 4;        // wavefronts per workgroup of the step kernels
 constexpr int kThreads = 64 * kWaves;
 
 BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint);
+// Probe-block width used when the caller passes 0: min(nvec, 64) for FP32,
+// min(nvec, 32) for FP64 (256-byte probe rows).
+int kpm_default_block(int nvec, int precision);
 
 // ---------------------------------------------------------------- moments
 hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
