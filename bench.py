@@ -282,7 +282,7 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
     lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
     # the FP64 baseline at its faster probe block (32 is the default; 64 wins on
     # matrices whose gathers miss the caches anyway)
-    t64_by_block = {b: _time_ms(lambda: fp64_jackson(b), reps) for b in (32, 64)}
+    t64_by_block = {b: _time_ms(lambda b=b: fp64_jackson(b), reps) for b in (32, 64)}
     b64 = min(t64_by_block, key=t64_by_block.get)
     t64 = t64_by_block[b64]
     t32 = _time_ms(fp32_learned, reps)
@@ -394,7 +394,7 @@ def large_leg(kpm, ctx, synth, reps=3):
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_LEARNED, nvec, 2005, x, precision="f32",
                                     damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005)[0]
 
-    t64_by_block = {b: _time_ms(lambda: fp64_jackson(b), reps) for b in (32, 64)}  # the faster is the baseline
+    t64_by_block = {b: _time_ms(lambda b=b: fp64_jackson(b), reps) for b in (32, 64)}  # the faster is the baseline
     t64 = min(t64_by_block.values())
     t32 = _time_ms(fp32_learned, reps)
     return {"workload": "anderson3d_128^3_W16_plus_2_longrange_pairs_per_row", "n": A.n, "nnz": A.nnz,
