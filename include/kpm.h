@@ -218,7 +218,14 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
  * largest |v_l^T T_k(B) v_l| / n over probes and degrees of each matrix (at
  * most 1 when its spectrum lies in [lb, ub]; +inf if non-finite).  Returns
  * KPM_ERR_SPECTRUM (after writing every output) if a matrix's spectrum is
- * not inside its [lb, ub].  nmat <= 65535.
+ * not inside its [lb, ub].  nmat <= 65535, and at most 65535 (matrix, probe
+ * block) pairs.  Device memory (one allocation per shape, kept by the
+ * context until the shape changes or kpm_destroy): two probe blocks of
+ * n_m x ld values per pair, dot partials of two steps per workgroup (2 x 2 x
+ * ld doubles each; a pair gets at least 16 workgroups when there are more
+ * pairs than resident workgroups), K x 2 x ld doubles of dots per pair and
+ * the per-probe moments -- about 40 GB for 9,216 matrices of n = 2,048 with
+ * 256 FP32 probes each.  KPM_ERR_ALLOC if it cannot be allocated.
  */
 kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
                                const double* ub, const kpm_moment_opts* opts, double* mu,
