@@ -224,7 +224,7 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
  * n_m x ld values per pair, dot partials of two steps per workgroup (2 x 2 x
  * ld doubles each; a pair gets at least 16 workgroups when there are more
  * pairs than resident workgroups), K x 2 x ld doubles of dots per pair and
- * the per-probe moments -- about 40 GB for 9,216 matrices of n = 2,048 with
+ * the per-probe moments -- about 45 GB for 9,216 matrices of n = 2,048 with
  * 256 FP32 probes each.  KPM_ERR_ALLOC if it cannot be allocated.
  */
 kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
