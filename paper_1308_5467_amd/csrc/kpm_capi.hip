@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -215,6 +216,7 @@ extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
     for (auto& kv : ctx->prof_map)
         for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
     if (ctx->pinned) hipHostFree(ctx->pinned);
+    if (ctx->copy_done) hipEventDestroy(ctx->copy_done);
     delete ctx;
     return KPM_OK;
 }
@@ -231,10 +233,11 @@ extern "C" const char* kpm_last_error(const kpm_ctx* ctx) {
 }
 
 // ---------------------------------------------------------------- bounds
-extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed,
-                                 double margin, double* lb, double* ub) {
-    if (!ctx) return KPM_ERR_ARG;
-    ctx->err.clear();
+// The bounds of kpm_bounds.  `overlap` (nullable) enqueues more work on the
+// context's stream after the Lanczos coefficients' copy; the host then waits
+// for the copy alone, so that work runs while the host finishes the bounds.
+static kpm_status bounds_impl(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed, double margin,
+                              double* lb, double* ub, const std::function<kpm_status()>& overlap) {
     if (!lb || !ub) return kpm_fail(ctx, KPM_ERR_ARG, "lb/ub output is NULL");
     if (steps < 1 || steps > 32) return kpm_fail(ctx, KPM_ERR_ARG, "steps must be in [1, 32]");
     if (!(margin >= 0.0 && margin < 0.5)) return kpm_fail(ctx, KPM_ERR_ARG, "margin must be in [0, 0.5)");
@@ -263,7 +266,14 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     void* stage;
     if ((st = kpm_pinned(ctx, 256 * 8, &stage)) != KPM_OK) return st;
     KPM_HIP(ctx, hipMemcpyAsync(stage, coef, 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
-    if ((st = sync(ctx)) != KPM_OK) return st;
+    if (overlap) {
+        if (!ctx->copy_done) KPM_HIP(ctx, hipEventCreateWithFlags(&ctx->copy_done, hipEventDisableTiming));
+        KPM_HIP(ctx, hipEventRecord(ctx->copy_done, ctx->stream));
+        if ((st = overlap()) != KPM_OK) return st;
+        KPM_HIP(ctx, hipEventSynchronize(ctx->copy_done));
+    } else if ((st = sync(ctx)) != KPM_OK) {
+        return st;
+    }
     std::vector<double> hc((const double*)stage, (const double*)stage + 256);
     // Breakdown test in step order: stop at the first residual below 1e-12 of
     // the largest coefficient seen so far.
@@ -320,6 +330,13 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     *lb = c - d;
     *ub = c + d;
     return KPM_OK;
+}
+
+extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed,
+                                 double margin, double* lb, double* ub) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    return bounds_impl(ctx, Ain, steps, seed, margin, lb, ub, nullptr);
 }
 
 extern "C" kpm_status kpm_gershgorin(kpm_ctx* ctx, const kpm_csr* Ain, double* lo, double* hi) {
@@ -413,7 +430,7 @@ static kpm_status moments_collect(kpm_ctx* ctx, const MomentsPending& P, double*
 // device results are described there; finish with moments_collect.
 static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
                                const kpm_moment_opts* o, double* mu, double* mu_per_vec, bool legendre,
-                               MomentsPending* pending = nullptr) {
+                               MomentsPending* pending = nullptr, bool block0_filled = false) {
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
     if (!o || (!mu && !pending)) return kpm_fail(ctx, KPM_ERR_ARG, "opts or mu is NULL");
@@ -470,7 +487,8 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
         }
         const int gridb = ncols == b ? grid : cheb_step_grid(A, o->precision, gb);
         const int64_t vec0 = (int64_t)blk * b;
-        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
+        if (!(blk == 0 && block0_filled))
+            KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
         const int swb = (gb.ld + 31) / 32;
         if (leg_rec)
             KPM_HIP(ctx, launch_sign_bits(ctx->stream, o->seed, vec0, ncols, A.n, swb, (uint32_t*)sgn));
@@ -770,10 +788,30 @@ extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lancz
     if (!o || !x || !phi || !lb || !ub || npts < 0) return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
     if (damping != KPM_DAMP_NONE && damping != KPM_DAMP_JACKSON && damping != KPM_DAMP_LEARNED)
         return kpm_fail(ctx, KPM_ERR_ARG, "unknown damping kind");
-    kpm_status st = kpm_bounds(ctx, A, lanczos_steps, lanczos_seed, margin, lb, ub);
+    // The first probe block does not depend on the bounds: it is filled while
+    // the host waits for the Lanczos coefficients (same arguments, hence the
+    // same block, as the fill moments_impl would otherwise launch).
+    bool prefilled = false;
+    auto prefill = [&]() -> kpm_status {
+        const int maxb = o->precision == KPM_FP64 ? 128 : 256;
+        if (o->nvec < 1 || o->nvec > (1 << 24) || o->block < 0 || o->block > maxb ||
+            (o->precision != KPM_FP32 && o->precision != KPM_FP64) || o->rows_per_block < 0 ||
+            o->rows_per_block > (1 << 20) || o->M < 0 || o->M > (1 << 20))
+            return KPM_OK;  // moments_impl reports the bad argument
+        const int b = o->block > 0 ? std::min(o->block, o->nvec) : default_block(o->nvec, o->precision);
+        const BlockGeom g = make_geom(A->n, b, o->precision, o->rows_per_block);
+        const int esz = o->precision == KPM_FP64 ? 8 : 4;
+        void* X0;
+        kpm_status s2 = kpm_ws(ctx, "X0", (size_t)A->n * g.ld * esz, &X0);
+        if (s2 != KPM_OK) return s2;
+        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A->n, o->precision, 1, X0));
+        prefilled = true;
+        return KPM_OK;
+    };
+    kpm_status st = bounds_impl(ctx, A, lanczos_steps, lanczos_seed, margin, lb, ub, prefill);
     if (st != KPM_OK) return st;
     MomentsPending P;
-    if ((st = moments_impl(ctx, A, *lb, *ub, o, nullptr, nullptr, false, &P)) != KPM_OK) return st;
+    if ((st = moments_impl(ctx, A, *lb, *ub, o, nullptr, nullptr, false, &P, prefilled)) != KPM_OK) return st;
     const int M = P.M;
     void *gd, *xd, *pd;
     if ((st = kpm_ws(ctx, "pipe_g", (size_t)(M + 1) * 8, &gd)) != KPM_OK) return st;

@@ -137,6 +137,7 @@ struct kpm_ctx {
     std::vector<double> host_scratch;
     void* pinned = nullptr;  // grow-only page-locked host staging for device-to-host copies
     size_t pinned_cap = 0;
+    hipEvent_t copy_done = nullptr;  // marks a device-to-host copy the host waits for alone
     // damping network
     bool mlp_ready = false;
     kpm_dev_buf mlp_params;
