@@ -48,6 +48,24 @@ def test_pipeline_equals_separate_calls(ctx, dtype, damping):
     assert np.max(np.abs(mu - ref)) < (1e-12 if dtype == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_pipeline_host_matrix(ctx, dtype):
+    """A host-resident CSR (FP64 values, copied in by each step; the FP32
+    path rounds them) through the pipeline, whose first probe block is
+    filled while the bounds finish, against the separate calls."""
+    A = synth.add_diagonal_disorder(synth.laplacian2d_dirichlet(40), 2.0, 12)
+    H = kpm.HostCSR(A.n, A.row_ptr, A.col_idx, A.val)
+    x = np.linspace(-5.0, 13.0, 57)
+    phi, mu, lb, ub = kpm.kpm_dos_pipeline(ctx, H, 40, 70, 5, x, precision=dtype, block=32)
+    lb2, ub2 = kpm.kpm_bounds(ctx, H, 20, 3002, 0.01)
+    mu2 = kpm.kpm_moments(ctx, H, lb2, ub2, 40, 70, 5, precision=dtype, block=32, validate=False)
+    phi2 = kpm.kpm_dos(ctx, mu2, kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, 40), lb2, ub2, x)
+    assert (lb, ub) == (lb2, ub2)
+    assert np.array_equal(mu, mu2) and np.array_equal(phi, phi2)
+    Ao = A if dtype == "f64" else A.rounded_f32()
+    assert np.max(np.abs(mu - oracle.moments(Ao, lb, ub, 40, 70, 5))) < (1e-12 if dtype == "f64" else 1e-5)
+
+
 @pytest.mark.parametrize("M", [127, 16])
 def test_pipeline_learned_damping(ctx, M):
     kpm.kpm_mlp_init(ctx, 5)
