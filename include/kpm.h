@@ -464,7 +464,8 @@ kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path);
 
 /*
  * kpm_hbm_copy_probe -- achievable device-memory bandwidth: a plain
- * streaming copy of `bytes` bytes (16-byte loads/stores) run `iters` times
+ * streaming copy of `bytes` bytes (one 16-byte non-temporal load and store
+ * per thread, one workgroup per 4 KiB) run `iters` times
  * between two context-owned buffers; *gbs = 2 * bytes * iters / time / 1e9.
  * The practical denominator beside the HBM specification peak and the
  * calibration kernel for hardware byte counters.

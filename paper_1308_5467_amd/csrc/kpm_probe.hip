@@ -1,5 +1,5 @@
-// Achievable-bandwidth probe: a plain streaming copy (16-byte loads and
-// stores, grid-stride) used as the practical denominator beside the HBM
+// Achievable-bandwidth probe: a plain streaming copy (16-byte non-temporal
+// loads and stores) used as the practical denominator beside the HBM
 // specification peak, and as the calibration kernel for the byte counters.
 #include <hip/hip_runtime.h>
 
@@ -7,20 +7,16 @@
 
 namespace kpm {
 
-// Each thread moves four 16-byte elements per iteration (four loads in
-// flight), strided by the grid so every wavefront access is contiguous.
-__global__ __launch_bounds__(256) void copy_probe_kernel(const float4* __restrict__ src,
-                                                         float4* __restrict__ dst, int64_t n4) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n4; i += stride) dst[i] = src[i];
+// One 16-byte element per thread with non-temporal loads and stores, one
+// workgroup per 4 KiB: the fastest plain copy measured on MI355X (6.6 TB/s
+// read + write for 1 GiB, against 4.4-5.9 TB/s for grid-stride loops of 1-8
+// elements per thread on 4-256 workgroups per CU, and 6.2 TB/s with cached
+// stores).
+typedef float probe_f4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_probe_kernel(const probe_f4* __restrict__ src,
+                                                         probe_f4* __restrict__ dst, int64_t n4) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace kpm
@@ -37,10 +33,9 @@ extern "C" kpm_status kpm_hbm_copy_probe(kpm_ctx* ctx, int64_t bytes, int iters,
     if ((st = kpm_ws(ctx, "probe_a", (size_t)n4 * 16, &a)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "probe_b", (size_t)n4 * 16, &b)) != KPM_OK) return st;
     KPM_HIP(ctx, hipMemsetAsync(a, 0, (size_t)n4 * 16, ctx->stream));
-    hipDeviceProp_t prop;
-    KPM_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
-    const int grid = prop.multiProcessorCount * 8;
-    kpm::copy_probe_kernel<<<grid, 256, 0, ctx->stream>>>((const float4*)a, (float4*)b, n4);  // warm-up
+    const int64_t grid = (n4 + 255) / 256;  // <= 2^24 for 64 GiB
+    kpm::copy_probe_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>((const kpm::probe_f4*)a, (kpm::probe_f4*)b,
+                                                                   n4);  // warm-up
     KPM_HIP(ctx, hipGetLastError());
     hipEvent_t e0, e1;
     KPM_HIP(ctx, hipEventCreate(&e0));
@@ -48,8 +43,8 @@ extern "C" kpm_status kpm_hbm_copy_probe(kpm_ctx* ctx, int64_t bytes, int iters,
     hipEventRecord(e0, ctx->stream);
     for (int i = 0; i < iters; ++i) {
         kpm_prof_begin(ctx, "copy_probe");
-        kpm::copy_probe_kernel<<<grid, 256, 0, ctx->stream>>>((const float4*)(i & 1 ? b : a),
-                                                              (float4*)(i & 1 ? a : b), n4);
+        kpm::copy_probe_kernel<<<(unsigned)grid, 256, 0, ctx->stream>>>(
+            (const kpm::probe_f4*)(i & 1 ? b : a), (kpm::probe_f4*)(i & 1 ? a : b), n4);
         kpm_prof_end(ctx, "copy_probe", 1);
     }
     hipEventRecord(e1, ctx->stream);
