@@ -4,23 +4,32 @@
 One step = one pass of the whole path over one synthetic matrix already
 resident in HBM: Lanczos bounds (20 steps, FP64) -> stochastic Chebyshev
 moments (probe fill, fused recurrence + dot steps, reductions) -> Jackson
-damping -> DOS on 200 points.  Workload (default): 3D Anderson model, 7-point
-periodic Laplacian on a 64^3 grid plus uniform[-8, 8] diagonal disorder
-(n = 262,144, nnz = 1,835,008), degree M = 256, 64 Rademacher probes, FP32
-values and vectors with FP64 dot accumulation.
+damping -> DOS on 200 points.
+
+Headline workload (the largest one that runs on one GPU): 3D Anderson model,
+7-point periodic Laplacian on a 128^3 grid plus uniform[-8, 8] diagonal
+disorder, plus 2 random N(0, 0.1^2) long-range pairs per row, mirrored
+(n = 2,097,152, nnz ~ 23.07M); degree M = 1000, 256 Rademacher probes as 4
+blocks of 64, FP32 values and vectors with FP64 dot accumulation.  The 64^3
+Anderson workload (degree 256, 64 probes) is reported as an extra leg.
 
 Metric: nnz * M * nvec / second (Chebyshev degree-moments per second).
 The roofline object reports the fused recurrence step kernel: algorithmic
-bytes per launch (8 nnz + 4 (n + 1) + 3 * 4 n b for FP32) over its average
-device duration, timed with HIP events on the library's stream inside the
-timed region.  The CPU baseline is the FP64 oracle (plain C recurrence,
-OpenMP over probes) on a bounded sample of the same workload.
+bytes per launch ((s_v + 4) nnz + 4 (n + 1) + 3 s_v n b, s_v = 4 for FP32)
+over its average device duration, timed with HIP events on the library's
+stream inside the timed region; `traffic` is the HBM bytes per launch from
+the committed rocprofv3 counter summary of the same kernel and workload,
+reported only while the step kernel's sources are the ones it was measured
+on (null otherwise).  The CPU baseline is the FP64 oracle (plain C
+recurrence, OpenMP over probes) on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,12 +39,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per dispatch of the fused step kernel on the default workload,
-# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
-# what the same counters read for a plain copy of known size (2.000 and
-# 1.000); see profiles/.  Only valid for the default workload and the
-# kernel version it was measured on.
-MEASURED_TRAFFIC_BYTES = 265830605
+# Sources that define the step kernel: a counter record in profiles/ is used
+# only while their contents hash to the value stored with it.
+STEP_SOURCES = ("paper_1308_5467_amd/csrc/kpm_step.h", "paper_1308_5467_amd/csrc/kpm_moments.hip")
+
+WORKLOADS = {
+    # name: (matrix config, degree, probes, block, probe seed, Lanczos seed)
+    "anderson3d_128^3_W16_longrange2": ("c5", 1000, 256, 64, 2005, 3005),
+    "anderson3d_64^3_periodic_W16": ("c2", 256, 64, 64, 2002, 3002),
+}
+HEADLINE = "anderson3d_128^3_W16_longrange2"
+
+
+def step_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summaries (lines 'traffic_record: kernel=... workload=...
+    bytes_per_launch=... fetch_kib=... write_kib=... step_sources=...'),
+    or (None, reason) when there is none for the current sources."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None, "no profiles/ directory"
+    cur = step_source_hash()
+    stale = None
+    for fn in sorted(os.listdir(d)):
+        with open(os.path.join(d, fn)) as f:
+            for ln in f:
+                m = re.match(r"traffic_record:\s*(.*)", ln.strip().strip("`"))
+                if not m:
+                    continue
+                kv = dict(t.split("=", 1) for t in m.group(1).split())
+                if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                    continue
+                if kv.get("step_sources") != cur:
+                    stale = fn
+                    continue
+                return {"bytes": int(kv["bytes_per_launch"]), "source": f"profiles/{fn}",
+                        "fetch_kib": float(kv["fetch_kib"]), "write_kib": float(kv["write_kib"])}, None
+    return None, (f"counters in profiles/{stale} predate the current step kernel" if stale
+                  else "no counter record for this kernel and workload")
 
 
 def parse():
@@ -43,21 +92,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--M", type=int, default=256)
-    ap.add_argument("--nvec", type=int, default=64)
-    ap.add_argument("--block", type=int, default=64)
-    ap.add_argument("--grid", type=int, default=64, help="side of the periodic cubic grid")
+    ap.add_argument("--M", type=int, default=0, help="degree (0: the workload's)")
+    ap.add_argument("--nvec", type=int, default=0, help="probes (0: the workload's)")
+    ap.add_argument("--block", type=int, default=0, help="probe block width (0: the workload's)")
     ap.add_argument("--rows-per-block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the equal-accuracy comparison and the batched-workload rate")
+                    help="skip the extra legs (64^3 workload, equal-accuracy comparisons, batched sets, ...)")
     ap.add_argument("--copy-probe-only", action="store_true",
                     help="only run the streaming-copy bandwidth probe (counter calibration)")
     ap.add_argument("--slq-only", action="store_true",
-                    help="only run the stochastic Lanczos leg on the workload (profiling)")
-    ap.add_argument("--large-only", action="store_true",
-                    help="only the large-workload leg (128^3 + long-range pairs, M = 1000, 256 probes)")
+                    help="only run the stochastic Lanczos leg on the 64^3 workload (profiling)")
     ap.add_argument("--training-set-only", action="store_true",
                     help="only the damping network's full-size training set (8,192 random n = 2,048 + "
                          "1,024 2D Anderson, M = 127, 256 probes)")
@@ -71,8 +118,132 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner measurements (profiling one geometry)")
     ap.add_argument("--cpu-sample-vectors", type=int, default=0,
-                    help="probes in the oracle sample (0 = all cores' worth)")
+                    help="probes in the oracle sample (0 = one per host core used, at most 16)")
+    ap.add_argument("--cpu-sample-degree", type=int, default=0,
+                    help="degree of the oracle sample (0 = 100 on the large workload, the full degree otherwise)")
     return ap.parse_args()
+
+
+def load_workload(kpm, synth, name, precision="f32"):
+    cfg, M, nvec, block, seed, lz_seed = WORKLOADS[name]
+    A = synth.config_matrix(cfg)
+    vals = A.val.astype(np.float32) if precision == "f32" else A.val
+    D = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, precision)
+    return A, D, dict(M=M, nvec=nvec, block=block, seed=seed, lz_seed=lz_seed)
+
+
+def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, warmup, precision="f32",
+                   rows_per_block=0, separate=True):
+    """Whole-path steps (bounds -> moments -> Jackson -> density) on one
+    workload, the step kernel against the HBM roofline, and the same four
+    steps as separate calls."""
+    import torch
+    x = np.linspace(-10.0, 22.0, 200)
+    # validate the matrix once, outside the timed region
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, lz_seed, 0.01)
+    kpm.kpm_moments(ctx, D, lb, ub, 2, 1, seed, precision=precision, validate=True)
+
+    def step():
+        phi, mu, _, _ = kpm.kpm_dos_pipeline(ctx, D, M, nvec, seed, x, precision=precision, block=block,
+                                             damping=kpm.KPM_DAMP_JACKSON, lanczos_steps=20, lanczos_seed=lz_seed,
+                                             margin=0.01, rows_per_block=rows_per_block)
+        return mu, phi
+
+    def step_separate():
+        lb, ub = kpm.kpm_bounds(ctx, D, 20, lz_seed, 0.01)
+        mu = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, seed, precision=precision, block=block,
+                             validate=False, rows_per_block=rows_per_block)
+        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
+        phi = kpm.kpm_dos(ctx, mu, g, lb, ub, x)
+        return mu, phi
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kpm.kpm_profile_enable(ctx, False)
+    ms_separate = None
+    if separate:
+        step_separate()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            step_separate()
+        torch.cuda.synchronize()
+        ms_separate = (time.perf_counter() - t2) * 1000.0 / steps
+    nl, step_ms_total = kpm.kpm_profile_query(ctx, "cheb_step")
+    nf, first_ms_total = kpm.kpm_profile_query(ctx, "cheb_first")
+    nlz, lz_ms_total = kpm.kpm_profile_query(ctx, "lanczos")
+
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    units = float(A.nnz) * M * nvec
+    s_v = 4 if precision == "f32" else 8
+    b = min(block, nvec)
+    nblocks_vec = (nvec + b - 1) // b
+    bytes_per_launch = (s_v + 4) * A.nnz + 4 * (A.n + 1) + 3 * s_v * A.n * b
+    avg_ms = step_ms_total / max(nl, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel = ("cheb_step_kernel<float, float, false, true, 7, false>" if precision == "f32"
+              else "cheb_step_kernel<double, double, false, true, 7, false>")
+    rec, why = counter_traffic(kernel, name)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": rec["bytes"] if rec else None,
+            "kernel": "cheb_step_kernel", "avg_launch_us": round(avg_ms * 1000, 2),
+            "launches": nl, "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    if rec:
+        roof["traffic_source"] = rec["source"]
+        roof["traffic_over_algorithmic"] = round(rec["bytes"] / bytes_per_launch, 3)
+        roof["traffic_rate_gbs"] = round(rec["bytes"] / (avg_ms * 1e-3) / 1e9, 1)
+    else:
+        roof["traffic_note"] = why
+    return {
+        "value": units / (ms_per_step / 1000.0), "ms_per_step": ms_per_step,
+        "config": {"workload": name, "n": A.n, "nnz": A.nnz, "M": M, "nvec": nvec, "block": b,
+                   "vector_blocks": nblocks_vec, "precision": precision, "dot_accumulation": "f64",
+                   "lanczos_steps": 20, "dos_points": 200, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "breakdown_ms_per_step": {"cheb_step_total": step_ms_total / steps,
+                                  "cheb_first": first_ms_total / steps,
+                                  "lanczos_enqueue_to_done": lz_ms_total / steps},
+        "ms_per_step_separate_calls": round(ms_separate, 4) if ms_separate is not None else None,
+        "hbm_gbs_whole_step_algorithmic": round(bytes_per_launch * ((M + 1) // 2) * nblocks_vec
+                                                / (ms_per_step * 1e-3) / 1e9, 1),
+        "lb_ub": [lb, ub],
+    }
+
+
+def cpu_baseline_leg(A, lb, ub, M, nvec, seed, args, full_M):
+    """The oracle as it stands on a bounded sample: one probe per host core
+    used (at most 16), at a reduced degree on the large workload (the
+    oracle's cost is linear in probes x degree, so the rate is the
+    workload's)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    nv = min(nvec, args.cpu_sample_vectors or cores)
+    Ms = args.cpu_sample_degree or (100 if full_M > 256 else full_M)
+    Ao = A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    ts = time.perf_counter()
+    oracle.moments_per_vector(Ao, c, d, Ms, nv, seed, nthreads=min(cores, nv))
+    te = time.perf_counter()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": float(A.nnz) * Ms * nv / (te - ts), "unit": "nnz*deg*vec/s", "cores": min(cores, nv),
+            "kind": "oracle",
+            "sample": f"{nv} of {nvec} probes at degree {Ms} of {full_M}, full matrix, FP64 plain recurrence "
+                      f"(no doubling), one probe per thread; {te - ts:.2f} s (cost is linear in probes x degree)",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -80,158 +251,89 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the KPM engine runs on one GPU per process here (probe blocks would shard across GPUs); --gpus must be 1"}))
         sys.exit(2)
-    import torch
+    import torch  # noqa: F401
     import paper_1308_5467_amd as kpm
     import synth
 
+    ctx = kpm.Context(0)
     if args.batched_only:
-        ctx = kpm.Context(0)
         print(json.dumps({"batched_uneven_48": batched_leg(kpm, ctx, synth, tune=not args.no_autotune)}))
         return
-
     if args.copy_probe_only:
-        ctx = kpm.Context(0)
         out = {f"copy_gbs_{sz >> 20}MiB": kpm.kpm_hbm_copy_probe(ctx, sz, 5) for sz in (1 << 30, 1 << 26)}
         print(json.dumps(out))
-        return
-
-    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(args.grid), 16.0, 1002)
-    vals = A.val.astype(np.float32) if args.precision == "f32" else A.val
-    D = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, args.precision)
-    ctx = kpm.Context(0)
-    M, nvec, block = args.M, args.nvec, args.block
-    x = np.linspace(-10.0, 22.0, 200)
-    if args.large_only:
-        print(json.dumps({"large": large_leg(kpm, ctx, synth)}))
-        return
-    if args.legendre_only:
-        print(json.dumps({"legendre_dgl": legendre_leg(kpm, ctx, D, x, args)}))
         return
     if args.training_set_only:
         print(json.dumps({"training_set": training_set_leg(kpm, ctx, synth, bounds=args.training_set_bounds)}))
         return
-    if args.slq_only:
-        D32 = D if args.precision == "f32" else kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx,
-                                                                         A.val.astype(np.float32), "f32")
-        print(json.dumps({"stochastic_lanczos": slq_leg(kpm, ctx, A, D32, x)}))
+    if args.slq_only or args.legendre_only:
+        A2, D2, w2 = load_workload(kpm, synth, "anderson3d_64^3_periodic_W16")
+        x = np.linspace(-10.0, 22.0, 200)
+        if args.slq_only:
+            print(json.dumps({"stochastic_lanczos": slq_leg(kpm, ctx, A2, D2, x)}))
+        else:
+            print(json.dumps({"legendre_dgl": legendre_leg(kpm, ctx, D2, x, 256, 64, 64, "f32")}))
         return
-    # validate the matrix once, outside the timed region
-    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
-    kpm.kpm_moments(ctx, D, lb, ub, 2, 1, 2002, precision=args.precision, validate=True)
 
-    def step():
-        # bounds -> moments -> Jackson damping -> density, one library call
-        phi, mu, _, _ = kpm.kpm_dos_pipeline(ctx, D, M, nvec, 2002, x, precision=args.precision, block=block,
-                                             damping=kpm.KPM_DAMP_JACKSON, lanczos_steps=20, lanczos_seed=3002,
-                                             margin=0.01, rows_per_block=args.rows_per_block)
-        return mu, phi
-
-    def step_separate():
-        # the same four steps as separate calls (one wait each)
-        lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
-        mu = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision, block=block,
-                             validate=False, rows_per_block=args.rows_per_block)
-        g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
-        phi = kpm.kpm_dos(ctx, mu, g, lb, ub, x)
-        return mu, phi
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kpm.kpm_profile_reset(ctx)
-    kpm.kpm_profile_enable(ctx, True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mu, phi = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kpm.kpm_profile_enable(ctx, False)
-    step_separate()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step_separate()
-    torch.cuda.synchronize()
-    ms_separate = (time.perf_counter() - t2) * 1000.0 / args.steps
-    copy_gbs = kpm.kpm_hbm_copy_probe(ctx, 1 << 30, 10)
-    nl, step_ms_total = kpm.kpm_profile_query(ctx, "cheb_step")
-    nf, first_ms_total = kpm.kpm_profile_query(ctx, "cheb_first")
-    nlz, lz_ms_total = kpm.kpm_profile_query(ctx, "lanczos")
-
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    units = float(A.nnz) * M * nvec
-    value = units / (ms_per_step / 1000.0)
-    s_v = 4 if args.precision == "f32" else 8
-    s_a = s_v
-    b = min(block, nvec)
-    nblocks_vec = (nvec + b - 1) // b
-    bytes_per_launch = (s_a + 4) * A.nnz + 4 * (A.n + 1) + 3 * s_v * A.n * b
-    avg_ms = step_ms_total / max(nl, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (MEASURED_TRAFFIC_BYTES if (args.grid, M, nvec, block, args.precision) == (64, 256, 64, 64, "f32")
-                        else None),
-            "kernel": "cheb_step_kernel", "avg_launch_us": round(avg_ms * 1000, 2),
-            "launches": nl, "algorithmic_bytes_per_launch": int(bytes_per_launch),
-            "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy_probe": round(achieved / copy_gbs, 4)}
-
+    A, D, w = load_workload(kpm, synth, args.workload, args.precision)
+    M = args.M or w["M"]
+    nvec = args.nvec or w["nvec"]
+    block = args.block or w["block"]
+    head = throughput_leg(kpm, ctx, A, D, args.workload, M, nvec, block, w["seed"], w["lz_seed"], args.steps,
+                          args.warmup, args.precision, args.rows_per_block)
     out = {
         "metric": "Chebyshev moment nnz*deg*vec/s",
-        "value": value,
+        "value": head["value"],
         "unit": "nnz*deg*vec/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"anderson3d_{args.grid}^3_periodic_W16", "n": A.n, "nnz": A.nnz, "M": M,
-                   "nvec": nvec, "block": b, "vector_blocks": nblocks_vec, "precision": args.precision,
-                   "dot_accumulation": "f64", "lanczos_steps": 20, "dos_points": 200,
-                   "parallelism": "single-gpu"},
-        "roofline": roof,
-        "breakdown_ms_per_step": {"cheb_step_total": step_ms_total / args.steps,
-                                  "cheb_first": first_ms_total / args.steps,
-                                  "lanczos_enqueue_to_done": lz_ms_total / args.steps},
-        "ms_per_step_separate_calls": round(ms_separate, 4),
-        "hbm_gbs_whole_step": round(bytes_per_launch * (M + 1) // 2 * nblocks_vec / (ms_per_step * 1e-3) / 1e9, 1),
+        "config": head["config"],
+        "roofline": head["roofline"],
     }
+    for k in ("breakdown_ms_per_step", "ms_per_step_separate_calls", "hbm_gbs_whole_step_algorithmic"):
+        out[k] = head[k]
+    out["roofline"]["copy_probe_gbs"] = round(kpm.kpm_hbm_copy_probe(ctx, 1 << 30, 10), 1)
+    out["roofline"]["frac_of_copy_probe"] = round(out["roofline"]["achieved"] / out["roofline"]["copy_probe_gbs"], 4)
+    if A.nnz > 7 * A.n:
+        # the entries beyond the 7-point stencil gather rows of the probe
+        # block at random: each costs a whole probe row that no cache keeps
+        b = out["config"]["block"]
+        s_v = 4 if args.precision == "f32" else 8
+        unc = out["roofline"]["algorithmic_bytes_per_launch"] + (A.nnz - 7 * A.n) * s_v * b
+        out["roofline"]["bytes_with_uncached_long_range_gathers"] = int(unc)
+        out["roofline"]["frac_uncached_gather_model"] = round(
+            unc / (out["roofline"]["avg_launch_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    lb, ub = head["lb_ub"]
 
     if not args.no_extras:
-        out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A, D, x)
+        x = np.linspace(-10.0, 22.0, 200)
+        if args.workload == HEADLINE:
+            out["large_equal_accuracy"] = large_equal_accuracy_leg(kpm, ctx, A, D, synth)
+            del D
+            torch.cuda.empty_cache()
+        A2, D2, w2 = load_workload(kpm, synth, "anderson3d_64^3_periodic_W16")
+        leg = throughput_leg(kpm, ctx, A2, D2, "anderson3d_64^3_periodic_W16", w2["M"], w2["nvec"], w2["block"],
+                             w2["seed"], w2["lz_seed"], 20, 3)
+        out["anderson3d_64"] = {k: leg[k] for k in ("value", "ms_per_step", "config", "roofline",
+                                                     "breakdown_ms_per_step", "ms_per_step_separate_calls")}
+        out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A2, D2, x)
         out["batched_uneven_48"] = batched_leg(kpm, ctx, synth, tune=not args.no_autotune)
-        out["stochastic_lanczos"] = slq_leg(kpm, ctx, A, D, x)
-        out["legendre_dgl"] = legendre_leg(kpm, ctx, D, x, args)
-        out["large"] = large_leg(kpm, ctx, synth)
+        out["stochastic_lanczos"] = slq_leg(kpm, ctx, A2, D2, x)
+        out["legendre_dgl"] = legendre_leg(kpm, ctx, D2, x, w2["M"], w2["nvec"], w2["block"], "f32")
         out["training_set"] = training_set_leg(kpm, ctx, synth)
         if not args.no_autotune:
-            out["autotune"] = autotune_leg(kpm, ctx, D, lb, ub, args, roof)
+            l2, u2 = leg["lb_ub"]
+            out["autotune"] = autotune_leg(kpm, ctx, D2, l2, u2, w2["nvec"], leg["roofline"])
 
     if not args.no_cpu_baseline:
-        import oracle
-        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        cores = max(1, min(cores, 16))
-        nv = args.cpu_sample_vectors or nvec
-        Ao = A.rounded_f32() if args.precision == "f32" else A
-        c, d = oracle.rescale(lb, ub)
-        ts = time.perf_counter()
-        oracle.moments_per_vector(Ao, c, d, M, nv, 2002, nthreads=cores)
-        te = time.perf_counter()
-        cpu_units = float(A.nnz) * M * nv / (te - ts)
-        model = ""
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-        except OSError:
-            pass
-        out["cpu_baseline"] = {"value": cpu_units, "unit": "nnz*deg*vec/s", "cores": cores, "kind": "oracle",
-                               "sample": f"{nv} of {nvec} probes, full matrix, full degree M={M}, "
-                                         f"FP64 plain recurrence (no doubling); {te - ts:.2f} s",
-                               "cpu_model": model, "host_cpus": os.cpu_count()}
+        out["cpu_baseline"] = cpu_baseline_leg(A, lb, ub, M, nvec, w["seed"], args, M)
     print(json.dumps(out))
 
 
@@ -359,30 +461,14 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
             "sparse_products_per_probe": M_SLQ}
 
 
-def large_leg(kpm, ctx, synth, reps=3):
-    """The large workload: 3D Anderson 128^3 + 2 random N(0, 0.1^2)
-    long-range pairs per row (n = 2,097,152, nnz ~ 23.07M), 256 probes as 4
-    blocks of 64.  Throughput at degree 1000 in FP32 (FP64 sums) with the step
-    kernel against the HBM roofline, and the equal-accuracy comparison at the
-    degrees the accuracy study found for this matrix."""
-    A = synth.config_matrix("c5")
-    D32 = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32")
+def large_equal_accuracy_leg(kpm, ctx, A, D32, synth, reps=3):
+    """The equal-accuracy comparison on the large workload: whole-pipeline
+    time of FP64 + Jackson and FP32 + learned damping at the degrees where
+    each reaches L1 <= 1e-2, 256 probes."""
     D64 = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64), "f64")
     lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3005, 0.01)
     x = np.linspace(lb, ub, 200)
-    M, nvec = 1000, 256
-    kpm.kpm_moments(ctx, D32, lb, ub, 16, nvec, 2005, validate=True)  # matrix check outside the timing
-    kpm.kpm_profile_reset(ctx)
-    kpm.kpm_profile_enable(ctx, True)
-    t_mom = _time_ms(lambda: kpm.kpm_moments(ctx, D32, lb, ub, M, nvec, 2005, block=64, validate=False), reps)
-    kpm.kpm_profile_enable(ctx, False)
-    nl, ms = kpm.kpm_profile_query(ctx, "cheb_step")
-    us = ms / max(nl, 1) * 1000.0
-    byts = 8 * A.nnz + 4 * (A.n + 1) + 12 * A.n * 64
-    gbs = byts / (us * 1e-6) / 1e9
-    # the random long-range entries (beyond the 7-point stencil) gather rows
-    # that no cache keeps: each costs a full 256-byte row of the probe block
-    byts_uncached = byts + (A.nnz - 7 * A.n) * 4 * 64
+    nvec = 256
     kpm.kpm_mlp_init(ctx, 1)
 
     def fp64_jackson(block=0):
@@ -397,21 +483,16 @@ def large_leg(kpm, ctx, synth, reps=3):
     t64_by_block = {b: _time_ms(lambda b=b: fp64_jackson(b), reps) for b in (32, 64)}  # the faster is the baseline
     t64 = min(t64_by_block.values())
     t32 = _time_ms(fp32_learned, reps)
-    return {"workload": "anderson3d_128^3_W16_plus_2_longrange_pairs_per_row", "n": A.n, "nnz": A.nnz,
-            "M": M, "nvec": nvec, "block": 64, "ms_moments": round(t_mom, 2),
-            "value": float(A.nnz) * M * nvec / (t_mom * 1e-3), "unit": "nnz*deg*vec/s",
-            "step_us": round(us, 1), "step_algorithmic_bytes": int(byts), "step_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "step_bytes_with_uncached_long_range_gathers": int(byts_uncached),
-            "step_frac_of_hbm_peak_uncached_model": round(byts_uncached / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-            "equal_accuracy": {"criterion": "L1(sigma=0.02) <= 1e-2 against the FP64 oracle's degree-512 series, same probes",
-                               "accuracy_source": "tests/test_gpu_accuracy.py::test_fp32_learned_vs_fp64_jackson_on_large",
-                               "M_fp64_jackson": M_LARGE_FP64_JACKSON, "M_fp32_learned": M_LARGE_FP32_LEARNED,
-                               "ms_fp64_jackson_pipeline": round(t64, 2), "ms_fp32_learned_pipeline": round(t32, 2),
-                               "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 2) for b, t in t64_by_block.items()},
-                               "speedup_pipeline": round(t64 / t32, 2)}}
+    del D64
+    return {"criterion": "L1(sigma=0.02) <= 1e-2 against the FP64 oracle's degree-512 series, same probes",
+            "accuracy_source": "tests/test_gpu_accuracy.py::test_fp32_learned_vs_fp64_jackson_on_large",
+            "M_fp64_jackson": M_LARGE_FP64_JACKSON, "M_fp32_learned": M_LARGE_FP32_LEARNED,
+            "ms_fp64_jackson_pipeline": round(t64, 2), "ms_fp32_learned_pipeline": round(t32, 2),
+            "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 2) for b, t in t64_by_block.items()},
+            "speedup_pipeline": round(t64 / t32, 2)}
 
 
-def legendre_leg(kpm, ctx, D, x, args, reps=5):
+def legendre_leg(kpm, ctx, D, x, M, nvec, block, precision, reps=5):
     """Legendre moments of the workload (degree M, the probes and precision
     of the timed steps) by the two device routes -- Chebyshev moments
     converted with non-negative weights (ceil(M/2) sparse products) and the
@@ -419,11 +500,10 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
     Delta-Gauss-Legendre density at the 200 points (sigma = 0.02 of the
     half-width, stopping tolerance 1e-6)."""
     lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
-    M, nvec = args.M, args.nvec
 
     def run(rec):
-        return kpm.kpm_legendre_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision,
-                                        block=args.block, validate=False, recurrence=rec)
+        return kpm.kpm_legendre_moments(ctx, D, lb, ub, M, nvec, 2002, precision=precision,
+                                        block=block, validate=False, recurrence=rec)
 
     t_conv = _time_ms(lambda: run(False), reps)
     t_rec = _time_ms(lambda: run(True), reps)
@@ -434,8 +514,8 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
     run(True)
     kpm.kpm_profile_enable(ctx, False)
     nl, ms_steps = kpm.kpm_profile_query(ctx, "cheb_step")
-    s_v = 4 if args.precision == "f32" else 8
-    b = min(args.block, nvec)
+    s_v = 4 if precision == "f32" else 8
+    b = min(block, nvec)
     leg_bytes = (s_v + 4) * D.nnz + 4 * (D.n + 1) + 3 * s_v * D.n * b + 4 * D.n * ((b + 31) // 32)
     us_leg = ms_steps / max(nl, 1) * 1000.0
     leg_gbs = leg_bytes / (us_leg * 1e-6) / 1e9
@@ -446,12 +526,12 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
     _, deg = kpm.kpm_dgl_dos(ctx, mu, lb, ub, sigma, x)
     # heat capacity of section 4.3 (eq. (gfunc)) at 50 temperatures from the
     # Chebyshev moments of the same run, Jackson-damped
-    muT = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2002, precision=args.precision, block=args.block,
+    muT = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2002, precision=precision, block=block,
                           validate=False)
     gJ = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
     temps = np.geomspace(0.05, 5.0, 50)
     t_cv = _time_ms(lambda: kpm.kpm_heat_capacity(ctx, muT, lb, ub, temps, g=gJ), reps)
-    return {"M": M, "nvec": nvec, "precision": args.precision,
+    return {"M": M, "nvec": nvec, "precision": precision,
             "ms_moments_converted": round(t_conv, 3), "ms_moments_recurrence": round(t_rec, 3),
             "speedup_converted": round(t_rec / t_conv, 2), "max_abs_diff_routes": diff,
             "legendre_step_us": round(us_leg, 2), "legendre_step_algorithmic_bytes": int(leg_bytes),
@@ -460,10 +540,10 @@ def legendre_leg(kpm, ctx, D, x, args, reps=5):
             "ms_heat_capacity_50_temperatures": round(t_cv, 3)}
 
 
-def autotune_leg(kpm, ctx, D, lb, ub, args, roof):
+def autotune_leg(kpm, ctx, D, lb, ub, nvec, roof):
     """The measured geometry choice for this workload next to the fixed
     default the timed steps use (block 64, library panel height, gather 7)."""
-    t = kpm.kpm_autotune(ctx, D, lb, ub, args.nvec, seed=2002, precision=args.precision)
+    t = kpm.kpm_autotune(ctx, D, lb, ub, nvec, seed=2002, precision="f32")
     return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")},
             "us_per_step_chosen": round(t["us_per_step"], 2),
             "us_per_step_default": roof.get("avg_launch_us")}

@@ -397,6 +397,16 @@ kpm_status kpm_functional(kpm_ctx* ctx, const double* mu, const double* g, int M
                           const double* fvals, int Q, double* out);
 
 /*
+ * kpm_functional_nodes -- the Q points of A's axis at which kpm_functional
+ * takes the caller's samples of f: x[q] = c + d cos((q + 1/2) pi / Q),
+ * c = (lb+ub)/2, d = (ub-lb)/2 (the Gauss-Chebyshev nodes of the theta =
+ * arccos t integral above, mapped back by eq. (cd)).  Host-only, no
+ * context; x: host [Q], caller-owned.  KPM_ERR_ARG for Q < 1, Q > 2^26,
+ * lb >= ub, non-finite bounds or a NULL x.
+ */
+kpm_status kpm_functional_nodes(int Q, double lb, double ub, double* x);
+
+/*
  * kpm_heat_capacity -- section 4.3: C_v(T_j) = <phi~, g_T> for the KPM
  * density as in kpm_functional, with g_T of eq. (gfunc) in units where
  * k_B = 1 and hbar c / k_B = 1, as a function of lambda = omega^2:

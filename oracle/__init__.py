@@ -21,6 +21,8 @@ densities of large matrices" in plain numpy / C, in the paper's order:
   (with the 1/n that keeps unit mass) and the blurred KPM approximation used
   for comparisons in section 4;
 * ``mlp_*``           -- FP64 forward/backward of the damping network;
+* ``adam_step``, ``train_full_batch`` -- the Adam update (Kingma & Ba 2015,
+  Algorithm 1) the network is trained with, and a full-batch trajectory;
 * ``lanczos_*``       -- the stochastic Lanczos method of section 3.2.1
   (``slq.py``);
 * ``haydock_dos``     -- Haydock's method of section 3.2.2 from the same
@@ -341,7 +343,7 @@ def scaled_eigenvalues(A, lb: float, ub: float) -> np.ndarray:
 
 
 from .mlp import (mlp_init, mlp_forward, mlp_backward, mlp_loss_and_grads,  # noqa: E402
-                  blur_operator, gelu)
+                  blur_operator, gelu, adam_step, train_full_batch)
 from .slq import (lanczos_tridiag, lanczos_nodes, lanczos_dos, quadrature_moments,  # noqa: E402
                   steps_used as lanczos_steps_used, haydock_dos, lorentz)
 from .dgl import (legendre_moments, legendre_moments_per_vector, dgl_gamma, dgl_dos,  # noqa: E402

@@ -99,3 +99,47 @@ def mlp_loss_and_grads(p: dict, X: np.ndarray, target: np.ndarray, K: np.ndarray
     dphi = np.sign(e) * dt / N
     dg = (dphi @ K) * X
     return loss, mlp_backward(p, cache, dg), g
+
+
+# ---------------------------------------------------------------- Adam
+# The network is trained with Adam (Kingma & Ba, "Adam: a method for
+# stochastic optimization", ICLR 2015, Algorithm 1): exponential moving
+# averages of the gradient and of its square, each divided by one minus its
+# decay rate raised to the step count (the bias correction of their
+# section 3), and a step of lr * m_hat / (sqrt(v_hat) + eps).
+ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8
+
+
+def adam_step(p: dict, grads: dict, m: dict, v: dict, t: int, lr: float,
+              beta1: float = ADAM_BETA1, beta2: float = ADAM_BETA2, eps: float = ADAM_EPS):
+    """One Adam update at step t >= 1 (FP64).  Returns new (p, m, v) dicts;
+    the inputs are not modified."""
+    if t < 1:
+        raise ValueError("Adam's step count starts at 1")
+    p_new, m_new, v_new = {}, {}, {}
+    for name, g in grads.items():
+        m_t = beta1 * m[name] + (1.0 - beta1) * g
+        v_t = beta2 * v[name] + (1.0 - beta2) * g * g
+        m_hat = m_t / (1.0 - beta1 ** t)
+        v_hat = v_t / (1.0 - beta2 ** t)
+        p_new[name] = p[name] - lr * m_hat / (np.sqrt(v_hat) + eps)
+        m_new[name] = m_t
+        v_new[name] = v_t
+    return p_new, m_new, v_new
+
+
+def train_full_batch(p: dict, X: np.ndarray, target: np.ndarray, K: np.ndarray, steps: int, lr: float):
+    """Adam on the whole batch for `steps` updates from p (moments start at
+    zero).  Returns the parameters after each update, the loss before each
+    update, and the smallest |residual| of the blurred density met on the
+    way (the L1 loss's gradient changes sign where a residual does)."""
+    m = {k: np.zeros_like(a) for k, a in p.items()}
+    v = {k: np.zeros_like(a) for k, a in p.items()}
+    traj, losses, min_resid = [], [], np.inf
+    for t in range(1, steps + 1):
+        loss, grads, g = mlp_loss_and_grads(p, X, target, K)
+        min_resid = min(min_resid, float(np.min(np.abs((g * X) @ K.T - target))))
+        p, m, v = adam_step(p, grads, m, v, t, lr)
+        traj.append(p)
+        losses.append(loss)
+    return traj, losses, min_resid

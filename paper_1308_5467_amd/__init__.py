@@ -30,7 +30,7 @@ EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
-    "kpm_legendre_dos", "kpm_functional", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_dos_pipeline", "kpm_autotune", "kpm_autotune_batched",
+    "kpm_legendre_dos", "kpm_functional", "kpm_functional_nodes", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_dos_pipeline", "kpm_autotune", "kpm_autotune_batched",
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_dgl_dos": ([P, P, I32, D, D, D, D, P, I32, P, P], I32),
         "kpm_legendre_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_functional": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_functional_nodes": ([I32, D, D, P], I32),
         "kpm_dos_pipeline": ([P, P, I32, U64, D, P, I32, P, I32, P, P, P, P], I32),
         "kpm_heat_capacity": ([P, P, P, I32, D, D, P, I32, I32, P], I32),
         "kpm_slq_heat_capacity": ([P, P, P, I32, I32, P, I32, P], I32),
@@ -322,17 +323,21 @@ def kpm_dos_pipeline(ctx: Context, A, M: int, nvec: int, seed: int, x, precision
     return phi, mu, lb.value, ub.value
 
 
-def chebyshev_nodes(Q: int, lb: float, ub: float) -> np.ndarray:
-    """The Q quadrature nodes of kpm_functional on A's axis: c + d cos((q + 1/2) pi / Q)."""
-    c, d = 0.5 * (lb + ub), 0.5 * (ub - lb)
-    return c + d * np.cos((np.arange(Q) + 0.5) * np.pi / Q)
+def kpm_functional_nodes(Q: int, lb: float, ub: float) -> np.ndarray:
+    """The Q points of A's axis at which kpm_functional samples f (computed
+    by the library)."""
+    x = np.zeros(int(Q))
+    st = load_library().kpm_functional_nodes(int(Q), float(lb), float(ub), _p(x))
+    if st != 0:
+        raise KpmError(st, "kpm_functional_nodes: bad argument")
+    return x
 
 
 def kpm_functional(ctx: Context, mu, lb: float, ub: float, f, Q: int = 1024, g=None) -> float:
     """<phi~, f> of the KPM density; f is a callable evaluated (on the host)
     at the Q quadrature nodes, or an array of its values there."""
     m = _f64(mu)
-    fv = _f64(f(chebyshev_nodes(Q, lb, ub)) if callable(f) else f)
+    fv = _f64(f(kpm_functional_nodes(Q, lb, ub)) if callable(f) else f)
     if fv.size != Q:
         raise ValueError("need one value of f per node")
     gg = None if g is None else _f64(g)

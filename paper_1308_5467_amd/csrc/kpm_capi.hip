@@ -469,7 +469,19 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
     const size_t vbytes = (size_t)A.n * g.ld * esz;
     if ((st = kpm_ws(ctx, "X0", vbytes, &X0)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "X1", vbytes, &X1)) != KPM_OK) return st;
-    if ((st = kpm_ws(ctx, "partial", (size_t)std::max(K, 1) * grid * 2 * g.ld * 8, &part)) != KPM_OK) return st;
+    // Per-workgroup dot partials are kept for a ring of R steps and reduced
+    // every R steps (and after the last), so this buffer is bounded (about
+    // 64 MiB) whatever the degree; storing all K steps grew with the degree
+    // (K x grid x 2 x ld x 8 bytes: 0.5 GB at degree 1000 and 64 FP32 probes).
+    // The reduction of each step is the same fixed-order sum either way.
+    size_t step_part = (size_t)grid * 2 * g.ld * 8;
+    if (nvec % b != 0) {
+        BlockGeom gr = make_geom(A.n, nvec % b, o->precision, o->rows_per_block);
+        gr.gather = g.gather;
+        step_part = std::max(step_part, (size_t)cheb_step_grid(A, o->precision, gr) * 2 * gr.ld * 8);
+    }
+    const int R = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(K, 1), ((size_t)64 << 20) / step_part));
+    if ((st = kpm_ws(ctx, "partial", (size_t)R * step_part, &part)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "dots", (size_t)std::max(K, 1) * 2 * g.ld * 8, &dots)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "zeta", (size_t)nvec * (M + 1) * 8, &zeta)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "mu", (size_t)(M + 1) * 8, &mud)) != KPM_OK) return st;
@@ -494,7 +506,7 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
             KPM_HIP(ctx, launch_sign_bits(ctx->stream, o->seed, vec0, ncols, A.n, swb, (uint32_t*)sgn));
         void* X[2] = {X0, X1};
         for (int s = 0; s < K; ++s) {
-            double* ps = (double*)part + (size_t)s * gridb * 2 * gb.ld;
+            double* ps = (double*)part + (size_t)(s % R) * gridb * 2 * gb.ld;
             // One event pair brackets the first step and one the run of the
             // remaining steps (events between launches would add gaps).
             if (s == 0) kpm_prof_begin(ctx, "cheb_first");
@@ -513,8 +525,12 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
             }
             if (s == 0) kpm_prof_end(ctx, "cheb_first", 1);
             if (s == K - 1 && K > 1) kpm_prof_end(ctx, "cheb_step", K - 1);
+            if ((s + 1) % R == 0 || s == K - 1) {
+                const int s0 = s - s % R;
+                KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gridb, 2 * gb.ld, s - s0 + 1,
+                                                    (double*)dots + (size_t)s0 * 2 * gb.ld));
+            }
         }
-        KPM_HIP(ctx, launch_reduce_partials(ctx->stream, (double*)part, gridb, 2 * gb.ld, K, (double*)dots));
         if (leg_rec)
             KPM_HIP(ctx, launch_legendre_assemble(ctx->stream, (double*)dots, gb.ld, ncols, M, (double)A.n, vec0,
                                                   (double*)zeta));

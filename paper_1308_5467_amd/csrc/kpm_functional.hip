@@ -132,6 +132,13 @@ static kpm_status series_nodes(kpm_ctx* ctx, const double* mu, const double* g, 
 
 static bool check_range(double lb, double ub) { return std::isfinite(lb) && std::isfinite(ub) && ub > lb; }
 
+extern "C" kpm_status kpm_functional_nodes(int Q, double lb, double ub, double* x) {
+    if (!x || Q < 1 || Q > (1 << 26) || !check_range(lb, ub)) return KPM_ERR_ARG;
+    const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
+    for (int q = 0; q < Q; ++q) x[q] = c + d * cos((q + 0.5) * M_PI / Q);
+    return KPM_OK;
+}
+
 extern "C" kpm_status kpm_functional(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb, double ub,
                                      const double* fvals, int Q, double* out) {
     if (!ctx) return KPM_ERR_ARG;

@@ -98,19 +98,6 @@ hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, d
 hipError_t launch_dos_bins(hipStream_t s, const double* mu, const double* g, int M, double c,
                            double d, const double* edges, int nbins, double* mass);
 
-// ---------------------------------------------------------------- MLP
-hipError_t mlp_forward_dev(hipStream_t s, int N, const float* x, const float* params,
-                           float* z1, float* h1, float* z2, float* h2, float* g);
-hipError_t mlp_loss_grad_dev(hipStream_t s, int N, const float* x, const float* target,
-                             const float* K, const float* params, float* act, float* grads,
-                             float* loss_parts, float* dwork);
-hipError_t mlp_blur_operator_dev(hipStream_t s, int nmom, int npts, float sigma, float* K);
-hipError_t mlp_adam_dev(hipStream_t s, int64_t P, float* params, const float* grads, float* m,
-                        float* v, float lr, float b1, float b2, float eps, int t);
-hipError_t mlp_init_dev(hipStream_t s, uint64_t seed, float* params);
-hipError_t mlp_gather_rows_dev(hipStream_t s, const float* src, int cols, const int32_t* idx,
-                               int nrows, float* dst);
-
 }  // namespace kpm
 
 // ---------------------------------------------------------------- context
@@ -141,6 +128,10 @@ struct kpm_ctx {
     // damping network
     bool mlp_ready = false;
     kpm_dev_buf mlp_params;
+    // the blur operator held in this context's "mlp_blur" workspace: the
+    // sigma it was built for (< 0: not built) and the buffer it was built in
+    float mlp_blur_sigma = -1.0f;
+    const void* mlp_blur_buf = nullptr;
     kpm_batch_state* batch = nullptr;
     // profiling
     bool prof = false;

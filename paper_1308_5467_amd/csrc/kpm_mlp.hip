@@ -419,14 +419,15 @@ kpm_status blur_op(kpm_ctx* ctx, float sigma, float** K) {
     void* k;
     kpm_status st = kpm_ws(ctx, "mlp_blur", (size_t)NPTS * NOUT * sizeof(float), &k);
     if (st != KPM_OK) return st;
-    static thread_local float cached_sigma = -1.0f;
-    static thread_local void* cached_ptr = nullptr;
-    if (cached_sigma != sigma || cached_ptr != k) {
+    // The operator is rebuilt whenever this context has not built it for
+    // this sigma in this buffer (the cache lives in the context, so a new
+    // context never trusts memory it has not written).
+    if (ctx->mlp_blur_sigma != sigma || ctx->mlp_blur_buf != k) {
         blur_operator_kernel<<<(NPTS * NOUT + 127) / 128, 128, 0, ctx->stream>>>(NOUT, NPTS, (double)sigma, 8192,
                                                                                (float*)k);
         KPM_HIP(ctx, hipGetLastError());
-        cached_sigma = sigma;
-        cached_ptr = k;
+        ctx->mlp_blur_sigma = sigma;
+        ctx->mlp_blur_buf = k;
     }
     *K = (float*)k;
     return KPM_OK;

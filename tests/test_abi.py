@@ -45,3 +45,24 @@ def test_null_context_is_rejected_without_gpu():
     assert lib.kpm_destroy(None) == -1
     assert lib.kpm_last_error(None) == b"context is NULL"
     assert lib.kpm_profile_enable(None, 1) == -1
+
+
+def test_functional_nodes_are_gauss_chebyshev():
+    """kpm_functional_nodes is host-only.  Mapped back to t = (x - c)/d, its
+    Q nodes integrate T_k exactly against the Chebyshev weight: the mean of
+    T_k(t_q) is 1 for k = 0 and 0 for 0 < k < 2Q (Gauss-Chebyshev rule), and
+    the nodes are distinct, decreasing and inside (lb, ub)."""
+    import numpy as np
+    lb, ub, Q = -3.5, 9.25, 37
+    x = kpm.kpm_functional_nodes(Q, lb, ub)
+    c, d = 0.5 * (lb + ub), 0.5 * (ub - lb)
+    t = (x - c) / d
+    assert np.all(np.diff(x) < 0) and lb < x.min() and x.max() < ub
+    for k in range(0, 2 * Q):
+        mean = np.mean(np.polynomial.chebyshev.chebval(t, [0] * k + [1]))
+        assert abs(mean - (1.0 if k == 0 else 0.0)) < 1e-12, k
+    assert abs(np.mean(np.polynomial.chebyshev.chebval(t, [0] * (2 * Q) + [1])) + 1.0) < 1e-12
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_functional_nodes(0, lb, ub)
+    with pytest.raises(kpm.KpmError):
+        kpm.kpm_functional_nodes(4, 1.0, 1.0)

@@ -89,6 +89,33 @@ def test_loss_and_gradient_parity(ctx):
         assert np.max(np.abs(got[name] - rg[name])) <= 2e-4 * scale, name
 
 
+def test_blur_operator_rebuilt_per_context_and_sigma():
+    """The loss's blur operator is cached in the context that built it:
+    a context created after another was destroyed (its workspace may land
+    at the same address, holding other data by then) and a change of sigma
+    both rebuild it.  Loss and gradients against the oracle each time."""
+    import torch
+    p = _params(31)
+    X, T = _batch(40, 32)
+    for sigma in (0.05, 0.05, 0.03):
+        c = kpm.Context(0)
+        kpm.kpm_mlp_set_params(c, kpm.mlp_pack(p))
+        loss, _ = kpm.kpm_mlp_loss_grad(c, X, T, sigma)
+        rl, _, _ = oracle.mlp_loss_and_grads(p, X, T, oracle.blur_operator(128, 200, sigma, 8192))
+        assert abs(loss - rl) <= 1e-5 * rl, (sigma, loss, rl)
+        c.close()
+        # reuse the freed device memory for something else before the next context
+        junk = torch.full((1 << 22,), 7.0, device="cuda")
+        del junk
+    c = kpm.Context(0)
+    kpm.kpm_mlp_set_params(c, kpm.mlp_pack(p))
+    for sigma in (0.05, 0.02, 0.05):
+        loss, _ = kpm.kpm_mlp_loss_grad(c, X, T, sigma)
+        rl, _, _ = oracle.mlp_loss_and_grads(p, X, T, oracle.blur_operator(128, 200, sigma, 8192))
+        assert abs(loss - rl) <= 1e-5 * rl, (sigma, loss, rl)
+    c.close()
+
+
 def test_init_starts_near_jackson_and_is_deterministic(ctx):
     kpm.kpm_mlp_init(ctx, 11)
     p1 = kpm.kpm_mlp_get_params(ctx)
@@ -123,6 +150,55 @@ def test_save_load_and_learned_damping_entry(ctx, tmp_path):
         f.write(b"XXXX")
     with pytest.raises(kpm.KpmError):
         kpm.kpm_mlp_load(ctx, path)
+
+
+def _adam_case(N=64, steps=4, lr=1e-3):
+    """Fixed parameters, moments and targets for the training-update parity
+    test, and the oracle's FP64 full-batch Adam trajectory from them.  The
+    targets sit 0.1 to ~2 away from the initial blurred density on either
+    side, so that no residual of the L1 loss changes sign over a few small
+    steps (where one does, the loss's gradient jumps)."""
+    p0 = _params(21)
+    X, _ = _batch(N, 22)
+    K = oracle.blur_operator(128, 200, 0.05, 8192)
+    g0, _ = oracle.mlp_forward(p0, X)
+    phi0 = (g0 * X) @ K.T
+    rng = np.random.default_rng(23)
+    T = phi0 + rng.choice([-1.0, 1.0], size=phi0.shape) * (0.1 + 0.5 * np.abs(rng.normal(0, 1, phi0.shape)))
+    T = T.astype(np.float32).astype(np.float64)
+    traj, losses, min_resid = oracle.train_full_batch(p0, X, T, K, steps, lr)
+    return p0, X, T, traj, losses, min_resid
+
+
+def test_adam_trajectory_parity(ctx):
+    """kpm_mlp_train on the whole batch (batch = N, so the per-epoch shuffle
+    only reorders rows inside the one batch) for 1..4 updates from the same
+    parameters, against the oracle's FP64 Adam (Kingma & Ba 2015,
+    Algorithm 1) trajectory.  Each update moves a parameter by about lr;
+    tolerance: every parameter within 2e-2 lr, and 99.9 % of each tensor
+    within 2e-3 lr (FP32 forward/backward; the few looser entries have
+    gradients that nearly cancel over the batch).  A wrong decay rate or
+    bias correction moves most parameters by 0.05 to 2 lr."""
+    N, S, lr = 64, 4, 1e-3
+    p0, X, T, traj, losses, min_resid = _adam_case(N, S, lr)
+    assert min_resid > 1e-3, min_resid  # no residual near a sign change
+    for s in range(1, S + 1):
+        kpm.kpm_mlp_set_params(ctx, kpm.mlp_pack(p0))
+        lg = kpm.kpm_mlp_train(ctx, X, T, 0.05, s, N, lr, 1 + s)
+        got = kpm.mlp_unpack(kpm.kpm_mlp_get_params(ctx))
+        for e in range(s):
+            assert abs(lg[e] - losses[e]) <= 1e-5 * losses[e], (s, e, lg[e], losses[e])
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            ref = traj[s - 1][name]
+            d = np.abs(got[name].astype(np.float64) - ref)
+            moved = np.abs(ref - p0[name])
+            _say(f"step {s} {name}: max |d|/lr {d.max() / lr:.2e}, p99.9 {np.quantile(d, 0.999) / lr:.2e}")
+            assert d.max() <= 2e-2 * lr + 2e-7 * np.max(np.abs(ref)), (s, name)
+            assert np.mean(d <= 2e-3 * lr + 2e-7 * np.abs(ref)) >= 0.999, (s, name)
+            if name != "W3" and name != "b3":
+                assert np.median(moved) > 0.5 * s * lr  # the update did move them
+    # the first output's factor is pinned to 1: its weights get no gradient
+    assert np.array_equal(got["W3"][:, 0], p0["W3"][:, 0].astype(np.float32))
 
 
 # ---------------------------------------------------------------- training gain

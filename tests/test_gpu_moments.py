@@ -318,30 +318,64 @@ def test_c2_full_size_sampled(ctx):
     assert mu[0] == 1.0 and np.all(np.abs(pv) <= 1 + 1e-5)
 
 
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _c5_golden():
+    """Bounds and the oracle's moments of probes 254, 255 at degree 1000,
+    written by tests/golden/make_c5_probe_moments.py (oracle only)."""
+    rows = [ln.split() for ln in open(f"{GOLDEN}/c5_probe_moments.txt") if ln.strip() and not ln.startswith("#")]
+    assert rows[0][0] == "lb" and rows[1][0] == "ub"
+    z = np.array([[float(r[1]), float(r[2])] for r in rows[2:]]).T
+    assert z.shape == (2, 1001)
+    return float(rows[0][1]), float(rows[1][1]), z
+
+
 def test_c5_full_size_sampled(ctx):
     """c5 at full size: 3D Anderson 128^3 plus random long-range hoppings
-    (n = 2,097,152, nnz ~ 23M), 256 probes in blocks of 64, FP32.
-
-    The degree-1000 run is checked by invariants, and its first 201 moments
-    must equal those of a degree-200 run bitwise (the first 100 steps are
-    the same deterministic launches).  The degree-200 run is checked against
-    the oracle on probes 254 and 255 (the last block)."""
+    (n = 2,097,152, nnz ~ 23M), degree 1000, 256 probes in blocks of 64,
+    FP32 -- the configuration the benchmark times.  Probes 254 and 255 (the
+    last block) against the oracle at every degree up to 1000, 1e-5; the
+    oracle's bounds are used on both sides and the library's own bounds must
+    agree with them (1e-9 relative); invariants on every probe; the first
+    201 moments equal a degree-200 run bitwise (the same launches)."""
+    lb, ub, z = _c5_golden()
     _say("c5 full size: generating matrix")
     A = synth.config_matrix("c5")
     assert A.n == 128**3 and 20_000_000 < A.nnz < 26_000_000
     D = dev(A, "f32")
     _say("c5 bounds")
-    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3005, 0.01)
+    glb, gub = kpm.kpm_bounds(ctx, D, 20, 3005, 0.01)
+    assert abs(glb - lb) <= 1e-9 * (ub - lb) and abs(gub - ub) <= 1e-9 * (ub - lb), (glb, gub, lb, ub)
     _say("c5 moments M=1000")
     mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 1000, 256, 2005, precision="f32", block=64,
                              validate=True, per_vector=True)
     assert mu[0] == 1.0 and np.all(np.abs(pv) <= 1 + 1e-5)
+    err = np.abs(pv[254:256] - z)
+    _say(f"c5 probes 254, 255: max |dmu| {err.max():.2e} (degrees 0-200 {err[:, :201].max():.2e}, "
+         f"201-1000 {err[:, 201:].max():.2e})")
+    assert err.max() < TOL32
     _say("c5 moments M=200")
     mu2, pv2 = kpm.kpm_moments(ctx, D, lb, ub, 200, 256, 2005, precision="f32", block=64,
                                validate=False, per_vector=True)
     assert np.array_equal(pv[:, :201], pv2)
+
+
+def test_anderson32_longrange_fp32_degree1000_all_probes(ctx):
+    """The large workload's family at 32^3 (3D Anderson + 2 long-range pairs
+    per row, n = 32,768), degree 1000, 70 probes (one block of 64 and a
+    ragged block of 6), FP32: every probe, every degree against the oracle
+    at 1e-5."""
+    A = synth.config_matrix("c5", scale=32)
+    D = dev(A, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3105, 0.01)
+    _say("32^3 + long range, degree 1000, 70 probes")
+    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 1000, 70, 2105, precision="f32", block=64,
+                             validate=True, per_vector=True)
     Ao = A.rounded_f32()
     c, d = oracle.rescale(lb, ub)
-    _say("c5 oracle probes 254, 255 at M=200")
-    z = oracle.moments_per_vector(Ao, c, d, 200, 2, 2005, vec0=254, nthreads=2) / A.n
-    assert np.max(np.abs(pv2[254:256] - z)) < TOL32
+    z = oracle.moments_per_vector(Ao, c, d, 1000, 70, 2105, nthreads=16) / A.n
+    err = np.abs(pv - z)
+    _say(f"max |dmu| {err.max():.2e}; mean moments {np.abs(mu - z.mean(axis=0)).max():.2e}")
+    assert err.max() < TOL32
+    assert np.abs(mu - z.mean(axis=0)).max() < TOL32

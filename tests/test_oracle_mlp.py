@@ -75,3 +75,97 @@ def test_output_zero_is_pinned_to_one():
     X, _ = _batch()
     g, _ = oracle.mlp_forward(p, X)
     assert np.all(g[:, 0] == 1.0) and np.all((g > 0) & (g <= 1))
+
+
+# ---------------------------------------------------------------- Adam
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _scalar(v):
+    return {"w": np.array([float(v)])}
+
+
+def test_adam_two_steps_hand_worked():
+    """Two updates of one scalar against values worked by hand in exact
+    rational arithmetic (tests/golden/adam_two_steps.txt)."""
+    rows = [ln.split() for ln in open(f"{GOLDEN}/adam_two_steps.txt") if ln.strip() and not ln.startswith("#")]
+    p, m, v = _scalar(1.0), _scalar(0.0), _scalar(0.0)
+    for (step, m_ref, v_ref, th_ref), g in zip(rows, (0.5, -0.25)):
+        p, m, v = oracle.adam_step(p, _scalar(g), m, v, int(step), 0.1)
+        assert abs(m["w"][0] - float(m_ref)) < 4e-17
+        assert abs(v["w"][0] - float(v_ref)) < 1e-18
+        assert abs(p["w"][0] - float(th_ref)) < 1e-15
+
+
+def test_adam_matches_torch_optimizer():
+    """torch.optim.Adam implements the same published algorithm: same
+    gradient sequence, same FP64 trajectory."""
+    rng = np.random.default_rng(4)
+    shapes = {"a": (5, 3), "b": (7,)}
+    p = {k: rng.normal(0, 1, s) for k, s in shapes.items()}
+    m = {k: np.zeros(s) for k, s in shapes.items()}
+    v = {k: np.zeros(s) for k, s in shapes.items()}
+    tp = {k: torch.tensor(a.copy(), requires_grad=True) for k, a in p.items()}
+    opt = torch.optim.Adam(list(tp.values()), lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for t in range(1, 30):
+        g = {k: rng.normal(0, 10.0 ** rng.uniform(-4, 1), s) for k, s in shapes.items()}
+        p, m, v = oracle.adam_step(p, g, m, v, t, 3e-3)
+        for k in shapes:
+            tp[k].grad = torch.tensor(g[k])
+        opt.step()
+        for k in shapes:
+            assert np.max(np.abs(tp[k].detach().numpy() - p[k])) < 1e-14
+
+
+def test_adam_bias_correction_constant_gradient():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step, so each update is exactly lr * g / (|g| + eps); a missing or
+    mis-powered correction changes the early steps."""
+    g = np.array([2.0, -3e-3, 7e-6])
+    p, m, v = _scalar(0.0), _scalar(0.0), _scalar(0.0)
+    p, m, v = {"w": np.zeros(3)}, {"w": np.zeros(3)}, {"w": np.zeros(3)}
+    for t in range(1, 41):
+        p, m, v = oracle.adam_step(p, {"w": g}, m, v, t, 1e-2)
+        assert np.allclose(p["w"], -t * 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_step_bound():
+    """Kingma & Ba, section 2.1: with (1 - beta1) > sqrt(1 - beta2) the
+    effective step never exceeds lr (1 - beta1) / sqrt(1 - beta2), and it
+    approaches that bound for a gradient spike after a long run of zero
+    gradients (the sparse case the paper describes)."""
+    lr = 1e-3
+    bound = lr * 0.1 / np.sqrt(0.001)
+    rng = np.random.default_rng(5)
+    spike_at = np.array([1, 2, 10, 100, 1000, 6000])
+    p, m, v = {"w": np.zeros(6)}, {"w": np.zeros(6)}, {"w": np.zeros(6)}
+    spike_step = np.zeros(6)
+    for t in range(1, 6001):
+        g = np.where(spike_at == t, rng.normal(0, 1, 6), 0.0)
+        if t > 6000 - 50:
+            g = g + np.where(spike_at < 6000, rng.normal(0, 1e-3, 6), 0.0)
+        p_new, m, v = oracle.adam_step(p, {"w": g}, m, v, t, lr)
+        step = np.abs(p_new["w"] - p["w"])
+        assert np.all(step <= bound * (1 + 1e-9))
+        spike_step = np.where(spike_at == t, step, spike_step)
+        p = p_new
+    assert abs(spike_step[0] - lr) < 1e-6 * lr      # first step: lr * sign(g), up to eps / |g|
+    assert spike_step[-1] > 0.95 * bound            # after 5,999 zero gradients
+
+
+def test_full_batch_trajectory_descends_and_matches_steps():
+    """train_full_batch is adam_step applied to mlp_loss_and_grads in turn."""
+    p = oracle.mlp_init(8)
+    X, T = _batch(5, 9)
+    K = oracle.blur_operator(128, 200, 0.05, 1024)
+    traj, losses, min_resid = oracle.train_full_batch(p, X, T, K, 3, 1e-3)
+    m = {k: np.zeros_like(a) for k, a in p.items()}
+    v = {k: np.zeros_like(a) for k, a in p.items()}
+    q = p
+    for t in range(1, 4):
+        loss, grads, _ = oracle.mlp_loss_and_grads(q, X, T, K)
+        assert loss == losses[t - 1]
+        q, m, v = oracle.adam_step(q, grads, m, v, t, 1e-3)
+        for k in q:
+            assert np.array_equal(q[k], traj[t - 1][k])
+    assert losses[-1] < losses[0] and min_resid > 0
