@@ -39,7 +39,7 @@ def main():
         f.write(f"# n {A.n} nnz {A.nnz} M {M} seed {SEED} probes {PROBES[0]} {PROBES[1]}\n")
         f.write(f"lb {lb!r}\nub {ub!r}\n")
         for k in range(M + 1):
-            f.write(f"{k} {z[0, k]!r} {z[1, k]!r}\n")
+            f.write(f"{k} {float(z[0, k])!r} {float(z[1, k])!r}\n")
     print(f"wrote {OUT}: lb {lb} ub {ub}")
 
 
