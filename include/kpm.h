@@ -35,6 +35,7 @@
 #ifndef KPM_H
 #define KPM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -169,6 +170,37 @@ kpm_status kpm_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
  */
 kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
                                 const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
+
+/*
+ * kpm_moments_noalloc -- kpm_moments for callers that cannot allocate
+ * device memory: code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc.  It calls no allocating routine (device
+ * or page-locked host) and does not wait: the launches are enqueued on the
+ * context's stream and the outputs are complete when the stream reaches
+ * the end of them.  Same moments as kpm_moments for the same opts (the same
+ * launches and geometry, bitwise), with these differences:
+ *  - A must be in device memory (on_device = 1); the FP32 path needs FP32
+ *    values; opts->validate must be 0 (KPM_ERR_UNSUPPORTED otherwise).
+ *  - mu: DEVICE [M+1] doubles; mu_per_vec: DEVICE [nvec * (M+1)] or NULL.
+ *  - No escape check: the caller checks |mu_per_vec| <= 1 if it needs to.
+ *  - Its work memory is one device array of KPM_NOALLOC_SCRATCH_BYTES per
+ *    device, reserved when the library's code is loaded on that device and
+ *    held until the process ends: two probe blocks of n x ld values (ld =
+ *    the block width rounded up to 4 FP32 or 2 FP64 values), the reduced
+ *    dots (ceil(M/2) x 2 x ld doubles), the per-probe moments when
+ *    mu_per_vec is NULL (nvec x (M+1) doubles) and at least one step of
+ *    per-workgroup dot partials (at most a few MiB).  A problem that does
+ *    not fit returns KPM_ERR_ARG before anything is enqueued (the 64^3
+ *    workload's 64 FP32 probes, 134 MB of probe blocks, fits).
+ *  - Every call on a device shares that array and leaves its contents
+ *    behind; calls that overlap on one device (two streams, two threads)
+ *    race and must be serialised by the caller.
+ * The context must come from kpm_create, which resolves the array's
+ * address on its device.
+ */
+#define KPM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+kpm_status kpm_moments_noalloc(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
+                               const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
 
 /*
  * kpm_autotune -- choose the device geometry of kpm_moments for A by

@@ -28,6 +28,7 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 # Every symbol include/kpm.h declares.
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
+    "kpm_moments_noalloc",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
     "kpm_legendre_dos", "kpm_functional", "kpm_functional_nodes", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_dos_pipeline", "kpm_autotune", "kpm_autotune_batched",
@@ -76,6 +77,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_last_error": ([P], ctypes.c_char_p),
         "kpm_bounds": ([P, P, I32, U64, D, P, P], I32),
         "kpm_moments": ([P, P, D, D, P, P, P], I32),
+        "kpm_moments_noalloc": ([P, P, D, D, P, P, P], I32),
         "kpm_moments_batched": ([P, I32, P, P, P, P, P, P], I32),
         "kpm_gershgorin": ([P, P, P, P], I32),
         "kpm_moments_robust": ([P, P, I32, U64, D, P, P, P, P, P, P], I32),
@@ -264,6 +266,27 @@ def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: 
                              _p(pv) if pv is not None else None)
     ctx.check(st)
     return (mu, pv) if per_vector else mu
+
+
+def kpm_moments_noalloc(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int, mu_out,
+                        per_vector_out=None, precision="f32", block: int = 0, rows_per_block: int = 0,
+                        gather: int = 0) -> None:
+    """kpm_moments into caller-owned device tensors (float64 CUDA tensors of
+    M+1 and nvec*(M+1) elements), enqueued on the context's stream without a
+    wait and without device allocation; A must be a DeviceCSR."""
+    import torch
+    if mu_out is None:
+        raise ValueError("mu_out is required")
+    for t, size in ((mu_out, M + 1), (per_vector_out, nvec * (M + 1))):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                                  and t.numel() >= size):
+            raise ValueError(f"outputs must be contiguous float64 CUDA tensors of at least {size} elements")
+    o = _opts(M, nvec, seed, precision, block, False, rows_per_block, _gather_flags(gather))
+    c = A.as_c()
+    ctx.check(ctx.lib.kpm_moments_noalloc(ctx.handle, ctypes.byref(c), lb, ub, ctypes.byref(o),
+                                          ctypes.c_void_p(mu_out.data_ptr()),
+                                          ctypes.c_void_p(per_vector_out.data_ptr())
+                                          if per_vector_out is not None else None))
 
 
 def kpm_legendre_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,

@@ -198,6 +198,7 @@ extern "C" kpm_status kpm_create(int device, void* hip_stream, kpm_ctx** out) {
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return KPM_ERR_HIP;
     if (device < 0 || device >= count) return KPM_ERR_ARG;
     if (hipSetDevice(device) != hipSuccess) return KPM_ERR_HIP;
+    kpm_noalloc_attach(device);
     kpm_ctx* ctx = new kpm_ctx();
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;

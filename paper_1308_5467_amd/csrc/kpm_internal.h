@@ -149,6 +149,10 @@ kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g)
 // The same from device moments into device factors, enqueued without a wait.
 kpm_status kpm_learned_damping_device(kpm_ctx* ctx, int M, const double* mu_dev, double* g_dev);
 
+// Resolves the no-allocation entry point's scratch array on `device` (which
+// the caller has made current); called once per context creation.
+void kpm_noalloc_attach(int device);
+
 // Grow-only workspace allocation by role name.
 kpm_status kpm_ws(kpm_ctx* ctx, const char* role, size_t bytes, void** out);
 // Grow-only page-locked host buffer of at least `bytes` (waits for the
