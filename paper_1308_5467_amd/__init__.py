@@ -18,6 +18,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkpm.so")
+# Damping-network weights shipped with the library (kpm_mlp_save format):
+# trained on the library's device path against exact blurred densities of
+# the training family (random sparse n = 2,048, 2D Anderson 32 x 64, 3D
+# Anderson 12^3); load with kpm_mlp_load for KPM_DAMP_LEARNED.
+DAMPING_WEIGHTS = os.path.join(_HERE, "damping_net.bin")
 
 KPM_FP32, KPM_FP64 = 0, 1
 KPM_DAMP_NONE, KPM_DAMP_JACKSON, KPM_DAMP_LEARNED = 0, 1, 2
@@ -68,6 +73,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_1308_5467_amd.build`")
+    # torch first: its HIP runtime (soname libamdhip64.so.7, requested by its
+    # own libraries as libamdhip64.so) must be the one libkpm.so binds to.
+    # Loaded the other way round, the process would hold two HIP runtimes
+    # and the library's calls would fail.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     sig = {

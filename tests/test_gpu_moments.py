@@ -379,3 +379,20 @@ def test_anderson32_longrange_fp32_degree1000_all_probes(ctx):
     _say(f"max |dmu| {err.max():.2e}; mean moments {np.abs(mu - z.mean(axis=0)).max():.2e}")
     assert err.max() < TOL32
     assert np.abs(mu - z.mean(axis=0)).max() < TOL32
+
+
+def test_context_created_before_torch_is_imported():
+    """A script that creates a context before importing torch: the binding
+    loads torch's HIP runtime first, so the library binds to the one runtime
+    in the process (two runtimes made kpm_create fail).  Run in a child
+    process, which imports nothing else first."""
+    import subprocess
+    code = ("import numpy as np, paper_1308_5467_amd as kpm, synth\n"
+            "c = kpm.Context(0)\n"
+            "A = synth.diagonal_matrix(np.linspace(-1, 1, 100))\n"
+            "D = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), 'f32')\n"
+            "mu = kpm.kpm_moments(c, D, -1.5, 1.5, 4, 2, 1)\n"
+            "print('ok', mu[0])\n")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and "ok 1.0" in r.stdout, (r.stdout, r.stderr)
