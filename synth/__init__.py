@@ -180,16 +180,40 @@ def batched_uneven_set(count: int = 48, seed_base: int = 3000) -> list[CSR]:
     return mats
 
 
+GOLDEN_RATIO_FRAC = 0.6180339887498949
+DAMPING_N_RANDOM, DAMPING_N_ANDERSON2D = 8192, 1024
+
+
+def damping_training_matrix(i: int, seed_base: int = 4000) -> CSR:
+    """Matrix i of the damping network's training family: i < 8,192 a random
+    sparse symmetric matrix (n = 2,048, 4.5 n mirrored N(0, 1) pairs,
+    uniform [-1, 1] diagonal, about 10 entries per row); 8,192 <= i < 9,216
+    a 2D Anderson matrix (32 x 64 periodic lattice, diagonal disorder of
+    width W = 1 + 15 frac(j * golden ratio), j = i - 8,192).  Seed seed_base + i."""
+    if i < DAMPING_N_RANDOM:
+        return random_sparse_symmetric(2048, 4.5, seed_base + i)
+    j = i - DAMPING_N_RANDOM
+    W = 1.0 + 15.0 * ((j * GOLDEN_RATIO_FRAC) % 1.0)
+    return add_diagonal_disorder(laplacian2d_periodic(32, 64), W, seed_base + i)
+
+
+def anderson3d_family_matrix(j: int, L: int = 12, seed_base: int = 14000) -> CSR:
+    """Member j of a small 3D Anderson family (L^3 periodic 7-point
+    Laplacian, diagonal disorder of width W = 1 + 15 frac(j * golden ratio)),
+    the family of the 3D workloads at a size whose spectrum dense eigh
+    resolves in well under a second.  Seed seed_base + j."""
+    W = 1.0 + 15.0 * ((j * GOLDEN_RATIO_FRAC) % 1.0)
+    return add_diagonal_disorder(laplacian3d_periodic(L), W, seed_base + j)
+
+
 def damping_training_set(n_random: int = 8192, n_anderson: int = 1024, seed_base: int = 4000) -> list[CSR]:
     """The damping network's training family at full size: ``n_random``
-    random sparse symmetric matrices (n = 2,048, 4.5 n mirrored N(0, 1)
-    pairs, uniform [-1, 1] diagonal, about 10 entries per row) followed by
-    ``n_anderson`` 2D Anderson matrices (32 x 64 periodic lattice, diagonal
-    disorder of width W in [1, 16], W = 1 + 15 frac(i * golden ratio)).
-    Matrix i uses seed seed_base + i."""
+    random sparse symmetric matrices followed by ``n_anderson`` 2D Anderson
+    matrices, as damping_training_matrix describes (with the default counts
+    matrix i of the list is damping_training_matrix(i))."""
     mats = [random_sparse_symmetric(2048, 4.5, seed_base + i) for i in range(n_random)]
     for i in range(n_anderson):
-        W = 1.0 + 15.0 * ((i * 0.6180339887498949) % 1.0)
+        W = 1.0 + 15.0 * ((i * GOLDEN_RATIO_FRAC) % 1.0)
         mats.append(add_diagonal_disorder(laplacian2d_periodic(32, 64), W, seed_base + n_random + i))
     return mats
 

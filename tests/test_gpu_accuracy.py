@@ -1,21 +1,23 @@
-"""Equal-accuracy comparison on the 64^3 Anderson workload: FP32 moments +
-learned damping against FP64 moments + Jackson damping (Appendix A), and
-the stochastic Lanczos method (section 3.2.1) on the same probes.
+"""Equal-accuracy comparison on the 64^3 Anderson workload and the large
+workload: FP32 moments with the shipped learned damping, and with no
+damping, against FP64 moments + Jackson damping (Appendix A), and the
+stochastic Lanczos method (section 3.2.1) on the same probes.
 
 Error metric: L1 distance (eq. (err2), p = 1) on 200 midpoints of [-1, 1]
 between Gaussian-blurred densities (sigma = 0.02 in the scaled variable, as
 the paper blurs KPM before comparing in section 4.1).  Reference: the FP64
-oracle's undamped series of degree 512 with the same 64 probes (its blurred
+oracle's undamped series of degree 512 with the same probes (its blurred
 tail beyond degree 512 is below 1e-20), so the metric measures what the
 degree, the damping and the arithmetic precision cost, not the shared
-stochastic-trace noise.
+stochastic-trace noise.  Against that reference no damping is the best
+possible choice at every degree it has reached: whatever the damping
+removes is part of the reference.  The learned network's value is measured
+where trace noise counts, against exact densities (test_gpu_damping.py).
 
-The damping network is trained on device with truncation augmentation:
-every training sample appears with its moments cut at several degrees
-(zeros above), so one network serves any degree up to 127.  Training set:
-random sparse symmetric (n = 512), 2D Anderson 16 x 32 and 3D Anderson 8^3
-matrices with disorder widths in [1, 16]; moments from the library's
-batched path (256 probes), labels = blurred exact DOS from dense eigh.
+The network is the one the library ships (trained by test_gpu_damping.py on
+exact labels of the training family, with truncation augmentation, so it
+serves any degree up to 127).  The degrees at which each form first reaches
+L1 <= 1e-2 are the ones bench.py times; this test asserts they agree.
 """
 import json
 import os
@@ -24,6 +26,7 @@ import sys
 import numpy as np
 import pytest
 
+import bench
 import oracle
 import paper_1308_5467_amd as kpm
 import synth
@@ -31,7 +34,6 @@ import synth
 pytestmark = pytest.mark.gpu
 
 SIGMA = 0.02
-TRUNC = (15, 23, 31, 47, 63, 95, 127)
 DEGREES = (16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 127)
 SLQ_STEPS = (40, 50, 60, 65, 70, 80, 100)
 
@@ -60,33 +62,6 @@ def ctx():
     c.close()
 
 
-def _training_set(ctx, per_family=120, nvec=256):
-    mats = []
-    for i in range(per_family):
-        W = 1.0 + 15.0 * ((i * 0.6180339887) % 1.0)
-        mats.append(synth.random_sparse_symmetric(512, 4.5, 10_000 + i))
-        mats.append(synth.add_diagonal_disorder(synth.laplacian2d_periodic(16, 32), W, 20_000 + i))
-        mats.append(synth.add_diagonal_disorder(synth.laplacian3d_periodic(8), W, 30_000 + i))
-    t = oracle.midpoints(200)
-    lb, ub, targets = [], [], []
-    for A in mats:
-        lam = np.linalg.eigvalsh(A.rounded_f32().dense())
-        c, d = 0.5 * (lam[0] + lam[-1]), 0.5 * (lam[-1] - lam[0]) / 0.98
-        lb.append(c - d)
-        ub.append(c + d)
-        targets.append(oracle.blurred_exact((lam - c) / d, t, SIGMA))
-    D = [kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32") for A in mats]
-    mu = kpm.kpm_moments_batched(ctx, D, np.array(lb), np.array(ub), 127, nvec, 40_000)
-    targets = np.array(targets)
-    X, T = [], []
-    for m in TRUNC:
-        Xm = mu.copy()
-        Xm[:, m + 1:] = 0.0
-        X.append(Xm)
-        T.append(targets)
-    return np.concatenate(X), np.concatenate(T)
-
-
 def _blur_l1(mu, g, ref):
     t = oracle.midpoints(200)
     return oracle.l1_error(ref, oracle.blurred_kpm(mu, g, t, SIGMA, Q=8192))
@@ -94,14 +69,10 @@ def _blur_l1(mu, g, ref):
 
 @pytest.fixture(scope="module")
 def trained(ctx):
-    """The damping network, trained once on device for this module."""
-    _say("training set")
-    X, T = _training_set(ctx)
-    kpm.kpm_mlp_init(ctx, 7)
-    _say(f"training on {len(X)} samples")
-    losses = kpm.kpm_mlp_train(ctx, X, T, SIGMA, 150, 128, 1e-3, 3)
-    assert losses[-1] < losses[0]
-    return losses
+    """The shipped damping network."""
+    if not os.path.exists(kpm.DAMPING_WEIGHTS):
+        pytest.skip("no shipped damping weights")
+    kpm.kpm_mlp_load(ctx, kpm.DAMPING_WEIGHTS)
 
 
 def _degree_rows(ctx, mu32, mu64, ref):
@@ -121,9 +92,13 @@ def _degree_rows(ctx, mu32, mu64, ref):
     return rows
 
 
-def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
-    losses = trained
+def _degrees(rows):
+    """Lowest tabulated degree at which FP64 + Jackson, FP32 + learned and
+    FP32 undamped first reach L1 <= 1e-2."""
+    return tuple(min(r["M"] for r in rows if r[k] <= 1e-2) for k in ("fp64_jackson", "fp32_learned", "fp32_none"))
 
+
+def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
     _say("c2 workload")
     A = synth.config_matrix("c2")
     D32 = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32")
@@ -142,8 +117,7 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
     ref = oracle.blurred_kpm(mu_ref, np.ones(513), t, SIGMA, Q=8192)
 
     rows = _degree_rows(ctx, mu32, mu64, ref)
-    M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
-    M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
+    M_J, M_L, M_N = _degrees(rows)
 
     # Stochastic Lanczos method (section 3.2.1), same probes, FP64 recurrence:
     # M Lanczos steps = M sparse products per probe (KPM of degree M uses M/2).
@@ -155,12 +129,12 @@ def test_fp32_learned_vs_fp64_jackson_on_anderson64(ctx, trained):
         slq_rows.append(dict(M=Ms, slq_fp64=oracle.l1_error(ref, phi)))
         _say("Lanczos steps=%3d  L1 %.4f" % (Ms, slq_rows[-1]["slq_fp64"]))
     M_S = min(r["M"] for r in slq_rows if r["slq_fp64"] <= 1e-2)
-    summary = dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L,
-                   slq_rows=slq_rows, M_slq_fp64=M_S,
-                   train_loss_first=float(losses[0]), train_loss_last=float(losses[-1]))
+    summary = dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, M_fp32_none=M_N,
+                   slq_rows=slq_rows, M_slq_fp64=M_S)
     _save_study("accuracy_study.json", summary)
-    _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}; Lanczos steps {M_S}")
-    assert M_L < M_J
+    _say(f"degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}, FP32+none {M_N}; Lanczos steps {M_S}")
+    assert (M_J, M_L, M_N, M_S) == (bench.M_FP64_JACKSON, bench.M_FP32_LEARNED, bench.M_FP32_NONE, bench.M_SLQ)
+    assert M_L < M_J and M_N < M_J
     # the network must not be worse than Jackson at the same degree and precision
     for r in rows:
         assert r["fp32_learned"] <= r["fp32_jackson"] + 1e-3, r
@@ -188,11 +162,11 @@ def test_fp32_learned_vs_fp64_jackson_on_large(ctx, trained):
     assert np.max(np.abs(mu32 - mu_ref[:128])) < 1e-5
     ref = oracle.blurred_kpm(mu_ref, np.ones(513), oracle.midpoints(200), SIGMA, Q=8192)
     rows = _degree_rows(ctx, mu32, mu64, ref)
-    M_J = min(r["M"] for r in rows if r["fp64_jackson"] <= 1e-2)
-    M_L = min(r["M"] for r in rows if r["fp32_learned"] <= 1e-2)
+    M_J, M_L, M_N = _degrees(rows)
     _save_study("accuracy_study_large.json",
-                dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, nvec=nvec))
-    _say(f"large workload, degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}")
-    assert M_L < M_J
+                dict(sigma=SIGMA, rows=rows, M_fp64_jackson=M_J, M_fp32_learned=M_L, M_fp32_none=M_N, nvec=nvec))
+    _say(f"large workload, degree for L1 <= 1e-2: FP64+Jackson {M_J}, FP32+learned {M_L}, FP32+none {M_N}")
+    assert (M_J, M_L, M_N) == (bench.M_LARGE_FP64_JACKSON, bench.M_LARGE_FP32_LEARNED, bench.M_LARGE_FP32_NONE)
+    assert M_L < M_J and M_N < M_J
     for r in rows:
         assert r["fp32_learned"] <= r["fp32_jackson"] + 1e-3, r

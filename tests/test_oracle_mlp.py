@@ -169,3 +169,30 @@ def test_full_batch_trajectory_descends_and_matches_steps():
         for k in q:
             assert np.array_equal(q[k], traj[t - 1][k])
     assert losses[-1] < losses[0] and min_resid > 0
+
+
+def test_damping_labels_file_matches_its_recipe():
+    """tests/golden/damping_labels.npz holds what make_damping_labels.py
+    computes: recompute one training and one held-out matrix of each family
+    from the oracle (eigh bounds, blurred exact density), and check the
+    counts and that no matrix is both a training and a held-out one."""
+    import os
+    import sys
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    try:
+        import make_damping_labels as mk
+    finally:
+        sys.path.remove(here)
+    z = np.load(os.path.join(here, "damping_labels.npz"))
+    fam, idx, split = z["family"], z["index"], z["split"]
+    assert len(fam) == 2560 and int(np.sum(split == 0)) == 2304 and float(z["sigma"]) == 0.02
+    keys = {(int(f), int(i)) for f, i in zip(fam, idx)}
+    assert len(keys) == len(fam)
+    for f in (0, 1, 2):
+        for s in (0, 1):
+            k = int(np.flatnonzero((fam == f) & (split == s))[0])
+            lb, ub, phi = mk.label((int(fam[k]), int(idx[k])))
+            assert abs(lb - z["lb"][k]) < 1e-12 * abs(ub - lb) + 1e-12 and abs(ub - z["ub"][k]) < 1e-9
+            assert np.max(np.abs(phi - z["label"][k])) < 1e-6 * max(1.0, np.max(phi))
+            assert abs(np.sum(phi) * 0.01 - 1.0) < 2e-3  # unit mass up to the tails beyond [-1, 1]
