@@ -623,13 +623,16 @@ def batched_leg(kpm, ctx, synth, reps=5, tune=True):
             "autotuned": tuned_out}
 
 
-def training_set_leg(kpm, ctx, synth, reps=3, block=64, bounds="lanczos"):
+def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
     """Moments of the damping network's full-size training set in one
     batched call: 8,192 random sparse symmetric matrices (n = 2,048) and
-    1,024 2D Anderson 32 x 64 matrices, degree 127, 256 probes each as 4
-    blocks of 64, FP32, graph replay; then one network inference over all
-    9,216 moment vectors.  Bounds: Lanczos per matrix with escape recovery,
-    before timing."""
+    1,024 2D Anderson 32 x 64 matrices, degree 127, 256 probes each, FP32,
+    graph replay; on the on-chip path (the library's choice: one workgroup
+    per matrix and block of 8 probes, vectors in LDS for all 64 steps) and,
+    for comparison, on the streaming path (4 blocks of 64 probes in device
+    memory, one launch per step); then one network inference over all 9,216
+    moment vectors.  Bounds: Lanczos per matrix with escape recovery, before
+    timing."""
     t0 = time.perf_counter()
     mats = synth.damping_training_set()
     t_gen = time.perf_counter() - t0
@@ -647,7 +650,7 @@ def training_set_leg(kpm, ctx, synth, reps=3, block=64, bounds="lanczos"):
     ub = np.array([b[1] for b in bl])
     M, nvec = 127, 256
     for attempt in range(3):
-        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2004, block=block, return_max_abs=True)
+        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2004, return_max_abs=True)
         bad = [m for m in range(len(D)) if not mx[m] <= 1 + 1e-4]
         if not bad:
             break
@@ -657,25 +660,45 @@ def training_set_leg(kpm, ctx, synth, reps=3, block=64, bounds="lanczos"):
             else:
                 lo, hi = kpm.kpm_gershgorin(ctx, D[m])
                 lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
-    kpm.kpm_profile_reset(ctx)
-    kpm.kpm_profile_enable(ctx, True)
-    ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2004, block=block), reps)
-    kpm.kpm_profile_enable(ctx, False)
-    n_dev, dev_ms = kpm.kpm_profile_query(ctx, "batched")
-    dev_avg = dev_ms / max(n_dev, 1)
     nnz = sum(A.nnz for A in mats)
     n = sum(A.n for A in mats)
     K = (M + 1) // 2
-    nvb = (nvec + block - 1) // block
-    byts = K * nvb * (8 * nnz + 4 * (n + len(mats)) + 3 * 4 * n * block)
+
+    def timed(block):
+        kpm.kpm_profile_reset(ctx)
+        kpm.kpm_profile_enable(ctx, True)
+        ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2004, block=block), reps)
+        kpm.kpm_profile_enable(ctx, False)
+        n_dev, dev_ms = kpm.kpm_profile_query(ctx, "batched")
+        return ms, dev_ms / max(n_dev, 1)
+
+    ms, dev_avg = timed(0)
+    ms_s, dev_s = timed(64)
+    # on-chip path, blocks of 8 probes: every step reads each matrix's CSR
+    # (from L2: the 32 blocks of a matrix run side by side on one XCD) and
+    # moves each block's gathered rows, own and previous rows and new rows
+    # through LDS
+    b_res = 8
+    nvb_res = nvec // b_res
+    csr_bytes = K * nvb_res * (8 * nnz + 4 * (n + len(mats)))
+    lds_bytes = K * nvb_res * (nnz + 3 * n) * 4 * b_res
+    # streaming path, blocks of 64: the probe blocks' compulsory bytes
+    nvb_s = (nvec + 63) // 64
+    byts_s = K * nvb_s * (8 * nnz + 4 * (n + len(mats)) + 3 * 4 * n * 64)
     load_damping_network(kpm, ctx)
     X = np.ascontiguousarray(mu[:, :128])
     ms_inf = _time_ms(lambda: kpm.kpm_mlp_forward(ctx, X), 5)
-    return {"matrices": len(mats), "sum_n": n, "sum_nnz": nnz, "M": M, "nvec": nvec, "block": block,
+    return {"matrices": len(mats), "sum_n": n, "sum_nnz": nnz, "M": M, "nvec": nvec,
+            "path": "on-chip (LDS-resident vectors, one workgroup per matrix and 8-probe block)",
             "ms_per_call": round(ms, 2), "device_ms_per_call": round(dev_avg, 2),
             "units_per_s": nnz * M * nvec / (ms * 1e-3),
-            "algorithmic_gbs_device": round(byts / (dev_avg * 1e-3) / 1e9, 1),
-            "algorithmic_bytes_per_call": int(byts),
+            "csr_bytes_per_call": int(csr_bytes), "csr_gbs_device": round(csr_bytes / (dev_avg * 1e-3) / 1e9, 1),
+            "lds_bytes_per_call": int(lds_bytes), "lds_gbs_device": round(lds_bytes / (dev_avg * 1e-3) / 1e9, 1),
+            "streaming": {"block": 64, "ms_per_call": round(ms_s, 2), "device_ms_per_call": round(dev_s, 2),
+                          "units_per_s": nnz * M * nvec / (ms_s * 1e-3),
+                          "algorithmic_bytes_per_call": int(byts_s),
+                          "algorithmic_gbs_device": round(byts_s / (dev_s * 1e-3) / 1e9, 1)},
+            "speedup_over_streaming": round(dev_s / dev_avg, 2),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
             "network_inference_ms_9216": round(ms_inf, 3),
             "host_generation_s": round(t_gen, 1), "bounds": bounds, "bounds_s": round(t_bounds, 1)}

@@ -96,6 +96,12 @@ enum {
                               round trip per 7-point stencil row at 5
                               wavefronts per SIMD); the GATHER flags override
                               the KPM_TUNE environment default               */
+    KPM_FLAG_BATCH_STREAM = 32,   /* kpm_moments_batched: stream every probe
+                              block through device memory (one launch per
+                              step) even when the on-chip path applies     */
+    KPM_FLAG_BATCH_RESIDENT = 64, /* kpm_moments_batched: the on-chip path
+                              (KPM_ERR_UNSUPPORTED when a matrix is too
+                              large for it)                                 */
     KPM_FLAG_LEGENDRE_RECURRENCE = 16 /* kpm_legendre_moments: run the
                               Legendre three-term recurrence of Algorithm DGL
                               (M sparse products per block) instead of
@@ -238,11 +244,21 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
 
 /*
  * kpm_moments_batched -- the same moments for nmat independent matrices of
- * uneven size.  Each recurrence step is one launch over every (matrix,
- * probe block, row-panel range) of all matrices; the launch sequence is
- * captured once per shape (matrix pointers and sizes, M, nvec, block,
- * precision) in a HIP graph on a context-owned stream and replayed on later
- * calls (KPM_FLAG_NO_GRAPH launches it directly).  lb, ub: host [nmat].
+ * uneven size.  Two device paths:
+ *  - on-chip: when opts->block is 0 and two blocks of N, 2N or 4N probes
+ *    (N = 4 FP32, 2 FP64) of the largest matrix fit one workgroup's LDS
+ *    (160 KB: n up to 2,048 with 8 FP32 probes), one workgroup owns each
+ *    (matrix, probe block) pair for all ceil(M/2) steps of eq. (3term) and
+ *    the product identity, its vectors in LDS; one launch for all steps
+ *    (KPM_FLAG_BATCH_RESIDENT asks for it with a given block width);
+ *  - streaming (otherwise, or with KPM_FLAG_BATCH_STREAM): each recurrence
+ *    step is one launch over every (matrix, probe block, row-panel range)
+ *    of all matrices, the probe blocks in device memory.
+ * The per-probe vectors of both paths are bitwise equal (same per-row
+ * arithmetic); the dots are summed in different orders.  The launch
+ * sequence is captured once per shape (matrix pointers and sizes, M, nvec,
+ * block, precision, path) in a HIP graph on a context-owned stream and
+ * replayed on later calls (KPM_FLAG_NO_GRAPH launches it directly).  lb, ub: host [nmat].
  * All matrices share opts (M, nvec, block, precision, seed); matrix m uses
  * probe vectors of seed opts->seed + m.  mu: host [nmat * (M+1)], mu[m*(M+1)+k].
  * A[m].on_device must be 1 and the value type common to all m; the FP32
@@ -251,13 +267,16 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
  * most 1 when its spectrum lies in [lb, ub]; +inf if non-finite).  Returns
  * KPM_ERR_SPECTRUM (after writing every output) if a matrix's spectrum is
  * not inside its [lb, ub].  nmat <= 65535, and at most 65535 (matrix, probe
- * block) pairs.  Device memory (one allocation per shape, kept by the
- * context until the shape changes or kpm_destroy): two probe blocks of
- * n_m x ld values per pair, dot partials of two steps per workgroup (2 x 2 x
- * ld doubles each; a pair gets at least 16 workgroups when there are more
+ * block) pairs on the streaming path (2^26 on the on-chip path).  Device
+ * memory (one allocation per shape, kept by the context until the shape
+ * changes or kpm_destroy): on the streaming path two probe blocks of n_m x
+ * ld values per pair, dot partials of two steps per workgroup (2 x 2 x ld
+ * doubles each; a pair gets at least 16 workgroups when there are more
  * pairs than resident workgroups), K x 2 x ld doubles of dots per pair and
  * the per-probe moments -- about 45 GB for 9,216 matrices of n = 2,048 with
- * 256 FP32 probes each.  KPM_ERR_ALLOC if it cannot be allocated.
+ * 256 FP32 probes each, of which the on-chip path needs only the per-probe
+ * moments (nmat x nvec x (M+1) doubles, 2.4 GB there).  KPM_ERR_ALLOC if it
+ * cannot be allocated.
  */
 kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
                                const double* ub, const kpm_moment_opts* opts, double* mu,

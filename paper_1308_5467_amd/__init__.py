@@ -250,6 +250,7 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
 
 KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8, KPM_FLAG_GATHER7 = 1, 2, 4, 8
 KPM_FLAG_LEGENDRE_RECURRENCE = 16
+KPM_FLAG_BATCH_STREAM, KPM_FLAG_BATCH_RESIDENT = 32, 64
 
 
 def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
@@ -406,13 +407,19 @@ def kpm_slq_heat_capacity(ctx: Context, theta, tau2, T) -> np.ndarray:
 
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",
                         block: int = 0, validate: bool = False, graph: bool = True, rows_per_block: int = 0,
-                        return_max_abs: bool = False):
-    """Moments [nmat, M+1] of several device-resident matrices in one launch per step.
+                        return_max_abs: bool = False, path: str = "auto"):
+    """Moments [nmat, M+1] of several device-resident matrices.
 
-    With return_max_abs=True returns (mu, max_abs) and does not raise on a
-    spectrum escape (max_abs[m] > 1 marks the matrices whose [lb, ub] was too narrow).
+    path: "auto" (the on-chip path when block is 0 and every matrix fits it,
+    else streaming), "stream" or "resident" (KPM_FLAG_BATCH_STREAM /
+    KPM_FLAG_BATCH_RESIDENT).  With return_max_abs=True returns (mu,
+    max_abs) and does not raise on a spectrum escape (max_abs[m] > 1 marks
+    the matrices whose [lb, ub] was too narrow).
     """
-    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, 0 if graph else KPM_FLAG_NO_GRAPH)
+    flags = {"auto": 0, "stream": KPM_FLAG_BATCH_STREAM, "resident": KPM_FLAG_BATCH_RESIDENT}[path]
+    if not graph:
+        flags |= KPM_FLAG_NO_GRAPH
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags)
     arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
     lbv, ubv = _f64(lb), _f64(ub)
     mu = np.zeros((len(mats), M + 1))

@@ -15,6 +15,20 @@
 // range and stride through it together (one moving band of rows per mv and
 // XCD, whose plane-apart gathers stay in that XCD's L2).
 //
+// On-chip path.  When every matrix is small enough that two probe blocks of
+// it fit in one workgroup's LDS (160 KB on gfx950: n = 2,048 with 8 FP32 or
+// 4 FP64 probes per block), each (matrix, probe block) pair is owned by one
+// workgroup for all ceil(M/2) steps: the probes are generated in LDS, both
+// recurrence vectors stay there, the CSR is read from global memory (L2:
+// the pairs of one matrix run side by side on one XCD), each step's dots are
+// reduced in a fixed order and assembled into the per-probe moments at once.
+// No vector ever reaches HBM and no barrier is needed beyond the
+// workgroup's own, which answers the cross-step fence cost below for pairs
+// that fit.  Per row the arithmetic is that of the streaming step (same
+// FP32 sum order over the row's entries, the same FP64 combination), so
+// the vectors are bitwise those of the streaming path; only the dots'
+// summation order differs.
+//
 // Steps are separate launches rather than one kernel with device-wide
 // barriers between steps: on MI355X a device-scope release/acquire writes
 // back and invalidates an XCD's L2, while back-to-back launches on one
@@ -139,6 +153,251 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
     }
 }
 
+// ---------------------------------------------------------------- on-chip path
+constexpr int kResWaves = 16;
+constexpr int kResThreads = 64 * kResWaves;
+
+// Dynamic LDS of the on-chip kernel: two [n x LD] vector blocks and the
+// per-wave dot partials of two steps.
+__host__ __device__ constexpr size_t resident_lds_bytes(int n, int LD, int esz) {
+    return (((size_t)2 * n * LD * esz + 15) & ~(size_t)15) + (size_t)2 * kResWaves * 2 * LD * 8;
+}
+
+// Sliced layout of the matrices for the on-chip kernel.  A wavefront works
+// on C rows at a time (C = rows per wavefront), and its loads of the k-th
+// entry of those rows from CSR touch C different rows' entries -- many
+// cache lines per instruction, which made the texture path, not the bytes,
+// the limit.  Here each matrix's rows are ordered by decreasing length
+// (ties by index) and cut into slices of C; slice s stores its entries
+// slot-major, entry q of its l-th row at [slo[s] + q C + l] for q < W_s,
+// the slice's longest row, with that row's index in srow[s C + l] (-1 past
+// the last row).  Slots past a row's end hold the row itself with weight 0
+// (exact), as the streaming step pads its gather batches.  A wavefront's
+// load of one slot is then C consecutive pairs; ordering by length keeps
+// each slice's rows about equally long, so few slots are padding; and each
+// row's entries keep their CSR order, so the FP32 row sums are those of the
+// streaming path (only the order in which a lane accumulates its rows' dot
+// products changes).  Order, widths and offsets are fixed when the plan is
+// built; the entries are refilled from the CSR at every call (values may
+// change between calls, the sparsity structure of a matrix at a given
+// address not: a row longer than its slice's width is reported).
+struct SellMatDev {
+    const int32_t* rp;
+    const int32_t* ci;
+    const void* val;
+    void* sell;          // the slots of all matrices
+    const int32_t* slw;  // width of each slice of this matrix
+    const int64_t* slo;  // first slot of each slice (index into sell)
+    const int32_t* srow; // row of each slice lane [nsl * C], -1 past the last row
+    int32_t n, nsl;
+};
+
+// Row lengths of every matrix (grid: x over rows, y over matrices).
+__global__ void row_length_kernel(const SellMatDev* __restrict__ mats, const int64_t* __restrict__ row_base,
+                                  int32_t* __restrict__ len) {
+    const SellMatDev& m = mats[blockIdx.y];
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < m.n) len[row_base[blockIdx.y] + r] = m.rp[r + 1] - m.rp[r];
+}
+
+// Fill every matrix's slots from its CSR (grid: x over slice lanes, y over matrices).
+template <typename TA>
+__global__ void sell_fill_kernel(const SellMatDev* __restrict__ mats, int C, int* __restrict__ bad) {
+    const SellMatDev& m = mats[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = i / C, l = i - s * C;
+    if (s >= m.nsl) return;
+    const int W = m.slw[s];
+    const int r = m.srow[i];
+    CsrPair<TA>* e = static_cast<CsrPair<TA>*>(m.sell) + m.slo[s] + l;
+    const TA* val = static_cast<const TA*>(m.val);
+    int kb = 0, len = 0;
+    if (r >= 0) {
+        kb = m.rp[r];
+        len = m.rp[r + 1] - kb;
+        if (len > W) bad[0] = 1;
+    }
+    for (int q = 0; q < W; ++q) {
+        CsrPair<TA> t;
+        if (q < len) {
+            t.c = m.ci[kb + q];
+            t.v = val[kb + q];
+        } else {
+            t.c = r >= 0 ? r : 0;
+            t.v = (TA)0;
+        }
+        e[(int64_t)q * C] = t;
+    }
+}
+
+// One workgroup per (matrix, probe block) pair for all K steps (see the
+// file comment).  Writes zeta_norm[(mat * nvec + vec0 + c) * (M+1) + k] for
+// k = 0..M and the pair's columns c < ncols, as batched_assemble_kernel does
+// from the streaming path's dots:
+//   zeta_0 = n, zeta_1 = D0[0], zeta_{2m} = 2 D1[m-1] - n, zeta_{2m+1} = 2 D0[m] - zeta_1,
+// with D0[k] = <v_{k+1}, v_k> and D1[k] = <v_{k+1}, v_{k+1}> of step k.
+template <typename TA, typename TV, int LD, int G>
+__global__ __launch_bounds__(kResThreads) void resident_kernel(const BatchMvDev* __restrict__ mvs,
+                                                               const SellMatDev* __restrict__ mats, int nmv, int K,
+                                                               int M, int nvec, double* __restrict__ zeta_norm) {
+    constexpr int N = Pack<TV>::N;
+    constexpr int LPR = LD / N;            // lanes per matrix row
+    constexpr int RPW = 64 / LPR;          // rows per wavefront = slice height
+    extern __shared__ __align__(16) char lds_raw[];
+    const int pi = xcd_panel(blockIdx.x, nmv);  // consecutive pairs (one matrix's blocks) on one XCD
+    const BatchMvDev& mv = mvs[pi];
+    const SellMatDev& sm = mats[mv.mat];
+    const int n = mv.n;
+    TV* const buf0 = reinterpret_cast<TV*>(lds_raw);
+    TV* const buf1 = buf0 + (size_t)n * LD;
+    double* const red = reinterpret_cast<double*>(lds_raw + (((size_t)2 * n * LD * sizeof(TV) + 15) & ~(size_t)15));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rw = lane / LPR, cg = lane - rw * LPR;
+    const int c0 = cg * N;
+    const double nn = (double)n;
+    double* const zrow = zeta_norm + ((int64_t)mv.mat * nvec + mv.vec0) * (M + 1);
+    // zeta_0 = n: normalised 1
+    if ((int)threadIdx.x < mv.ncols) zrow[(int64_t)threadIdx.x * (M + 1)] = 1.0;
+    if (K == 0) return;
+
+    // v_0: Rademacher probes vec0 .. vec0 + ncols - 1, zero padding columns
+    for (int idx = threadIdx.x; idx < n * LD; idx += kResThreads) {
+        const int i = idx / LD, j = idx - i * LD;
+        buf0[idx] = j < mv.ncols ? (TV)rademacher_sign(mv.seed, (uint64_t)(mv.vec0 + j), (uint64_t)i) : (TV)0;
+    }
+    __syncthreads();
+    // global (not generic) pointers: the slot loads become global loads
+    typedef const __attribute__((address_space(1))) CsrPair<TA>* gpair;
+    const gpair sell = (gpair)sm.sell;
+    const int32_t* __restrict__ slw = sm.slw;
+    const int64_t* __restrict__ slo = sm.slo;
+    double zeta1 = 0.0;  // D0[0] of column threadIdx.x (threads < LD)
+    const int32_t* __restrict__ srow = sm.srow;
+    // G slots q0 .. q0 + G - 1 of this lane's row in slice s (slots at or past
+    // the slice width W, which is the same for the whole wavefront, are not
+    // loaded: the row itself with weight 0).
+    auto load_batch = [&](int64_t base, int W, int q0, int row, int (&j)[G], TV (&a)[G]) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (q0 + i < W) {
+                const int64_t at = base + (int64_t)(q0 + i) * RPW + rw;
+                j[i] = sell[at].c;
+                a[i] = (TV)sell[at].v;
+            } else {
+                j[i] = row;
+                a[i] = (TV)0;
+            }
+        }
+    };
+    // The first batch of a wavefront's next slice is loaded while the
+    // current one gathers (the slots do not change between steps, so the
+    // last slice of a step loads the first one's batch for the next step).
+    const int nsl = sm.nsl;
+    int jn[G];
+    TV an[G];
+    int rown = 0;
+    if (wave < nsl) {
+        rown = srow[wave * RPW + rw];
+        load_batch(slo[wave], slw[wave], 0, rown, jn, an);
+    }
+    for (int k = 0; k < K; ++k) {
+        const TV* V = (k & 1) ? buf1 : buf0;
+        TV* U = (k & 1) ? buf0 : buf1;
+        const double alpha = k == 0 ? 0.5 * mv.alpha : mv.alpha;
+        const double beta = k == 0 ? 0.5 * mv.beta : mv.beta;
+        double sx[N], ss[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) sx[e] = ss[e] = 0.0;
+#pragma unroll 1
+        for (int sl = wave; sl < nsl; sl += kResWaves) {
+            const int row = rown;
+            int jc[G];
+            TV ac[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                jc[i] = jn[i];
+                ac[i] = an[i];
+            }
+            const int W = slw[sl];
+            const int64_t base = slo[sl];
+            const int sn = sl + kResWaves < nsl ? sl + kResWaves : wave;
+            rown = srow[sn * RPW + rw];
+            if (sn != wave || k + 1 < K) load_batch(slo[sn], slw[sn], 0, rown, jn, an);
+            TV acc[N];
+#pragma unroll
+            for (int e = 0; e < N; ++e) acc[e] = (TV)0;
+            for (int q = 0; q < W; q += G) {
+                if (q != 0) load_batch(base, W, q, row, jc, ac);
+                if (row >= 0) {
+                    // only the slice's W slots: the slots of the last batch
+                    // past W are not gathered (W is the same for the wavefront)
+                    TV x[G][N];
+#pragma unroll
+                    for (int i = 0; i < G; ++i)
+                        if (q + i < W) Pack<TV>::load(V + (size_t)jc[i] * LD + c0, x[i]);
+#pragma unroll
+                    for (int i = 0; i < G; ++i)
+                        if (q + i < W)
+#pragma unroll
+                            for (int e = 0; e < N; ++e) acc[e] = fma(ac[i], x[i][e], acc[e]);
+                }
+            }
+            if (row < 0) continue;
+            TV own[N], out[N];
+            Pack<TV>::load(V + (size_t)row * LD + c0, own);
+            if (k == 0) {
+#pragma unroll
+                for (int e = 0; e < N; ++e) out[e] = (TV)fma(alpha, (double)acc[e], beta * (double)own[e]);
+            } else {
+                TV u[N];
+                Pack<TV>::load(U + (size_t)row * LD + c0, u);
+#pragma unroll
+                for (int e = 0; e < N; ++e)
+                    out[e] = (TV)fma(alpha, (double)acc[e], fma(beta, (double)own[e], -(double)u[e]));
+            }
+            Pack<TV>::store(U + (size_t)row * LD + c0, out);
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                const double o = (double)out[e];
+                sx[e] = fma(o, (double)own[e], sx[e]);
+                ss[e] = fma(o, o, ss[e]);
+            }
+        }
+        // rows of the wavefront -> one value per column, fixed butterfly
+#pragma unroll
+        for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                sx[e] += __shfl_xor(sx[e], off, 64);
+                ss[e] += __shfl_xor(ss[e], off, 64);
+            }
+        double* rk = red + (size_t)(k & 1) * kResWaves * 2 * LD;
+        if (rw == 0) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) {
+                rk[(wave * 2 + 0) * LD + c0 + e] = sx[e];
+                rk[(wave * 2 + 1) * LD + c0 + e] = ss[e];
+            }
+        }
+        __syncthreads();  // U complete for the next step; the partials of step k readable
+        const int t = threadIdx.x;
+        if (t < 2 * LD) {
+            const int d = t / LD, c = t - d * LD;
+            double s = 0.0;
+            for (int w = 0; w < kResWaves; ++w) s += rk[(w * 2 + d) * LD + c];
+            if (c < mv.ncols) {
+                if (d == 0) {  // D0[k]: zeta_{2k+1}
+                    if (k == 0) zeta1 = s;
+                    const double z = k == 0 ? s : 2.0 * s - zeta1;
+                    if (2 * k + 1 <= M) zrow[(int64_t)c * (M + 1) + 2 * k + 1] = z / nn;
+                } else if (2 * k + 2 <= M) {  // D1[k]: zeta_{2k+2}
+                    zrow[(int64_t)c * (M + 1) + 2 * k + 2] = (2.0 * s - nn) / nn;
+                }
+            }
+        }
+    }
+}
+
 // Probe blocks of every mv: X0 = Rademacher probes vec0.. of seed_mv (zero padding).
 template <typename T>
 __global__ void batched_fill_kernel(const BatchMvDev* __restrict__ mvs, int ld) {
@@ -237,6 +496,12 @@ struct BatchPlan {
     BatchShape shape;
     int nmat = 0, nmv = 0, nentries = 0, M = 0, K = 0, nvec = 0, ld = 0, lpr = 0, rpw = 0, rows = 0;
     int precision = 0, val_f64 = 0, stage = 1;
+    bool resident = false;  // the on-chip path: one workgroup per mv for all steps
+    size_t lds_bytes = 0;   // its dynamic LDS per workgroup
+    int sell_C = 0, max_nsl = 0;   // its slice height and the most slices of a matrix
+    void* sell_mem = nullptr;      // its slots (second allocation)
+    SellMatDev* d_mats = nullptr;  // per matrix: CSR and slice tables
+    int* d_bad = nullptr;          // set when a row outgrows its slice
     std::vector<BatchMvDev> mvs;  // host copy (alpha/beta/seed refreshed per call)
     void* mem = nullptr;          // one device allocation for everything below
     size_t mem_bytes = 0;
@@ -266,8 +531,48 @@ int batched_resident() {
     return per_cu * prop.multiProcessorCount;
 }
 
+template <typename TA, typename TV, int LD>
+const void* resident_fn() {
+    // 8 slots per batch; 4 with FP64 vectors (16-byte slots and FP64 rows
+    // would spill at 8)
+    return reinterpret_cast<const void*>(resident_kernel<TA, TV, LD, sizeof(TV) == 8 ? 4 : 8>);
+}
+
+// The on-chip kernel for this precision and block width (ld), or nullptr.
+template <typename TA, typename TV>
+const void* resident_kernel_for(int ld) {
+    constexpr int N = Pack<TV>::N;
+    if (ld == 4 * N) return resident_fn<TA, TV, 4 * N>();
+    if (ld == 2 * N) return resident_fn<TA, TV, 2 * N>();
+    if (ld == N) return resident_fn<TA, TV, N>();
+    return nullptr;
+}
+
+__global__ void clear_flag_kernel(int* flag) { flag[0] = 0; }
+
+template <typename TA, typename TV>
+hipError_t enqueue_resident(hipStream_t s, const BatchPlan& P) {
+    const void* fn = resident_kernel_for<TA, TV>(P.ld);
+    if (!fn) return hipErrorInvalidValue;
+    clear_flag_kernel<<<1, 1, 0, s>>>(P.d_bad);
+    const dim3 fg((unsigned)(((int64_t)P.max_nsl * P.sell_C + 255) / 256), P.nmat);
+    sell_fill_kernel<TA><<<fg, 256, 0, s>>>(P.d_mats, P.sell_C, P.d_bad);
+    int nmv = P.nmv, K = P.K, M = P.M, nvec = P.nvec;
+    double* z = P.d_zeta;
+    const BatchMvDev* mvs = P.d_mvs;
+    const SellMatDev* mats = P.d_mats;
+    void* args[] = {(void*)&mvs, (void*)&mats, &nmv, &K, &M, &nvec, &z};
+    hipError_t e = hipLaunchKernel(fn, dim3(P.nmv), dim3(kResThreads), args, P.lds_bytes, s);
+    if (e != hipSuccess) return e;
+    dim3 mg(P.M + 1, P.nmat);
+    batched_mean_kernel<<<mg, 64, 0, s>>>(P.d_zeta, P.nvec, P.M, P.d_mu);
+    batched_check_kernel<<<P.nmat, 256, 0, s>>>(P.d_zeta, P.nvec, P.M, P.d_maxabs);
+    return hipGetLastError();
+}
+
 template <typename TA, typename TV>
 hipError_t enqueue_batched(hipStream_t s, const BatchPlan& P) {
+    if (P.resident) return enqueue_resident<TA, TV>(s, P);
     dim3 fill_grid(256, P.nmv);
     batched_fill_kernel<TV><<<fill_grid, 256, 0, s>>>(P.d_mvs, P.ld);
     const size_t width = 2 * (size_t)P.ld;
@@ -308,9 +613,11 @@ void free_plan(BatchPlan& P) {
     if (P.exec) hipGraphExecDestroy(P.exec);
     if (P.graph) hipGraphDestroy(P.graph);
     if (P.mem) hipFree(P.mem);
+    if (P.sell_mem) hipFree(P.sell_mem);
     P.exec = nullptr;
     P.graph = nullptr;
     P.mem = nullptr;
+    P.sell_mem = nullptr;
     P.mem_bytes = 0;
 }
 
@@ -330,6 +637,18 @@ void kpm_batch_free(kpm_ctx* ctx) {
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// LDS bytes one workgroup may use on `device` (queried once per device).
+static size_t lds_per_workgroup(int device) {
+    static size_t cache[64] = {};
+    if (device < 0 || device >= 64) return 0;
+    if (!cache[device]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
+        cache[device] = prop.sharedMemPerBlock;
+    }
+    return cache[device];
+}
 
 // Lower bound on the table entries (workgroups) per mv when there are more
 // mvs than resident workgroups.  The proportional share then rounds to one
@@ -373,16 +692,44 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         if (o->validate && (st = kpm_validate_csr(ctx, D[m])) != KPM_OK) return st;
     }
     const int M = o->M, nvec = o->nvec;
-    const int b = o->block > 0 ? std::min(o->block, nvec) : kpm_default_block(nvec, o->precision);
     int64_t nmax = 0;
     for (int m = 0; m < nmat; ++m) nmax = std::max<int64_t>(nmax, D[m].n);
-    const BlockGeom g = make_geom(nmax, b, o->precision, o->rows_per_block);
     const int esz = o->precision == KPM_FP64 ? 8 : 4;
+    // On-chip path (file comment): the widest block of N, 2N or 4N probes
+    // (N = 4 FP32, 2 FP64 per lane) whose two vector blocks of the largest
+    // matrix fit one workgroup's LDS; used unless the caller fixes the block
+    // width or asks for the streaming path.
+    const bool force_stream = (o->flags & KPM_FLAG_BATCH_STREAM) != 0;
+    const bool force_res = (o->flags & KPM_FLAG_BATCH_RESIDENT) != 0;
+    if (force_stream && force_res)
+        return kpm_fail(ctx, KPM_ERR_ARG, "KPM_FLAG_BATCH_STREAM and KPM_FLAG_BATCH_RESIDENT exclude each other");
+    int rld = 0;
+    if (!force_stream && (o->block == 0 || force_res)) {
+        const size_t lds_max = lds_per_workgroup(ctx->device);
+        if (!lds_max) return kpm_fail(ctx, KPM_ERR_HIP, "could not query the device's LDS size");
+        const int N = o->precision == KPM_FP64 ? 2 : 4;
+        for (int cand = 4 * N; cand >= N && !rld; cand /= 2) {
+            if (o->block > 0 && cand < (o->block + N - 1) / N * N) break;
+            if (o->block > 0 && cand / 2 >= (o->block + N - 1) / N * N && cand > N) continue;
+            if (resident_lds_bytes((int)nmax, cand, esz) <= lds_max) rld = cand;
+        }
+        // a narrower block when the probes do not fill the chosen one
+        while (rld > N && o->block == 0 && rld / 2 >= nvec) rld /= 2;
+        if (force_res && !rld)
+            return kpm_fail(ctx, KPM_ERR_UNSUPPORTED,
+                            "the on-chip batched path needs two probe blocks of every matrix in one workgroup's LDS");
+    }
+    const bool resident = rld > 0;
+    const int b = o->block > 0 ? std::min(o->block, nvec)
+                               : (resident ? std::min(rld, nvec) : kpm_default_block(nvec, o->precision));
+    const BlockGeom g = make_geom(nmax, b, o->precision, o->rows_per_block);
     if ((uint64_t)nmax * g.ld * esz >= (1ull << 32))
         return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "batched probe blocks must be smaller than 4 GiB");
     const int nvb = (nvec + b - 1) / b;
-    if ((int64_t)nmat * nvb > 65535)
+    if (!resident && (int64_t)nmat * nvb > 65535)
         return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "at most 65535 (matrix, probe block) pairs per batch");
+    if ((int64_t)nmat * nvb > (1 << 26))
+        return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "at most 2^26 (matrix, probe block) pairs per batch");
 
     BatchShape shape;
     for (int m = 0; m < nmat; ++m) {
@@ -392,8 +739,8 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         shape.dims.push_back(D[m].n);
         shape.dims.push_back(D[m].nnz);
     }
-    const int64_t tail[] = {nmat, M, nvec, b, o->precision, D[0].val_f64, g.rows_per_block};
-    shape.dims.insert(shape.dims.end(), tail, tail + 7);
+    const int64_t tail[] = {nmat, M, nvec, b, o->precision, D[0].val_f64, g.rows_per_block, rld};
+    shape.dims.insert(shape.dims.end(), tail, tail + 8);
 
     if (!ctx->batch) ctx->batch = new kpm_batch_state();
     BatchPlan& P = ctx->batch->plan;
@@ -414,12 +761,153 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         P.precision = o->precision;
         P.val_f64 = D[0].val_f64;
         P.nmv = nmat * nvb;
+        P.resident = resident;
+    }
+    if (!reuse && resident) {
+        P.ld = rld;
+        P.lds_bytes = resident_lds_bytes((int)nmax, rld, esz);
+        const void* fn = o->precision == KPM_FP64
+                             ? (P.val_f64 ? resident_kernel_for<double, double>(rld) : resident_kernel_for<float, double>(rld))
+                             : resident_kernel_for<float, float>(rld);
+        if (!fn) return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "no on-chip kernel for this block width");
+        KPM_HIP(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes));
+        // slices of the sliced layout: one per wavefront's rows (rows per
+        // wavefront = 64 lanes / (block values per row / values per lane))
+        const int N = o->precision == KPM_FP64 ? 2 : 4;
+        P.sell_C = 64 / (rld / N);
+        std::vector<int64_t> slice_base(nmat + 1, 0);
+        P.max_nsl = 0;
+        for (int m = 0; m < nmat; ++m) {
+            const int nsl = (int)((D[m].n + P.sell_C - 1) / P.sell_C);
+            slice_base[m + 1] = slice_base[m] + nsl;
+            P.max_nsl = std::max(P.max_nsl, nsl);
+        }
+        const int64_t nslices = slice_base[nmat];
+        const int C = P.sell_C;
+        std::vector<int64_t> row_base(nmat + 1, 0);
+        for (int m = 0; m < nmat; ++m) row_base[m + 1] = row_base[m] + D[m].n;
+        // one device allocation: tables and outputs; the slots in a second
+        // one once their count is known
+        size_t off = 0;
+        const size_t o_mvs = off;
+        off += align256((size_t)P.nmv * sizeof(BatchMvDev));
+        const size_t o_mats = off;
+        off += align256((size_t)nmat * sizeof(SellMatDev));
+        const size_t o_slw = off;
+        off += align256((size_t)nslices * 4);
+        const size_t o_slo = off;
+        off += align256((size_t)nslices * 8);
+        const size_t o_srow = off;
+        off += align256((size_t)nslices * C * 4);
+        const size_t o_len = off;
+        off += align256((size_t)row_base[nmat] * 4);
+        const size_t o_rb = off;
+        off += align256((size_t)nmat * 8);
+        const size_t o_bad = off;
+        off += 256;
+        const size_t o_zeta = off;
+        off += align256((size_t)nmat * nvec * (M + 1) * 8);
+        const size_t o_mu = off;
+        off += align256((size_t)nmat * (M + 1) * 8);
+        const size_t o_max = off;
+        off += align256((size_t)nmat * 8);
+        if (hipMalloc(&P.mem, off) != hipSuccess) {
+            P.mem = nullptr;
+            return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the batched plan failed");
+        }
+        P.mem_bytes = off;
+        char* base = (char*)P.mem;
+        P.d_mvs = (BatchMvDev*)(base + o_mvs);
+        P.d_mats = (SellMatDev*)(base + o_mats);
+        int32_t* d_slw = (int32_t*)(base + o_slw);
+        int64_t* d_slo = (int64_t*)(base + o_slo);
+        int32_t* d_srow = (int32_t*)(base + o_srow);
+        int32_t* d_len = (int32_t*)(base + o_len);
+        int64_t* d_rb = (int64_t*)(base + o_rb);
+        P.d_bad = (int*)(base + o_bad);
+        P.d_zeta = (double*)(base + o_zeta);
+        P.d_mu = (double*)(base + o_mu);
+        P.d_maxabs = (double*)(base + o_max);
+        P.d_entries = nullptr;
+        P.d_e0 = P.d_e1 = nullptr;
+        P.d_partial = P.d_dots = nullptr;
+        P.nentries = 0;
+        std::vector<SellMatDev> hm(nmat);
+        for (int m = 0; m < nmat; ++m) {
+            hm[m].rp = D[m].rp;
+            hm[m].ci = D[m].ci;
+            hm[m].val = D[m].val;
+            hm[m].sell = nullptr;
+            hm[m].slw = d_slw + slice_base[m];
+            hm[m].slo = d_slo + slice_base[m];
+            hm[m].srow = d_srow + slice_base[m] * C;
+            hm[m].n = D[m].n;
+            hm[m].nsl = (int)(slice_base[m + 1] - slice_base[m]);
+        }
+        // row lengths to the host, in one copy
+        KPM_HIP(ctx, hipMemcpyAsync(P.d_mats, hm.data(), hm.size() * sizeof(SellMatDev), hipMemcpyHostToDevice,
+                                    P.gstream));
+        KPM_HIP(ctx, hipMemcpyAsync(d_rb, row_base.data(), (size_t)nmat * 8, hipMemcpyHostToDevice, P.gstream));
+        row_length_kernel<<<dim3((unsigned)((nmax + 255) / 256), nmat), 256, 0, P.gstream>>>(P.d_mats, d_rb, d_len);
+        KPM_HIP(ctx, hipGetLastError());
+        std::vector<int32_t> len(row_base[nmat]);
+        KPM_HIP(ctx, hipMemcpyAsync(len.data(), d_len, len.size() * 4, hipMemcpyDeviceToHost, P.gstream));
+        KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
+        // per matrix: rows by decreasing length (counting sort, ties by
+        // index), slices of C, each slice's width = its first row's length
+        std::vector<int32_t> srow((size_t)nslices * C, -1), w(nslices);
+        std::vector<int64_t> so(nslices);
+        std::vector<int32_t> cnt;
+        int64_t slots = 0;
+        for (int m = 0; m < nmat; ++m) {
+            const int n = D[m].n;
+            const int32_t* L = len.data() + row_base[m];
+            int lmax = 0;
+            for (int r = 0; r < n; ++r) lmax = std::max(lmax, L[r]);
+            cnt.assign((size_t)lmax + 2, 0);
+            for (int r = 0; r < n; ++r) ++cnt[(size_t)(lmax - L[r]) + 1];  // key lmax - len: longest first
+            for (int v = 1; v <= lmax + 1; ++v) cnt[v] += cnt[v - 1];
+            int32_t* out = srow.data() + slice_base[m] * C;
+            for (int r = 0; r < n; ++r) out[cnt[(size_t)(lmax - L[r])]++] = r;
+            for (int64_t sl = 0; sl < slice_base[m + 1] - slice_base[m]; ++sl) {
+                const int64_t g = slice_base[m] + sl;
+                w[g] = L[out[sl * C]];
+                so[g] = slots;
+                slots += (int64_t)w[g] * C;
+            }
+        }
+        const size_t pair_bytes = P.val_f64 ? 16 : 8;
+        if (hipMalloc(&P.sell_mem, std::max<size_t>(256, (size_t)slots * pair_bytes)) != hipSuccess) {
+            P.sell_mem = nullptr;
+            return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the sliced matrices failed");
+        }
+        for (int m = 0; m < nmat; ++m) hm[m].sell = P.sell_mem;
+        KPM_HIP(ctx, hipMemcpyAsync(d_slw, w.data(), (size_t)nslices * 4, hipMemcpyHostToDevice, P.gstream));
+        KPM_HIP(ctx, hipMemcpyAsync(d_slo, so.data(), (size_t)nslices * 8, hipMemcpyHostToDevice, P.gstream));
+        KPM_HIP(ctx, hipMemcpyAsync(d_srow, srow.data(), srow.size() * 4, hipMemcpyHostToDevice, P.gstream));
+        KPM_HIP(ctx, hipMemcpyAsync(P.d_mats, hm.data(), hm.size() * sizeof(SellMatDev), hipMemcpyHostToDevice,
+                                    P.gstream));
+        P.mvs.assign(P.nmv, BatchMvDev());
+        for (int m = 0; m < nmat; ++m)
+            for (int vb = 0; vb < nvb; ++vb) {
+                BatchMvDev& d = P.mvs[m * nvb + vb];
+                d.rp = D[m].rp;
+                d.ci = D[m].ci;
+                d.val = D[m].val;
+                d.X0 = d.X1 = nullptr;
+                d.n = D[m].n;
+                d.ncols = std::min(b, nvec - vb * b);
+                d.mat = m;
+                d.vec0 = vb * b;
+            }
+        KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
+    } else if (!reuse) {
         // work table: workgroups per mv proportional to its bytes of work,
         // and at least kMinEntriesPerMv (or one per panel) for every mv
-        const int resident = o->precision == KPM_FP64
-                                 ? (P.val_f64 ? batched_resident<double, double>() : batched_resident<float, double>())
-                                 : batched_resident<float, float>();
-        const int target = std::max(resident, 256);
+        const int resident_wg = o->precision == KPM_FP64
+                                    ? (P.val_f64 ? batched_resident<double, double>() : batched_resident<float, double>())
+                                    : batched_resident<float, float>();
+        const int target = std::max(resident_wg, 256);
         std::vector<double> work(P.nmv);
         double wsum = 0.0;
         for (int m = 0; m < nmat; ++m)
@@ -576,9 +1064,17 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
     }
     kpm_prof_end_on(ctx, "batched", P.gstream, 1);
     std::vector<double> maxabs(nmat);
+    int bad = 0;
     KPM_HIP(ctx, hipMemcpyAsync(mu, P.d_mu, (size_t)nmat * (M + 1) * 8, hipMemcpyDeviceToHost, P.gstream));
     KPM_HIP(ctx, hipMemcpyAsync(maxabs.data(), P.d_maxabs, (size_t)nmat * 8, hipMemcpyDeviceToHost, P.gstream));
+    if (P.resident) KPM_HIP(ctx, hipMemcpyAsync(&bad, P.d_bad, 4, hipMemcpyDeviceToHost, P.gstream));
     KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
+    if (bad) {
+        free_plan(P);  // rebuilt from the current structure on the next call
+        return kpm_fail(ctx, KPM_ERR_ARG,
+                        "a matrix's sparsity structure changed since its batched plan was built (same addresses and "
+                        "sizes): call again to rebuild the plan");
+    }
     kpm_prof_collect(ctx);
     if (max_abs_mu) memcpy(max_abs_mu, maxabs.data(), (size_t)nmat * 8);
     const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;

@@ -54,22 +54,31 @@ def oracle_mu(A, lb, ub, M, nvec, seed, dtype):
     return oracle.moments(Ao, lb, ub, M, nvec, seed)
 
 
-@pytest.mark.parametrize("dtype,tol,M,nvec,block", [("f32", 1e-5, 40, 10, 4), ("f64", 1e-12, 33, 6, 0),
-                                                    ("f32", 1e-5, 1, 3, 0), ("f32", 1e-5, 0, 2, 0),
-                                                    ("f32", 1e-5, 3, 5, 0), ("f64", 1e-12, 4, 3, 2)])
-def test_batched_parity_small(ctx, dtype, tol, M, nvec, block):
-    _say(f"batched small {dtype} M={M} nvec={nvec} block={block}")
+@pytest.mark.parametrize("dtype,tol,M,nvec,block,path", [
+    ("f32", 1e-5, 40, 10, 4, "auto"), ("f64", 1e-12, 33, 6, 0, "auto"), ("f32", 1e-5, 1, 3, 0, "auto"),
+    ("f32", 1e-5, 0, 2, 0, "auto"), ("f32", 1e-5, 3, 5, 0, "auto"), ("f64", 1e-12, 4, 3, 2, "auto"),
+    ("f32", 1e-5, 40, 10, 0, "stream"), ("f64", 1e-12, 33, 6, 0, "stream"),
+    ("f32", 1e-5, 41, 10, 4, "resident"), ("f32", 1e-5, 40, 37, 8, "resident"), ("f32", 1e-5, 12, 70, 16, "resident"),
+    ("f64", 1e-12, 33, 7, 2, "resident"), ("f64", 1e-12, 32, 9, 4, "resident"), ("f64", 1e-12, 2, 3, 8, "resident"),
+    ("f64", 1e-12, 0, 3, 0, "resident")])
+def test_batched_parity_small(ctx, dtype, tol, M, nvec, block, path):
+    """Both device paths, block widths of the on-chip path (N, 2N, 4N values:
+    4/8/16 FP32, 2/4/8 FP64) with ragged last blocks, odd and even degrees
+    and the degenerate M = 0, 1."""
+    _say(f"batched small {dtype} M={M} nvec={nvec} block={block} path={path}")
     mats = small_set()
     lb, ub = bounds_of(mats, dtype)
     D = [dev(A, dtype) for A in mats]
-    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 500, precision=dtype, block=block, validate=True)
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 500, precision=dtype, block=block, validate=True,
+                                 path=path)
     for m, A in enumerate(mats):
         ref = oracle_mu(A, lb[m], ub[m], M, nvec, 500 + m, dtype)
         assert np.max(np.abs(mu[m] - ref)) < tol, m
         assert mu[m, 0] == 1.0
 
 
-def test_graph_replay_matches_direct_launch(ctx):
+@pytest.mark.parametrize("path", ["resident", "stream"])
+def test_graph_replay_matches_direct_launch(ctx, path):
     """Replays of the captured graph, with eager work and syncs between them,
     equal the directly launched sequence bitwise; changing the bounds between
     calls updates the replay's scalars."""
@@ -77,21 +86,48 @@ def test_graph_replay_matches_direct_launch(ctx):
     mats = small_set()
     lb, ub = bounds_of(mats, "f32")
     D = [dev(A, "f32") for A in mats]
-    direct = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 9, graph=False)
+    kw = dict(path=path)
+    direct = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 9, graph=False, **kw)
     for rep in range(3):
         x = torch.randn(1 << 20, device="cuda")
         (x * 2.0).sum().item()  # eager work on the caller's stream
-        got = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 9, graph=True)
+        got = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 9, graph=True, **kw)
         torch.cuda.synchronize()
         assert np.array_equal(got, direct), rep
     lb2, ub2 = lb - 0.5, ub + 0.25
-    got2 = kpm.kpm_moments_batched(ctx, D, lb2, ub2, 50, 8, 9, graph=True)
-    direct2 = kpm.kpm_moments_batched(ctx, D, lb2, ub2, 50, 8, 9, graph=False)
+    got2 = kpm.kpm_moments_batched(ctx, D, lb2, ub2, 50, 8, 9, graph=True, **kw)
+    direct2 = kpm.kpm_moments_batched(ctx, D, lb2, ub2, 50, 8, 9, graph=False, **kw)
     assert np.array_equal(got2, direct2)
     assert not np.array_equal(got2, direct)
-    got3 = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 10, graph=True)  # new seed, same graph
-    direct3 = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 10, graph=False)
+    got3 = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 10, graph=True, **kw)  # new seed, same graph
+    direct3 = kpm.kpm_moments_batched(ctx, D, lb, ub, 50, 8, 10, graph=False, **kw)
     assert np.array_equal(got3, direct3)
+
+
+def test_paths_agree_and_flags(ctx):
+    """The on-chip and streaming paths at the same probe block width compute
+    bitwise the same vectors and sum the dots in different orders: the
+    moments agree to rounding (1e-13 FP32 path, 1e-14 FP64).  The on-chip
+    path refuses matrices too large for it; the two path flags exclude each
+    other."""
+    mats = small_set()
+    for dtype, tol in (("f32", 1e-13), ("f64", 1e-14)):
+        lb, ub = bounds_of(mats, dtype)
+        D = [dev(A, dtype) for A in mats]
+        for block in ((4, 8, 16) if dtype == "f32" else (2, 4, 8)):
+            a = kpm.kpm_moments_batched(ctx, D, lb, ub, 61, 20, 31, precision=dtype, block=block, path="resident")
+            b = kpm.kpm_moments_batched(ctx, D, lb, ub, 61, 20, 31, precision=dtype, block=block, path="stream")
+            assert np.max(np.abs(a - b)) < tol, (dtype, block)
+    big = synth.laplacian2d_dirichlet(100)  # n = 10,000: 2 x 10,000 x 4 FP32 values exceed 160 KB
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_moments_batched(ctx, [dev(big, "f32")], [-0.1], [8.1], 10, 4, 1, path="resident")
+    assert e.value.status == -6
+    import ctypes
+    o = kpm._opts(10, 4, 1, "f32", 0, False, 0, kpm.KPM_FLAG_BATCH_STREAM | kpm.KPM_FLAG_BATCH_RESIDENT)
+    arr = (kpm.kpm_csr * 1)(dev(big, "f32").as_c())
+    lbv, ubv, mu = np.array([-0.1]), np.array([8.1]), np.zeros(11)
+    assert ctx.lib.kpm_moments_batched(ctx.handle, 1, arr, kpm._p(lbv), kpm._p(ubv), ctypes.byref(o), kpm._p(mu),
+                                       None) == -1
 
 
 def test_batched_matches_single_matrix_path(ctx):
@@ -164,21 +200,24 @@ def test_c3_full_size_sampled(ctx):
         assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
-def test_many_small_matrices_every_matrix(ctx, dtype, tol):
+@pytest.mark.parametrize("dtype,tol,block", [("f32", 1e-5, 64), ("f64", 1e-12, 64), ("f32", 1e-5, 0),
+                                             ("f64", 1e-12, 0)])
+def test_many_small_matrices_every_matrix(ctx, dtype, tol, block):
     """More (matrix, probe block) pairs than resident workgroups (3,000
-    random sparse matrices, n = 150..349, 64 probes each): the work table
-    then splits every pair over up to 16 workgroups, and each step launch
-    reduces the previous step's partials.  Every matrix against the oracle."""
-    _say(f"many small matrices {dtype}")
+    random sparse matrices, n = 150..349, 64 probes each).  Block 64: the
+    streaming path's work table then splits every pair over up to 16
+    workgroups, and each step launch reduces the previous step's partials.
+    Block 0: the on-chip path (16 FP32 / 8 FP64 probes per workgroup, 12,000
+    / 24,000 pairs).  Every matrix against the oracle."""
+    _say(f"many small matrices {dtype} block {block}")
     mats = [synth.random_sparse_symmetric(150 + (i * 37) % 200, 4.5, 50_000 + i) for i in range(3000)]
     D = [dev(A, dtype) for A in mats]
     lo_hi = [kpm.kpm_gershgorin(ctx, d) for d in D]
     lb = np.array([lo - 0.01 * (hi - lo) for lo, hi in lo_hi])
     ub = np.array([hi + 0.01 * (hi - lo) for lo, hi in lo_hi])
     M, nvec = 9, 64
-    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=64)
-    mu_direct = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=64, graph=False)
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=block)
+    mu_direct = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 7000, precision=dtype, block=block, graph=False)
     assert np.array_equal(mu, mu_direct)
     worst = 0.0
     for m, A in enumerate(mats):
@@ -191,12 +230,14 @@ def test_many_small_matrices_every_matrix(ctx, dtype, tol):
 def test_training_set_full_size_sampled(ctx):
     """The damping network's training family at full size in one batched
     call: 8,192 random sparse symmetric matrices (n = 2,048) and 1,024 2D
-    Anderson 32 x 64 matrices, degree 127, 256 probes each as 4 blocks of
-    64, FP32 (36,864 (matrix, probe block) pairs).  Bounds: 20-step Lanczos
-    with the same escape recovery as the uneven batch (random sparse
-    matrices often have an outlying extreme eigenvalue the start vector
-    barely sees).  The oracle checks matrices at both ends of each family
-    and a few recovered ones over all 256 probes."""
+    Anderson 32 x 64 matrices, degree 127, 256 probes each, FP32: on the
+    on-chip path (blocks of 8 probes, 294,912 (matrix, probe block) pairs,
+    one workgroup each) and on the streaming path (4 blocks of 64, 36,864
+    pairs).  Bounds: 20-step Lanczos with the same escape recovery as the
+    uneven batch (random sparse matrices often have an outlying extreme
+    eigenvalue the start vector barely sees).  The oracle checks matrices at
+    both ends of each family and a few recovered ones over all 256 probes;
+    the two paths agree to rounding on every matrix."""
     _say("training set: generating 9,216 matrices")
     mats = synth.damping_training_set()
     assert len(mats) == 9216 and all(A.n == 2048 for A in mats)
@@ -208,7 +249,7 @@ def test_training_set_full_size_sampled(ctx):
     recovered = []
     for attempt in range(3):
         _say(f"training set: batched moments, attempt {attempt}")
-        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, block=64, return_max_abs=True)
+        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, return_max_abs=True)
         bad = [m for m in range(len(D)) if not mx[m] <= 1 + 1e-4]
         if not bad:
             break
@@ -220,8 +261,12 @@ def test_training_set_full_size_sampled(ctx):
                 lo, hi = kpm.kpm_gershgorin(ctx, D[m])
                 lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
     assert not bad
-    mu2 = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, block=64)
+    mu2 = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004)
     assert np.array_equal(mu, mu2)
+    _say("training set: streaming path")
+    mu_s = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004, block=64)
+    _say(f"training set: paths differ by {np.max(np.abs(mu - mu_s)):.2e}")
+    assert np.max(np.abs(mu - mu_s)) < 1e-12
     assert mu.shape == (9216, 128)
     assert np.all(mu[:, 0] == 1.0) and np.all(np.abs(mu) <= 1 + 1e-6)
     for m in sorted({0, 1, 4095, 8191, 8192, 9215} | set(recovered[:4])):
@@ -251,3 +296,43 @@ def test_gershgorin_matches_oracle(ctx):
         lo, hi = kpm.kpm_gershgorin(ctx, dev(A, "f64"))
         rlo, rhi = oracle.gershgorin(A)
         assert abs(lo - rlo) < 1e-12 * max(1, abs(rlo)) and abs(hi - rhi) < 1e-12 * max(1, abs(rhi))
+
+
+def test_on_chip_plan_detects_changed_structure(ctx):
+    """The on-chip path lays each matrix out in slices whose widths are fixed
+    when the plan is built; values are re-read at every call.  A caller that
+    rewrites a matrix's structure in place (same addresses and sizes) gets
+    KPM_ERR_ARG once, and the next call rebuilds the plan and matches the
+    oracle."""
+    import torch
+    n = 96
+    A = synth.add_diagonal_disorder(synth.laplacian2d_dirichlet(8), 2.0, 5)  # n = 64
+    B = synth.random_sparse_symmetric(n, 1.0, 6)
+    # the same sizes: pad B's entry count to A2's with zeros on the diagonal block
+    A2 = synth.random_sparse_symmetric(n, 3.0, 7)
+    assert B.nnz < A2.nnz
+    Sb = B.to_scipy().tolil()
+    pairs = ((i, j) for i in range(n) for j in range(i + 1, n))
+    while Sb.nnz < A2.nnz:  # long first rows, kept symmetric (2 entries per new pair)
+        i, j = next(pairs)
+        if Sb[i, j] == 0:
+            Sb[i, j] = Sb[j, i] = 1e-3
+    Sb = Sb.tocsr()
+    Sb.sort_indices()
+    assert Sb.nnz == A2.nnz, (Sb.nnz, A2.nnz)
+    Bm = synth.CSR(n, Sb.indptr.astype(np.int32), Sb.indices.astype(np.int32), Sb.data.copy())
+    D = [dev(A, "f32"), dev(A2, "f32")]
+    lb0, ub0 = bounds_of([A, A2], "f32")
+    mu = kpm.kpm_moments_batched(ctx, D, lb0, ub0, 20, 8, 3, path="resident")
+    # rewrite matrix 1 in place: same n and nnz, a row 0 longer than any of A2's rows
+    D[1].row_ptr.copy_(torch.as_tensor(Bm.row_ptr, device="cuda"))
+    D[1].col_idx.copy_(torch.as_tensor(Bm.col_idx, device="cuda"))
+    D[1].val.copy_(torch.as_tensor(Bm.val.astype(np.float32), device="cuda"))
+    lb, ub = bounds_of([A, Bm], "f32")
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_moments_batched(ctx, D, lb, ub, 20, 8, 3, path="resident")
+    assert e.value.status == -1 and "structure" in e.value.message
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, 20, 8, 3, path="resident")
+    for m, X in enumerate([A, Bm]):
+        ref = oracle_mu(X, lb[m], ub[m], 20, 8, 3 + m, "f32")
+        assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
