@@ -171,9 +171,12 @@ __host__ __device__ constexpr size_t resident_lds_bytes(int n, int LD, int esz) 
 // (ties by index) and cut into slices of C; slice s stores its entries
 // slot-major, entry q of its l-th row at [slo[s] + q C + l] for q < W_s,
 // the slice's longest row, with that row's index in srow[s C + l] (-1 past
-// the last row).  Slots past a row's end hold the row itself with weight 0
-// (exact), as the streaming step pads its gather batches.  A wavefront's
-// load of one slot is then C consecutive pairs; ordering by length keeps
+// the last row); slots are stored in pairs, slots 2p and 2p + 1 of row l
+// at [slo[s] + p 2C + 2l + {0, 1}], the width rounded up to even.  Slots
+// past a row's end hold the row itself with weight 0 (exact), as the
+// streaming step pads its gather batches.  A wavefront's load of two slots
+// is then one 16-byte load per lane over 2C consecutive pairs (FP32
+// values); ordering by length keeps
 // each slice's rows about equally long, so few slots are padding; and each
 // row's entries keep their CSR order, so the FP32 row sums are those of the
 // streaming path (only the order in which a lane accumulates its rows' dot
@@ -209,7 +212,7 @@ __global__ void sell_fill_kernel(const SellMatDev* __restrict__ mats, int C, int
     if (s >= m.nsl) return;
     const int W = m.slw[s];
     const int r = m.srow[i];
-    CsrPair<TA>* e = static_cast<CsrPair<TA>*>(m.sell) + m.slo[s] + l;
+    CsrPair<TA>* e = static_cast<CsrPair<TA>*>(m.sell) + m.slo[s] + 2 * l;
     const TA* val = static_cast<const TA*>(m.val);
     int kb = 0, len = 0;
     if (r >= 0) {
@@ -217,7 +220,8 @@ __global__ void sell_fill_kernel(const SellMatDev* __restrict__ mats, int C, int
         len = m.rp[r + 1] - kb;
         if (len > W) bad[0] = 1;
     }
-    for (int q = 0; q < W; ++q) {
+    const int Wp = (W + 1) & ~1;
+    for (int q = 0; q < Wp; ++q) {
         CsrPair<TA> t;
         if (q < len) {
             t.c = m.ci[kb + q];
@@ -226,8 +230,75 @@ __global__ void sell_fill_kernel(const SellMatDev* __restrict__ mats, int C, int
             t.c = r >= 0 ? r : 0;
             t.v = (TA)0;
         }
-        e[(int64_t)q * C] = t;
+        e[(int64_t)(q >> 1) * 2 * C + (q & 1)] = t;
     }
+}
+
+// Sum of v over the lanes of the wavefront with the same lane % LPR (LPR =
+// 1, 2 or 4), returned in every such lane.  Within each row of 16 lanes by
+// DPP lane moves (quad permutations for the strides below 4, row rotations
+// by 4 and 8), then across rows by gfx950's row swaps: permlane16_swap of a
+// value with itself gives every lane the value of its even-row partner and
+// of its odd-row partner, permlane32_swap those of its lower-half and
+// upper-half partners, so one add per level (even + odd, lower + upper, the
+// same order in every lane).  All on the vector ALU: the LDS unit, which
+// the gathers keep busy, sees no shuffles.  A fixed pattern: bitwise
+// reproducible.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+__device__ __forceinline__ double from_halves(uint32_t lo, uint32_t hi) {
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | (uint64_t)lo);
+}
+__device__ __forceinline__ double sum_row_pairs(double v) {  // rows 2i + 2i+1
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+    return from_halves(lo[0], hi[0]) + from_halves(lo[1], hi[1]);
+}
+__device__ __forceinline__ double sum_halves(double v) {  // lanes l and l ^ 32
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+    return from_halves(lo[0], hi[0]) + from_halves(lo[1], hi[1]);
+}
+template <int LPR>
+__device__ __forceinline__ double wave_sum_strided(double v) {
+    static_assert(LPR == 1 || LPR == 2 || LPR == 4, "lane stride");
+    if (LPR == 1) v += dpp_move<0xB1>(v);  // quad_perm [1,0,3,2]: lane ^ 1
+    if (LPR <= 2) v += dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_move<0x124>(v);               // row_ror:4
+    v += dpp_move<0x128>(v);               // row_ror:8
+    return sum_halves(sum_row_pairs(v));
+}
+
+// Two consecutive slots of the sliced layout: one 16-byte load for FP32
+// values, two for FP64.
+template <typename TA>
+__device__ __forceinline__ void load_slot_pair(const __attribute__((address_space(1))) CsrPair<TA>* p, int& j0,
+                                               TA& a0, int& j1, TA& a1);
+template <>
+__device__ __forceinline__ void load_slot_pair<float>(const __attribute__((address_space(1))) CsrPair<float>* p,
+                                                      int& j0, float& a0, int& j1, float& a1) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) i4* gi4;
+    const i4 t = *reinterpret_cast<gi4>(p);
+    j0 = t[0];
+    a0 = __int_as_float(t[1]);
+    j1 = t[2];
+    a1 = __int_as_float(t[3]);
+}
+template <>
+__device__ __forceinline__ void load_slot_pair<double>(const __attribute__((address_space(1))) CsrPair<double>* p,
+                                                       int& j0, double& a0, int& j1, double& a1) {
+    j0 = p[0].c;
+    a0 = p[0].v;
+    j1 = p[1].c;
+    a1 = p[1].v;
 }
 
 // One workgroup per (matrix, probe block) pair for all K steps (see the
@@ -276,16 +347,19 @@ __global__ __launch_bounds__(kResThreads) void resident_kernel(const BatchMvDev*
     // G slots q0 .. q0 + G - 1 of this lane's row in slice s (slots at or past
     // the slice width W, which is the same for the whole wavefront, are not
     // loaded: the row itself with weight 0).
+    static_assert(G % 2 == 0, "slots are loaded in pairs");
     auto load_batch = [&](int64_t base, int W, int q0, int row, int (&j)[G], TV (&a)[G]) {
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
+        for (int i = 0; i < G; i += 2) {
             if (q0 + i < W) {
-                const int64_t at = base + (int64_t)(q0 + i) * RPW + rw;
-                j[i] = sell[at].c;
-                a[i] = (TV)sell[at].v;
+                const int64_t at = base + (int64_t)((q0 + i) >> 1) * 2 * RPW + 2 * rw;
+                TA v0, v1;
+                load_slot_pair<TA>(sell + at, j[i], v0, j[i + 1], v1);
+                a[i] = (TV)v0;
+                a[i + 1] = (TV)v1;
             } else {
-                j[i] = row;
-                a[i] = (TV)0;
+                j[i] = j[i + 1] = row;
+                a[i] = a[i + 1] = (TV)0;
             }
         }
     };
@@ -363,14 +437,12 @@ __global__ __launch_bounds__(kResThreads) void resident_kernel(const BatchMvDev*
                 ss[e] = fma(o, o, ss[e]);
             }
         }
-        // rows of the wavefront -> one value per column, fixed butterfly
+        // rows of the wavefront -> one value per column
 #pragma unroll
-        for (int off = LPR; off < 64; off <<= 1)
-#pragma unroll
-            for (int e = 0; e < N; ++e) {
-                sx[e] += __shfl_xor(sx[e], off, 64);
-                ss[e] += __shfl_xor(ss[e], off, 64);
-            }
+        for (int e = 0; e < N; ++e) {
+            sx[e] = wave_sum_strided<LPR>(sx[e]);
+            ss[e] = wave_sum_strided<LPR>(ss[e]);
+        }
         double* rk = red + (size_t)(k & 1) * kResWaves * 2 * LD;
         if (rw == 0) {
 #pragma unroll
@@ -873,7 +945,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
                 const int64_t g = slice_base[m] + sl;
                 w[g] = L[out[sl * C]];
                 so[g] = slots;
-                slots += (int64_t)w[g] * C;
+                slots += (int64_t)((w[g] + 1) & ~1) * C;
             }
         }
         const size_t pair_bytes = P.val_f64 ? 16 : 8;
