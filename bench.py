@@ -12,6 +12,11 @@ disorder, plus 2 random N(0, 0.1^2) long-range pairs per row, mirrored
 (n = 2,097,152, nnz ~ 23.07M); degree M = 1000, 256 Rademacher probes as 4
 blocks of 64, FP32 values and vectors with FP64 dot accumulation.  The 64^3
 Anderson workload (degree 256, 64 probes) is reported as an extra leg.
+Both run with the library's locality renumbering (KPM_FLAG_LOCALITY: the
+grid matrix renumbered along its Morton curve inside the library, probes at
+the original indices, so the same moments; the order is built once per
+matrix in the warm-up, the per-call value gather is timed); the same steps
+in the caller's numbering are reported as `plain_order`.
 
 Metric: nnz * M * nvec / second (Chebyshev degree-moments per second).
 The roofline object reports the fused recurrence step kernel: algorithmic
@@ -44,9 +49,11 @@ HBM_PEAK_GBS = 8000.0
 STEP_SOURCES = ("paper_1308_5467_amd/csrc/kpm_step.h", "paper_1308_5467_amd/csrc/kpm_moments.hip")
 
 WORKLOADS = {
-    # name: (matrix config, degree, probes, block, probe seed, Lanczos seed)
-    "anderson3d_128^3_W16_longrange2": ("c5", 1000, 256, 64, 2005, 3005),
-    "anderson3d_64^3_periodic_W16": ("c2", 256, 64, 64, 2002, 3002),
+    # name: (matrix config, degree, probes, block, probe seed, Lanczos seed,
+    #        KPM_FLAG_LOCALITY: the library renumbers the grid matrix along its
+    #        Morton curve, probes at the original indices -- the same moments)
+    "anderson3d_128^3_W16_longrange2": ("c5", 1000, 256, 64, 2005, 3005, True),
+    "anderson3d_64^3_periodic_W16": ("c2", 256, 64, 64, 2002, 3002, True),
 }
 HEADLINE = "anderson3d_128^3_W16_longrange2"
 
@@ -98,6 +105,8 @@ def parse():
     ap.add_argument("--nvec", type=int, default=0, help="probes (0: the workload's)")
     ap.add_argument("--block", type=int, default=0, help="probe block width (0: the workload's)")
     ap.add_argument("--rows-per-block", type=int, default=0)
+    ap.add_argument("--locality", default="auto", choices=["auto", "on", "off"],
+                    help="KPM_FLAG_LOCALITY for the timed steps (auto: the workload's setting)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra legs (64^3 workload, equal-accuracy comparisons, batched sets, ...)")
@@ -125,15 +134,15 @@ def parse():
 
 
 def load_workload(kpm, synth, name, precision="f32"):
-    cfg, M, nvec, block, seed, lz_seed = WORKLOADS[name]
+    cfg, M, nvec, block, seed, lz_seed, locality = WORKLOADS[name]
     A = synth.config_matrix(cfg)
     vals = A.val.astype(np.float32) if precision == "f32" else A.val
     D = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, vals, precision)
-    return A, D, dict(M=M, nvec=nvec, block=block, seed=seed, lz_seed=lz_seed)
+    return A, D, dict(M=M, nvec=nvec, block=block, seed=seed, lz_seed=lz_seed, locality=locality)
 
 
 def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, warmup, precision="f32",
-                   rows_per_block=0, separate=True):
+                   rows_per_block=0, separate=True, locality=False):
     """Whole-path steps (bounds -> moments -> Jackson -> density) on one
     workload, the step kernel against the HBM roofline, and the same four
     steps as separate calls."""
@@ -146,13 +155,13 @@ def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, w
     def step():
         phi, mu, _, _ = kpm.kpm_dos_pipeline(ctx, D, M, nvec, seed, x, precision=precision, block=block,
                                              damping=kpm.KPM_DAMP_JACKSON, lanczos_steps=20, lanczos_seed=lz_seed,
-                                             margin=0.01, rows_per_block=rows_per_block)
+                                             margin=0.01, rows_per_block=rows_per_block, locality=locality)
         return mu, phi
 
     def step_separate():
         lb, ub = kpm.kpm_bounds(ctx, D, 20, lz_seed, 0.01)
         mu = kpm.kpm_moments(ctx, D, lb, ub, M, nvec, seed, precision=precision, block=block,
-                             validate=False, rows_per_block=rows_per_block)
+                             validate=False, rows_per_block=rows_per_block, locality=locality)
         g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
         phi = kpm.kpm_dos(ctx, mu, g, lb, ub, x)
         return mu, phi
@@ -205,6 +214,7 @@ def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, w
     return {
         "value": units / (ms_per_step / 1000.0), "ms_per_step": ms_per_step,
         "config": {"workload": name, "n": A.n, "nnz": A.nnz, "M": M, "nvec": nvec, "block": b,
+                   "locality_renumbering": bool(locality),
                    "vector_blocks": nblocks_vec, "precision": precision, "dot_accumulation": "f64",
                    "lanczos_steps": 20, "dos_points": 200, "parallelism": "single-gpu"},
         "roofline": roof,
@@ -216,6 +226,16 @@ def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, w
                                                 / (ms_per_step * 1e-3) / 1e9, 1),
         "lb_ub": [lb, ub],
     }
+
+
+def plain_order_leg(kpm, ctx, A, D, name, w, steps, warmup, precision="f32"):
+    """The same whole-path step without KPM_FLAG_LOCALITY (the caller's row
+    numbering kept), for comparison."""
+    leg = throughput_leg(kpm, ctx, A, D, name, w["M"], w["nvec"], w["block"], w["seed"], w["lz_seed"], steps,
+                         warmup, precision, separate=False, locality=False)
+    r = leg["roofline"]
+    return {"value": leg["value"], "ms_per_step": leg["ms_per_step"], "avg_launch_us": r["avg_launch_us"],
+            "frac": r["frac"], "steps": steps}
 
 
 def cpu_baseline_leg(A, lb, ub, M, nvec, seed, args, full_M):
@@ -279,8 +299,9 @@ def main():
     M = args.M or w["M"]
     nvec = args.nvec or w["nvec"]
     block = args.block or w["block"]
+    locality = {"on": True, "off": False, "auto": w["locality"]}[args.locality]
     head = throughput_leg(kpm, ctx, A, D, args.workload, M, nvec, block, w["seed"], w["lz_seed"], args.steps,
-                          args.warmup, args.precision, args.rows_per_block)
+                          args.warmup, args.precision, args.rows_per_block, locality=locality)
     out = {
         "metric": "Chebyshev moment nnz*deg*vec/s",
         "value": head["value"],
@@ -311,6 +332,9 @@ def main():
         out["roofline"]["frac_uncached_gather_model"] = round(
             unc / (out["roofline"]["avg_launch_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     lb, ub = head["lb_ub"]
+    if locality and not args.no_extras:
+        out["plain_order"] = plain_order_leg(kpm, ctx, A, D, args.workload, dict(w, M=M, nvec=nvec, block=block),
+                                             3, 1, args.precision)
 
     if not args.no_extras:
         x = np.linspace(-10.0, 22.0, 200)
@@ -320,9 +344,12 @@ def main():
             torch.cuda.empty_cache()
         A2, D2, w2 = load_workload(kpm, synth, "anderson3d_64^3_periodic_W16")
         leg = throughput_leg(kpm, ctx, A2, D2, "anderson3d_64^3_periodic_W16", w2["M"], w2["nvec"], w2["block"],
-                             w2["seed"], w2["lz_seed"], 20, 3)
+                             w2["seed"], w2["lz_seed"], 20, 3, locality=w2["locality"])
         out["anderson3d_64"] = {k: leg[k] for k in ("value", "ms_per_step", "config", "roofline",
                                                      "breakdown_ms_per_step", "ms_per_step_separate_calls")}
+        if w2["locality"]:
+            out["anderson3d_64"]["plain_order"] = plain_order_leg(kpm, ctx, A2, D2, "anderson3d_64^3_periodic_W16",
+                                                                  w2, 10, 2)
         out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A2, D2, x)
         out["batched_uneven_48"] = batched_leg(kpm, ctx, synth, tune=not args.no_autotune)
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A2, D2, x)

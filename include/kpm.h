@@ -102,6 +102,17 @@ enum {
     KPM_FLAG_BATCH_RESIDENT = 64, /* kpm_moments_batched: the on-chip path
                               (KPM_ERR_UNSUPPORTED when a matrix is too
                               large for it)                                 */
+    KPM_FLAG_LOCALITY = 128,      /* kpm_moments, kpm_legendre_moments,
+                              kpm_dos_pipeline: when the matrix comes from a
+                              2D or 3D grid numbered lexicographically (found
+                              by kpm_locality_order), run on it renumbered
+                              along the grid's Morton curve, probes at the
+                              original indices: the same moments up to
+                              rounding, plane-apart neighbours close in the
+                              probe block.  The renumbered structure is
+                              cached per matrix address in the context
+                              (values are re-read at every call; the
+                              structure at an address must not change)     */
     KPM_FLAG_LEGENDRE_RECURRENCE = 16 /* kpm_legendre_moments: run the
                               Legendre three-term recurrence of Algorithm DGL
                               (M sparse products per block) instead of
@@ -207,6 +218,21 @@ kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, doubl
 #define KPM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 kpm_status kpm_moments_noalloc(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub,
                                const kpm_moment_opts* opts, double* mu, double* mu_per_vec);
+
+/*
+ * kpm_locality_order -- host-only: the row order KPM_FLAG_LOCALITY uses.
+ * Finds a 2D or 3D grid behind a CSR matrix numbered lexicographically
+ * (x fastest) from the offsets (column - row) of its entries above the
+ * diagonal: the offsets occurring in at least 40 % of (a sample of at most
+ * 2^18) rows must be {1, nx} (2D, n = nx ny) or {1, nx, nx ny} (3D, n = nx
+ * ny nz).  perm (host [n]) receives the rows in the Morton (Z-order) of
+ * their grid coordinates, perm[new] = old; dims (host [3]) the grid (nx,
+ * ny, nz; nz = 1 in 2D) or zeros with perm the identity when no grid is
+ * found.  KPM_ERR_ARG for bad sizes, NULL arrays or row_ptr[0] != 0,
+ * row_ptr[n] != nnz.
+ */
+kpm_status kpm_locality_order(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                              int32_t* perm, int32_t* dims);
 
 /*
  * kpm_autotune -- choose the device geometry of kpm_moments for A by

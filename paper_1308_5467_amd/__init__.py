@@ -33,7 +33,7 @@ STATUS = {0: "KPM_OK", -1: "KPM_ERR_ARG", -2: "KPM_ERR_ALLOC", -3: "KPM_ERR_HIP"
 # Every symbol include/kpm.h declares.
 EXPORTS = [
     "kpm_create", "kpm_destroy", "kpm_set_stream", "kpm_last_error", "kpm_bounds", "kpm_moments",
-    "kpm_moments_noalloc",
+    "kpm_moments_noalloc", "kpm_locality_order",
     "kpm_moments_batched", "kpm_damping_factors", "kpm_dos", "kpm_dos_bins", "kpm_rademacher",
     "kpm_slq", "kpm_slq_dos", "kpm_haydock_dos", "kpm_tridiag_eig", "kpm_legendre_moments", "kpm_dgl_dos",
     "kpm_legendre_dos", "kpm_functional", "kpm_functional_nodes", "kpm_heat_capacity", "kpm_slq_heat_capacity", "kpm_dos_pipeline", "kpm_autotune", "kpm_autotune_batched",
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_legendre_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_functional": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_functional_nodes": ([I32, D, D, P], I32),
+        "kpm_locality_order": ([I64, I64, P, P, P, P], I32),
         "kpm_dos_pipeline": ([P, P, I32, U64, D, P, I32, P, I32, P, P, P, P], I32),
         "kpm_heat_capacity": ([P, P, P, I32, D, D, P, I32, I32, P], I32),
         "kpm_slq_heat_capacity": ([P, P, P, I32, I32, P, I32, P], I32),
@@ -251,6 +252,7 @@ def kpm_bounds(ctx: Context, A, steps: int = 20, seed: int = 0, margin: float = 
 KPM_FLAG_NO_GRAPH, KPM_FLAG_GATHER4, KPM_FLAG_GATHER8, KPM_FLAG_GATHER7 = 1, 2, 4, 8
 KPM_FLAG_LEGENDRE_RECURRENCE = 16
 KPM_FLAG_BATCH_STREAM, KPM_FLAG_BATCH_RESIDENT = 32, 64
+KPM_FLAG_LOCALITY = 128
 
 
 def _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags=0) -> kpm_moment_opts:
@@ -267,9 +269,11 @@ def _gather_flags(gather: int) -> int:
 
 def kpm_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
                 precision="f32", block: int = 0, validate: bool = True, per_vector: bool = False,
-                rows_per_block: int = 0, gather: int = 0):
-    """Normalised moments mu[0..M]; with per_vector=True also [nvec, M+1] per-probe moments."""
-    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, _gather_flags(gather))
+                rows_per_block: int = 0, gather: int = 0, locality: bool = False):
+    """Normalised moments mu[0..M]; with per_vector=True also [nvec, M+1] per-probe moments.
+    locality=True: KPM_FLAG_LOCALITY (grid matrices renumbered along a Morton curve inside the library)."""
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block,
+              _gather_flags(gather) | (KPM_FLAG_LOCALITY if locality else 0))
     mu = np.zeros(M + 1)
     pv = np.zeros((nvec, M + 1)) if per_vector else None
     c = A.as_c()
@@ -302,11 +306,11 @@ def kpm_moments_noalloc(ctx: Context, A, lb: float, ub: float, M: int, nvec: int
 
 def kpm_legendre_moments(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int,
                          precision="f32", block: int = 0, validate: bool = True, per_vector: bool = False,
-                         rows_per_block: int = 0, recurrence: bool = False):
+                         rows_per_block: int = 0, recurrence: bool = False, locality: bool = False):
     """Normalised Legendre moments mu[0..M] (tr L_k(B)/n estimates); with
     recurrence=True by the Legendre three-term recurrence in the fused step."""
     o = _opts(M, nvec, seed, precision, block, validate, rows_per_block,
-              KPM_FLAG_LEGENDRE_RECURRENCE if recurrence else 0)
+              (KPM_FLAG_LEGENDRE_RECURRENCE if recurrence else 0) | (KPM_FLAG_LOCALITY if locality else 0))
     mu = np.zeros(M + 1)
     pv = np.zeros((nvec, M + 1)) if per_vector else None
     c = A.as_c()
@@ -342,9 +346,11 @@ def kpm_legendre_dos(ctx: Context, mu, lb: float, ub: float, x, g=None) -> np.nd
 
 def kpm_dos_pipeline(ctx: Context, A, M: int, nvec: int, seed: int, x, precision="f32", block: int = 0,
                      damping: int = KPM_DAMP_JACKSON, lanczos_steps: int = 20, lanczos_seed: int = 3002,
-                     margin: float = 0.01, validate: bool = False, rows_per_block: int = 0):
-    """Bounds, moments, damping and density in one call: (phi, mu, lb, ub)."""
-    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block)
+                     margin: float = 0.01, validate: bool = False, rows_per_block: int = 0,
+                     locality: bool = False):
+    """Bounds, moments, damping and density in one call: (phi, mu, lb, ub).
+    locality=True: KPM_FLAG_LOCALITY."""
+    o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, KPM_FLAG_LOCALITY if locality else 0)
     x = _f64(x)
     phi = np.zeros(x.size)
     mu = np.zeros(M + 1)
@@ -355,6 +361,20 @@ def kpm_dos_pipeline(ctx: Context, A, M: int, nvec: int, seed: int, x, precision
                                        ctypes.byref(o), damping, _p(x), x.size, _p(phi), _p(mu), ctypes.byref(lb),
                                        ctypes.byref(ub)))
     return phi, mu, lb.value, ub.value
+
+
+def kpm_locality_order(row_ptr, col_idx):
+    """(perm, dims): the grid found behind a CSR matrix and its rows in Morton
+    order (perm[new] = old), or the identity and zeros (host only)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = rp.size - 1
+    perm = np.zeros(max(n, 0), dtype=np.int32)
+    dims = np.zeros(3, dtype=np.int32)
+    st = load_library().kpm_locality_order(n, ci.size, _p(rp), _p(ci), _p(perm), _p(dims))
+    if st != 0:
+        raise KpmError(st, "kpm_locality_order: bad argument")
+    return perm, tuple(int(d) for d in dims)
 
 
 def kpm_functional_nodes(Q: int, lb: float, ub: float) -> np.ndarray:

@@ -211,6 +211,7 @@ extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
     kpm_batch_free(ctx);
+    kpm_locality_free(ctx);
     for (auto& kv : ctx->bufs)
         if (kv.second.p) hipFree(kv.second.p);
     if (ctx->mlp_params.p) hipFree(ctx->mlp_params.p);
@@ -450,6 +451,19 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
     kpm_status st = kpm_prepare_csr(ctx, Ain, o->precision, &A, "");
     if (st != KPM_OK) return st;
     if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
+    // KPM_FLAG_LOCALITY: the same moments on the matrix renumbered along its
+    // grid's Morton curve, probes generated at the original row indices
+    const int32_t* rows = nullptr;
+    if (o->flags & KPM_FLAG_LOCALITY) {
+        if (legendre && (o->flags & KPM_FLAG_LEGENDRE_RECURRENCE))
+            return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "KPM_FLAG_LOCALITY with the Legendre recurrence");
+        // a host matrix lives in reused workspace: its cached structure is
+        // not trusted across calls
+        if (!Ain->on_device) kpm_locality_free(ctx);
+        CsrDev R;
+        if ((st = kpm_locality_view(ctx, A, &R, &rows)) != KPM_OK) return st;
+        A = R;
+    }
 
     const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
     const double alpha = 2.0 / d, beta = -2.0 * c / d;
@@ -501,7 +515,7 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
         const int gridb = ncols == b ? grid : cheb_step_grid(A, o->precision, gb);
         const int64_t vec0 = (int64_t)blk * b;
         if (!(blk == 0 && block0_filled))
-            KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0));
+            KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, vec0, ncols, gb.ld, A.n, o->precision, 1, X0, rows));
         const int swb = (gb.ld + 31) / 32;
         if (leg_rec)
             KPM_HIP(ctx, launch_sign_bits(ctx->stream, o->seed, vec0, ncols, A.n, swb, (uint32_t*)sgn));
@@ -818,10 +832,19 @@ extern "C" kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lancz
         const int b = o->block > 0 ? std::min(o->block, o->nvec) : default_block(o->nvec, o->precision);
         const BlockGeom g = make_geom(A->n, b, o->precision, o->rows_per_block);
         const int esz = o->precision == KPM_FP64 ? 8 : 4;
+        // with KPM_FLAG_LOCALITY the block is that of the renumbered matrix
+        const int32_t* rows = nullptr;
+        if (o->flags & KPM_FLAG_LOCALITY) {
+            if (!A->on_device) return KPM_OK;  // moments_impl fills it
+            CsrDev D, R;
+            kpm_status s1 = kpm_prepare_csr(ctx, A, o->precision, &D, "");
+            if (s1 != KPM_OK) return KPM_OK;  // moments_impl reports it
+            if ((s1 = kpm_locality_view(ctx, D, &R, &rows)) != KPM_OK) return s1;
+        }
         void* X0;
         kpm_status s2 = kpm_ws(ctx, "X0", (size_t)A->n * g.ld * esz, &X0);
         if (s2 != KPM_OK) return s2;
-        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A->n, o->precision, 1, X0));
+        KPM_HIP(ctx, launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A->n, o->precision, 1, X0, rows));
         prefilled = true;
         return KPM_OK;
     };

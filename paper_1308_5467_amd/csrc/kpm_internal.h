@@ -41,8 +41,10 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
 int kpm_default_block(int nvec, int precision);
 
 // ---------------------------------------------------------------- moments
+// rows (nullable): row i of the block takes entry rows[i] of each probe
+// (a renumbered matrix's probes at the original indices).
 hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
-                             int64_t n, int precision, int zero_pad, void* out);
+                             int64_t n, int precision, int zero_pad, void* out, const int32_t* rows = nullptr);
 // Workgroups every step launch of this geometry uses (= partial rows per step).
 int cheb_step_grid(const CsrDev& A, int precision, const BlockGeom& g);
 // Legendre moments from Chebyshev moments: a[0..M] connection weights
@@ -114,7 +116,8 @@ struct kpm_prof_entry {
     double total_ms = 0.0;
 };
 
-struct kpm_batch_state;  // batched-moments plan and captured graph (kpm_batched.hip)
+struct kpm_batch_state;     // batched-moments plan and captured graph (kpm_batched.hip)
+struct kpm_locality_state;  // renumbered structure of the last matrix (kpm_locality.hip)
 
 struct kpm_ctx {
     int device = 0;
@@ -133,6 +136,7 @@ struct kpm_ctx {
     float mlp_blur_sigma = -1.0f;
     const void* mlp_blur_buf = nullptr;
     kpm_batch_state* batch = nullptr;
+    kpm_locality_state* loc = nullptr;
     // profiling
     bool prof = false;
     std::map<std::string, kpm_prof_entry> prof_map;
@@ -143,6 +147,11 @@ struct kpm_ctx {
 kpm_status kpm_prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, kpm::CsrDev* out, const char* tag);
 kpm_status kpm_validate_csr(kpm_ctx* ctx, const kpm::CsrDev& D);
 void kpm_batch_free(kpm_ctx* ctx);
+// KPM_FLAG_LOCALITY: the matrix renumbered along a Morton curve of its grid
+// when kpm_locality_order finds one (*out = the renumbered view, *orig = the
+// original index of each of its rows), else *out = A and *orig = NULL.
+kpm_status kpm_locality_view(kpm_ctx* ctx, const kpm::CsrDev& A, kpm::CsrDev* out, const int32_t** orig);
+void kpm_locality_free(kpm_ctx* ctx);
 
 // Learned damping (damping network on the device); host mu/g arrays.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g);

@@ -1,0 +1,205 @@
+// Locality renumbering of structured-grid matrices for the single-matrix
+// moment path (KPM_FLAG_LOCALITY).
+//
+// A matrix from a d-dimensional grid numbered lexicographically (x fastest)
+// has its off-diagonal entries on a few dominant column offsets, 1, nx and
+// nx * ny.  With that numbering the neighbours one plane apart (nx * ny rows
+// later) are far in the probe block: on a 128^3 grid with 64 FP32 probes a
+// plane is 4 MB, the size of an XCD's L2, so every plane-apart gather
+// misses it.  Renumbering the rows along a Morton (Z-order) curve of the
+// grid coordinates keeps all neighbours of a row within a small block of
+// rows.  The moments do not depend on the numbering: with P the
+// permutation, v^T T_k(A) v = (P v)^T T_k(P A P^T) (P v), and the probes of
+// the renumbered matrix are generated at the original row indices, so the
+// same probes enter and the per-probe moments agree up to rounding.
+//
+// kpm_locality_order finds the grid from the offsets of the entries (the
+// two or three offsets that each occur in at least 40 % of the rows, the
+// smallest being 1) and returns the permutation; random long-range entries
+// have offsets that repeat rarely and do not disturb it.  The context caches
+// the renumbered structure per matrix (row offsets, columns, the source
+// index of each entry, the original index of each row) and gathers the
+// values at every call, so values may change between calls; the structure
+// at a given address may not.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <unordered_map>
+#include <vector>
+
+#include "kpm_internal.h"
+
+using namespace kpm;
+
+namespace {
+
+// Interleave the bits of x, y, z (z most significant of each triple).
+uint64_t morton3(uint64_t x, uint64_t y, uint64_t z) {
+    uint64_t key = 0;
+    for (int b = 0; b < 21; ++b)
+        key |= ((x >> b) & 1ull) << (3 * b) | ((y >> b) & 1ull) << (3 * b + 1) | ((z >> b) & 1ull) << (3 * b + 2);
+    return key;
+}
+
+template <typename T>
+__global__ void gather_values_kernel(const T* __restrict__ src_val, const int32_t* __restrict__ src,
+                                     int64_t nnz, T* __restrict__ out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = src_val[src[k]];
+}
+
+}  // namespace
+
+extern "C" kpm_status kpm_locality_order(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                                         int32_t* perm, int32_t* dims) {
+    if (n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx) || !perm || !dims)
+        return KPM_ERR_ARG;
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return KPM_ERR_ARG;
+    dims[0] = dims[1] = dims[2] = 0;
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    // offsets of the entries above the diagonal, over a sample of at most
+    // 2^18 evenly spaced rows
+    const int64_t step = std::max<int64_t>(1, n >> 18);
+    std::unordered_map<int64_t, int64_t> count;
+    int64_t rows = 0;
+    for (int64_t i = 0; i < n; i += step, ++rows) {
+        const int32_t kb = row_ptr[i], ke = row_ptr[i + 1];
+        if (kb > ke || kb < 0 || ke > nnz) return KPM_ERR_ARG;
+        for (int32_t k = kb; k < ke; ++k)
+            if (col_idx[k] > i) ++count[col_idx[k] - i];
+    }
+    std::vector<int64_t> off;
+    for (const auto& kv : count)
+        if (kv.second * 5 >= rows * 2) off.push_back(kv.first);
+    std::sort(off.begin(), off.end());
+    int64_t nx = 0, ny = 1, nz = 1;
+    if (off.size() == 2 && off[0] == 1 && n % off[1] == 0) {
+        nx = off[1];
+        ny = n / nx;
+    } else if (off.size() == 3 && off[0] == 1 && off[2] % off[1] == 0 && n % off[2] == 0) {
+        nx = off[1];
+        ny = off[2] / off[1];
+        nz = n / off[2];
+    } else {
+        return KPM_OK;  // no grid found: the identity
+    }
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+        key[(size_t)i] = {morton3((uint64_t)x, (uint64_t)y, (uint64_t)z), (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t r = 0; r < n; ++r) perm[r] = key[(size_t)r].second;
+    dims[0] = (int32_t)nx;
+    dims[1] = (int32_t)ny;
+    dims[2] = (int32_t)nz;
+    return KPM_OK;
+}
+
+struct kpm_locality_state {
+    const int32_t* rp = nullptr;  // the matrix the plan belongs to
+    const int32_t* ci = nullptr;
+    int64_t n = 0, nnz = 0;
+    bool structured = false;
+    void* mem = nullptr;  // rp2 | ci2 | src | orig | val2
+    int32_t *rp2 = nullptr, *ci2 = nullptr, *src = nullptr, *orig = nullptr;
+    void* val2 = nullptr;
+};
+
+void kpm_locality_free(kpm_ctx* ctx) {
+    if (!ctx->loc) return;
+    if (ctx->loc->mem) hipFree(ctx->loc->mem);
+    delete ctx->loc;
+    ctx->loc = nullptr;
+}
+
+kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const int32_t** orig) {
+    *out = A;
+    *orig = nullptr;
+    kpm_locality_state*& L = ctx->loc;
+    if (!L || L->rp != A.rp || L->ci != A.ci || L->n != A.n || L->nnz != A.nnz) {
+        KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        kpm_locality_free(ctx);
+        L = new kpm_locality_state();
+        L->rp = A.rp;
+        L->ci = A.ci;
+        L->n = A.n;
+        L->nnz = A.nnz;
+        std::vector<int32_t> rp((size_t)A.n + 1), ci((size_t)A.nnz), perm((size_t)A.n);
+        KPM_HIP(ctx, hipMemcpyAsync(rp.data(), A.rp, rp.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        if (A.nnz > 0) KPM_HIP(ctx, hipMemcpyAsync(ci.data(), A.ci, ci.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+        KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        int32_t dims[3];
+        kpm_status st = kpm_locality_order(A.n, A.nnz, rp.data(), ci.data(), perm.data(), dims);
+        if (st != KPM_OK) {
+            kpm_locality_free(ctx);
+            return kpm_fail(ctx, st, "locality renumbering: malformed row offsets");
+        }
+        L->structured = dims[0] > 0;
+        if (!L->structured) return KPM_OK;
+        // the renumbered structure: row r is row perm[r] of A, its columns
+        // renumbered and sorted, src[k] the entry of A it came from
+        std::vector<int32_t> inv((size_t)A.n), rp2((size_t)A.n + 1), ci2((size_t)A.nnz), src((size_t)A.nnz);
+        for (int64_t r = 0; r < A.n; ++r) inv[(size_t)perm[(size_t)r]] = (int32_t)r;
+        std::vector<std::pair<int32_t, int32_t>> row;
+        rp2[0] = 0;
+        for (int64_t r = 0; r < A.n; ++r) {
+            const int32_t o = perm[(size_t)r];
+            row.clear();
+            for (int32_t k = rp[(size_t)o]; k < rp[(size_t)o + 1]; ++k) row.push_back({inv[(size_t)ci[(size_t)k]], k});
+            std::sort(row.begin(), row.end());
+            int32_t at = rp2[(size_t)r];
+            for (const auto& e : row) {
+                ci2[(size_t)at] = e.first;
+                src[(size_t)at] = e.second;
+                ++at;
+            }
+            rp2[(size_t)r + 1] = at;
+        }
+        const size_t vsz = A.val_f64 ? 8 : 4;
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t b_rp = al((size_t)(A.n + 1) * 4), b_ci = al((size_t)A.nnz * 4 + 4), b_or = al((size_t)A.n * 4);
+        const size_t total = b_rp + 2 * b_ci + b_or + al((size_t)A.nnz * vsz + vsz);
+        if (hipMalloc(&L->mem, total) != hipSuccess) {
+            L->mem = nullptr;
+            kpm_locality_free(ctx);
+            return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the renumbered matrix failed");
+        }
+        char* p = static_cast<char*>(L->mem);
+        L->rp2 = reinterpret_cast<int32_t*>(p);
+        L->ci2 = reinterpret_cast<int32_t*>(p + b_rp);
+        L->src = reinterpret_cast<int32_t*>(p + b_rp + b_ci);
+        L->orig = reinterpret_cast<int32_t*>(p + b_rp + 2 * b_ci);
+        L->val2 = p + b_rp + 2 * b_ci + b_or;
+        KPM_HIP(ctx, hipMemcpyAsync(L->rp2, rp2.data(), rp2.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        if (A.nnz > 0) {
+            KPM_HIP(ctx, hipMemcpyAsync(L->ci2, ci2.data(), ci2.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+            KPM_HIP(ctx, hipMemcpyAsync(L->src, src.data(), src.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        }
+        KPM_HIP(ctx, hipMemcpyAsync(L->orig, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+        const hipError_t e = hipStreamSynchronize(ctx->stream);  // the host arrays go out of scope
+        if (e != hipSuccess) {
+            kpm_locality_free(ctx);
+            return kpm_hip_fail(ctx, e, "renumbered matrix upload");
+        }
+    }
+    if (!L->structured) return KPM_OK;
+    // the current values, in the renumbered order
+    if (A.nnz > 0) {
+        const int64_t blocks = std::min<int64_t>(8192, (A.nnz + 255) / 256);
+        if (A.val_f64)
+            gather_values_kernel<double><<<(int)blocks, 256, 0, ctx->stream>>>(
+                static_cast<const double*>(A.val), L->src, A.nnz, static_cast<double*>(L->val2));
+        else
+            gather_values_kernel<float><<<(int)blocks, 256, 0, ctx->stream>>>(
+                static_cast<const float*>(A.val), L->src, A.nnz, static_cast<float*>(L->val2));
+        KPM_HIP(ctx, hipGetLastError());
+    }
+    out->rp = L->rp2;
+    out->ci = L->ci2;
+    out->val = L->val2;
+    *orig = L->orig;
+    return KPM_OK;
+}

@@ -72,13 +72,16 @@ BlockGeom make_geom(int64_t n, int ncols, int precision, int rows_per_block_hint
 // no 64-bit division is needed per element.
 template <typename T>
 __global__ __launch_bounds__(256) void rademacher_fill_kernel(uint64_t seed, int64_t vec0, int ncols, int ld,
-                                                              int64_t n, int zero_pad, T* __restrict__ out) {
+                                                              int64_t n, int zero_pad, T* __restrict__ out,
+                                                              const int32_t* __restrict__ rows) {
     const int rpp = 256 / ld;
     const int r_in = (int)threadIdx.x / ld;
     const int j = (int)threadIdx.x - r_in * ld;
     if (r_in >= rpp || (j >= ncols && !zero_pad)) return;
-    for (int64_t i = (int64_t)blockIdx.x * rpp + r_in; i < n; i += (int64_t)gridDim.x * rpp)
-        out[i * ld + j] = j < ncols ? (T)rademacher_sign(seed, (uint64_t)(vec0 + j), (uint64_t)i) : (T)0;
+    for (int64_t i = (int64_t)blockIdx.x * rpp + r_in; i < n; i += (int64_t)gridDim.x * rpp) {
+        const uint64_t gi = rows ? (uint64_t)rows[i] : (uint64_t)i;
+        out[i * ld + j] = j < ncols ? (T)rademacher_sign(seed, (uint64_t)(vec0 + j), gi) : (T)0;
+    }
 }
 
 // Any leading dimension (the public fill allows ld > 256): one element per
@@ -86,29 +89,30 @@ __global__ __launch_bounds__(256) void rademacher_fill_kernel(uint64_t seed, int
 template <typename T>
 __global__ __launch_bounds__(256) void rademacher_fill_wide_kernel(uint64_t seed, int64_t vec0, int ncols,
                                                                    int64_t ld, int64_t n, int zero_pad,
-                                                                   T* __restrict__ out) {
+                                                                   T* __restrict__ out,
+                                                                   const int32_t* __restrict__ rows) {
     const int64_t total = n * ld;
     for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
         const int64_t i = idx / ld;
         const int64_t j = idx - i * ld;
         if (j < ncols)
-            out[idx] = (T)rademacher_sign(seed, (uint64_t)(vec0 + j), (uint64_t)i);
+            out[idx] = (T)rademacher_sign(seed, (uint64_t)(vec0 + j), rows ? (uint64_t)rows[i] : (uint64_t)i);
         else if (zero_pad)
             out[idx] = (T)0;
     }
 }
 
 hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int ncols, int64_t ld,
-                             int64_t n, int precision, int zero_pad, void* out) {
+                             int64_t n, int precision, int zero_pad, void* out, const int32_t* rows) {
     if (ld < 1) return hipErrorInvalidValue;
     if (ld > 256) {
         const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(16384, (n * ld + 255) / 256));
         if (precision == KPM_FP64)
             rademacher_fill_wide_kernel<double><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
-                                                                            (double*)out);
+                                                                            (double*)out, rows);
         else
             rademacher_fill_wide_kernel<float><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, ld, n, zero_pad,
-                                                                           (float*)out);
+                                                                           (float*)out, rows);
         return hipGetLastError();
     }
     const int64_t rpp = 256 / ld;
@@ -117,10 +121,10 @@ hipError_t launch_rademacher(hipStream_t s, uint64_t seed, int64_t vec0, int nco
     if (blocks < 1) blocks = 1;
     if (precision == KPM_FP64)
         rademacher_fill_kernel<double><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, (int)ld, n, zero_pad,
-                                                                   (double*)out);
+                                                                   (double*)out, rows);
     else
         rademacher_fill_kernel<float><<<(int)blocks, 256, 0, s>>>(seed, vec0, ncols, (int)ld, n, zero_pad,
-                                                                  (float*)out);
+                                                                  (float*)out, rows);
     return hipGetLastError();
 }
 
@@ -135,6 +139,7 @@ struct StepParams {
     double alpha, beta;
     int32_t n, ld, lpr, rpw, rows_per_block, npanels, stage;
     int32_t reverse;  // walk each XCD's panel range from its end
+    int32_t ntu;      // non-temporal loads of U (probe blocks beyond the MALL)
     // Legendre step only: coefficient of v_{k-1}, sign bits of v_0
     double gam;
     const uint32_t* sgn;
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kThreads) void cheb_step_kernel(StepParams p) {
         const int r1 = min(p.n, r0 + p.rows_per_block);
         process_panel<TA, TV, FIRST, OFF32, G, kLdsDoubles, LEG>(r0, r1, rp, ci, val, Vb, Ub, ldb, coffb, p.alpha,
                                                                  p.beta, p.stage, smem, lane_on, wave, rw, p.rpw, sx,
-                                                                 ss, &leg);
+                                                                 ss, &leg, p.ntu);
     }
 
     // One partial per workgroup: the lanes' sums over every row they
@@ -350,6 +355,9 @@ hipError_t launch_cheb_step(hipStream_t s, const CsrDev& A, int precision, bool 
     p.npanels = g.nblocks;
     p.stage = tune().stage;
     p.reverse = reverse && tune().rev;
+    // probe blocks larger than 128 MiB (the MALL holds 256 MB and the U
+    // stream would otherwise evict the gathered rows from it)
+    p.ntu = (uint64_t)A.n * (uint64_t)g.ld * (precision == KPM_FP64 ? 8u : 4u) > (128ull << 20);
     p.gam = leg ? leg->gam : 0.0;
     p.sgn = leg ? leg->sgn : nullptr;
     p.sw = leg ? leg->sw : 0;

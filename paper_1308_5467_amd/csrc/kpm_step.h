@@ -45,6 +45,11 @@ struct Pack<float> {
         const float4 t = *reinterpret_cast<const float4*>(p);
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     }
+    __device__ static __forceinline__ void load_nt(const float* p, float (&v)[4]) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+        v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
+    }
     __device__ static __forceinline__ void store(float* p, const float (&v)[4]) {
         *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
     }
@@ -60,6 +65,11 @@ struct Pack<double> {
     __device__ static __forceinline__ void load(const double* p, double (&v)[2]) {
         const double2 t = *reinterpret_cast<const double2*>(p);
         v[0] = t.x; v[1] = t.y;
+    }
+    __device__ static __forceinline__ void load_nt(const double* p, double (&v)[2]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+        v[0] = t[0]; v[1] = t[1];
     }
     __device__ static __forceinline__ void store(double* p, const double (&v)[2]) {
         *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
@@ -136,6 +146,11 @@ struct LegArgs {
 // which keeps the loads unconditional instead of behind one branch and one
 // index wait each.
 //
+// With `ntu` set the U row (read once here, then overwritten) is loaded
+// non-temporally: for probe blocks larger than the 256 MB MALL this leaves
+// the cache to the gathered rows (large workload: 3 % faster; on a 67 MB
+// block it cost 25 %, so the caller sets it by block size).
+//
 // EARLY (indices in LDS): the own-row and U loads go out first and overlap
 // the gathers.  Without staging the index loads share the in-order vector
 // memory counter with them, so the own-row and U loads are issued after the
@@ -147,14 +162,20 @@ template <typename TA, typename TV, bool FIRST, bool EARLY, bool OFF32, int G, t
 __device__ __forceinline__ void step_row(int row, int kb, int ke, const E& csr, const char* __restrict__ Vb,
                                          char* __restrict__ Ub, uint32_t ldb, uint32_t coffb,
                                          double alpha, double beta, double (&sx)[Pack<TV>::N],
-                                         double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr) {
+                                         double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr,
+                                         int ntu = 0) {
     constexpr int N = Pack<TV>::N;
     const uint64_t orow = voff<OFF32>(row, ldb, coffb);
     TV own[N], u[N];
     uint32_t bits = 0;
     if (EARLY) {
         Pack<TV>::load(reinterpret_cast<const TV*>(Vb + orow), own);
-        if (!FIRST) Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        if (!FIRST) {
+            if (ntu)
+                Pack<TV>::load_nt(reinterpret_cast<const TV*>(Ub + orow), u);
+            else
+                Pack<TV>::load(reinterpret_cast<const TV*>(Ub + orow), u);
+        }
         if (LEG) bits = leg->sgn[(int64_t)row * leg->sw + leg->sword] >> leg->sshift;
     }
     TV acc[N];
@@ -228,7 +249,8 @@ __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __r
                                               uint32_t coffb, double alpha, double beta, int stage,
                                               double (&smem)[LDS_DOUBLES], bool lane_on, int wave, int rw,
                                               int rpw, double (&sx)[Pack<TV>::N],
-                                              double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr) {
+                                              double (&ss)[Pack<TV>::N], const LegArgs* leg = nullptr,
+                                              int ntu = 0) {
     const int pass_rows = kWaves * rpw;
     // Staging layout in LDS: [row offsets (R+1) x 4 bytes, padded to 16]
     // [(index, value) pairs pnnz x sizeof(CsrPair<TA>)].
@@ -252,7 +274,7 @@ __device__ __forceinline__ void process_panel(int r0, int r1, const int32_t* __r
             for (int row = r0 + wave * rpw + rw; row < r1; row += pass_rows) {
                 const int lr = row - r0;
                 step_row<TA, TV, FIRST, true, OFF32, G, CsrPairs<TA>, LEG>(row, s_rp[lr], s_rp[lr + 1], csr, Vb, Ub,
-                                                                           ldb, coffb, alpha, beta, sx, ss, leg);
+                                                                           ldb, coffb, alpha, beta, sx, ss, leg, ntu);
             }
         }
         __syncthreads();  // before the LDS is restaged or reused

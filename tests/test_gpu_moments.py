@@ -396,3 +396,66 @@ def test_context_created_before_torch_is_imported():
     root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
     assert r.returncode == 0 and "ok 1.0" in r.stdout, (r.stdout, r.stderr)
+
+
+# ---------------------------------------------------------------- locality renumbering
+@pytest.mark.parametrize("prec,tol", [("f32", TOL32), ("f64", TOL64)])
+def test_locality_renumbering_parity(ctx, prec, tol):
+    """KPM_FLAG_LOCALITY: the matrix renumbered inside the library along its
+    grid's Morton curve, probes at the original indices -- per-probe moments
+    against the oracle on the original matrix (3D Anderson 24^3 + long-range
+    pairs, 2D periodic 40 x 24), and against the plain path.  A second call
+    reuses the cached structure with new values."""
+    import torch
+    mats = [synth.config_matrix("c5", scale=24), synth.add_diagonal_disorder(synth.laplacian2d_periodic(40, 24), 4.0, 9)]
+    for A in mats:
+        D = dev(A, prec)
+        lb, ub = kpm.kpm_bounds(ctx, D, 20, 31, 0.01)
+        mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 61, 21, 77, precision=prec, per_vector=True, locality=True)
+        ref = oracle_per_vec(A, lb, ub, 61, 21, 77, dtype=prec)
+        assert np.max(np.abs(pv - ref)) < tol
+        mu0 = kpm.kpm_moments(ctx, D, lb, ub, 61, 21, 77, precision=prec)
+        assert np.max(np.abs(mu - mu0)) < tol
+    # new values at the same address: the renumbered copy re-reads them
+    A = mats[1]
+    D = dev(A, prec)
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 31, 0.01)
+    kpm.kpm_moments(ctx, D, lb, ub, 10, 4, 5, precision=prec, locality=True)
+    B = synth.CSR(A.n, A.row_ptr, A.col_idx, A.val * 0.5)
+    D.val.copy_(torch.as_tensor(B.val.astype(np.float32 if prec == "f32" else np.float64), device="cuda"))
+    _, pv = kpm.kpm_moments(ctx, D, lb, ub, 30, 4, 5, precision=prec, per_vector=True, locality=True)
+    assert np.max(np.abs(pv - oracle_per_vec(B, lb, ub, 30, 4, 5, dtype=prec))) < tol
+
+
+def test_locality_without_grid_and_other_entry_points(ctx):
+    """No grid: the flag changes nothing (bitwise).  Host matrices of equal
+    sizes but different structure in a row: each renumbered from its own
+    structure.  Legendre moments by conversion take the flag; the Legendre
+    recurrence refuses it.  The whole-path pipeline with the flag equals the
+    pipeline without it to the moments' bar."""
+    R = synth.random_sparse_symmetric(700, 4.5, 4)
+    D = dev(R, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3, 0.01)
+    a = kpm.kpm_moments(ctx, D, lb, ub, 40, 9, 2, locality=True)
+    b = kpm.kpm_moments(ctx, D, lb, ub, 40, 9, 2)
+    assert np.array_equal(a, b)
+    for L in ((30, 20), (20, 30)):  # same n and nnz, different grids
+        A = synth.add_diagonal_disorder(synth.laplacian2d_periodic(*L), 2.0, 6)
+        H = kpm.HostCSR(A.n, A.row_ptr, A.col_idx, A.val)
+        lb, ub = kpm.kpm_bounds(ctx, H, 20, 3, 0.01)
+        _, pv = kpm.kpm_moments(ctx, H, lb, ub, 25, 6, 8, precision="f64", per_vector=True, locality=True)
+        assert np.max(np.abs(pv - oracle_per_vec(A, lb, ub, 25, 6, 8))) < TOL64, L
+    A = synth.config_matrix("c5", scale=16)
+    D = dev(A, "f32")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3, 0.01)
+    l1 = kpm.kpm_legendre_moments(ctx, D, lb, ub, 33, 8, 4, locality=True)
+    l0 = kpm.kpm_legendre_moments(ctx, D, lb, ub, 33, 8, 4)
+    assert np.max(np.abs(l1 - l0)) < TOL32
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_legendre_moments(ctx, D, lb, ub, 33, 8, 4, recurrence=True, locality=True)
+    assert e.value.status == -6
+    x = np.linspace(lb, ub, 50)
+    p1, m1, _, _ = kpm.kpm_dos_pipeline(ctx, D, 64, 16, 5, x, locality=True, lanczos_seed=3)
+    p0, m0, _, _ = kpm.kpm_dos_pipeline(ctx, D, 64, 16, 5, x, lanczos_seed=3)
+    assert np.max(np.abs(m1 - m0)) < TOL32
+    assert np.max(np.abs(p1 - p0)) < 1e-3 * np.max(np.abs(p0))
