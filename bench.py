@@ -83,7 +83,7 @@ def counter_traffic(kernel: str, workload: str):
                 if not m:
                     continue
                 kv = dict(t.split("=", 1) for t in m.group(1).split())
-                if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                if kv.get("kernel") != kernel.replace(" ", "") or kv.get("workload") != workload:
                     continue
                 if kv.get("step_sources") != cur:
                     stale = fn
