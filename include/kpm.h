@@ -197,7 +197,8 @@ kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, double lb, doubl
  * the end of them.  Same moments as kpm_moments for the same opts (the same
  * launches and geometry, bitwise), with these differences:
  *  - A must be in device memory (on_device = 1); the FP32 path needs FP32
- *    values; opts->validate must be 0 (KPM_ERR_UNSUPPORTED otherwise).
+ *    values; opts->validate must be 0 and KPM_FLAG_LOCALITY unset
+ *    (KPM_ERR_UNSUPPORTED otherwise).
  *  - mu: DEVICE [M+1] doubles; mu_per_vec: DEVICE [nvec * (M+1)] or NULL.
  *  - No escape check: the caller checks |mu_per_vec| <= 1 if it needs to.
  *  - Its work memory is one device array of KPM_NOALLOC_SCRATCH_BYTES per

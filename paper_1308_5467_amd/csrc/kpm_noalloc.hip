@@ -103,6 +103,8 @@ extern "C" kpm_status kpm_moments_noalloc(kpm_ctx* ctx, const kpm_csr* Ain, doub
     if (o->rows_per_block < 0 || o->rows_per_block > (1 << 20))
         return kpm_fail(ctx, KPM_ERR_ARG, "rows_per_block out of range");
     if (o->validate) return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "validate must be 0 (validation waits on the host)");
+    if (o->flags & KPM_FLAG_LOCALITY)
+        return kpm_fail(ctx, KPM_ERR_UNSUPPORTED, "KPM_FLAG_LOCALITY allocates its renumbered copy of the matrix");
     if (!(isfinite(lb) && isfinite(ub) && ub > lb)) return kpm_fail(ctx, KPM_ERR_ARG, "need finite lb < ub");
     void* base;
     kpm_status st = scratch_of(ctx, &base);

@@ -110,6 +110,9 @@ def test_noalloc_rejects_oversized_problems_and_bad_arguments(ctx):
     c = D.as_c()
     assert lib.kpm_moments_noalloc(ctx.handle, ctypes.byref(c), -1.5, 1.5, ctypes.byref(o),
                                    ctypes.c_void_p(mu.data_ptr()), None) == -6
+    o = kpm._opts(10, 4, 1, "f32", 0, False, 0, kpm.KPM_FLAG_LOCALITY)
+    assert lib.kpm_moments_noalloc(ctx.handle, ctypes.byref(c), -1.5, 1.5, ctypes.byref(o),
+                                   ctypes.c_void_p(mu.data_ptr()), None) == -6
     # a diagonal matrix: the Rademacher estimator is exact
     s = (np.linspace(-1.0, 1.0, 1000) - 0.0) / 1.5
     Asmall = synth.diagonal_matrix(np.linspace(-1.0, 1.0, 1000))
