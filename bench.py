@@ -491,6 +491,14 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
     kpm.kpm_profile_enable(ctx, False)
     launches, ms = kpm.kpm_profile_query(ctx, "slq_step")
     us_step = ms / launches * 1000.0
+    # the same with the library's locality renumbering of the grid matrix
+    kpm.kpm_slq(ctx, D32, lb, ub, M_SLQ, nvec, 2002, block=b, locality=True)
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    t_slq_loc = _time_ms(lambda: kpm.kpm_slq(ctx, D32, lb, ub, M_SLQ, nvec, 2002, block=b, locality=True), reps)
+    kpm.kpm_profile_enable(ctx, False)
+    launches_l, ms_l = kpm.kpm_profile_query(ctx, "slq_step")
+    us_step_loc = ms_l / launches_l * 1000.0
     nblk = nvec // b
     bytes_step = nblk * (8 * A.nnz + 4 * (A.n + 1)) + 32 * A.n * nvec
     gbs = bytes_step / (us_step * 1e-6) / 1e9
@@ -501,6 +509,8 @@ def slq_leg(kpm, ctx, A, D32, x, reps=5):
             "ms_pipeline_haydock": round(t_pipe_hay, 3), "ms_haydock_density": round(t_hay, 3),
             "us_per_step": round(us_step, 2), "algorithmic_bytes_per_step": bytes_step,
             "algorithmic_gbs": round(gbs, 1), "frac_of_hbm_peak": round(gbs / 8000.0, 4),
+            "locality": {"ms_lanczos": round(t_slq_loc, 3), "us_per_step": round(us_step_loc, 2),
+                         "frac_of_hbm_peak": round(bytes_step / (us_step_loc * 1e-6) / 8e12, 4)},
             "sparse_products_per_probe": M_SLQ}
 
 

@@ -103,7 +103,9 @@ enum {
                               (KPM_ERR_UNSUPPORTED when a matrix is too
                               large for it)                                 */
     KPM_FLAG_LOCALITY = 128,      /* kpm_moments, kpm_legendre_moments,
-                              kpm_dos_pipeline: when the matrix comes from a
+                              kpm_dos_pipeline, kpm_slq (the Lanczos run on
+                              P A P^T from P v has the same tridiagonal
+                              matrix): when the matrix comes from a
                               2D or 3D grid numbered lexicographically (found
                               by kpm_locality_order), run on it renumbered
                               along the grid's Morton curve, probes at the

@@ -454,14 +454,15 @@ def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int
 
 
 def kpm_slq(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int, block: int = 0,
-            validate: bool = False, rows_per_block: int = 0, coefficients: bool = False, nodes: bool = True):
+            validate: bool = False, rows_per_block: int = 0, coefficients: bool = False, nodes: bool = True,
+            locality: bool = False):
     """Stochastic Lanczos nodes: theta [nvec, M] (A's units), tau2 [nvec, M],
     steps_used [nvec]; with coefficients=True also alpha, beta [nvec, M] of B.
     nodes=False (with coefficients=True) skips the eigenvalue problems and
-    returns (steps_used, alpha, beta)."""
+    returns (steps_used, alpha, beta).  locality=True: KPM_FLAG_LOCALITY."""
     if not nodes and not coefficients:
         raise ValueError("nodes=False needs coefficients=True")
-    o = _opts(M, nvec, seed, "f64", block, validate, rows_per_block)
+    o = _opts(M, nvec, seed, "f64", block, validate, rows_per_block, KPM_FLAG_LOCALITY if locality else 0)
     theta = np.zeros((nvec, M)) if nodes else None
     tau2 = np.zeros((nvec, M)) if nodes else None
     used = np.zeros(nvec, dtype=np.int32)

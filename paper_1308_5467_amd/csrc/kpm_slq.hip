@@ -320,9 +320,11 @@ __global__ __launch_bounds__(256) void slq_reduce_kernel(const double* __restric
 // probe columns vec0_s .. (vec0_s = vec0 + s * ld, ncols_s of them), (0, 0)
 // for padding columns; coef_s = (alpha_{-1} = 0, beta_{-1} = ||v|| = sqrt(n))
 // for probe columns, (0, 0) for padding.
+// rows (nullable): row i takes entry rows[i] of each probe (a renumbered
+// matrix's probes at the original indices).
 __global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int nvec_left, int ld, int64_t n, double sqrt_n,
                                 double* __restrict__ Zall, int64_t zstride_d, double* __restrict__ coef_all,
-                                int64_t coef_stride) {
+                                int64_t coef_stride, const int32_t* __restrict__ rows) {
     const int s = blockIdx.y;
     const int64_t v0 = vec0 + (int64_t)s * ld;
     const int ncols = (int)min<int64_t>(ld, max<int64_t>(0, nvec_left - (int64_t)s * ld));
@@ -337,7 +339,8 @@ __global__ void slq_init_kernel(uint64_t seed, int64_t vec0, int nvec_left, int 
     for (int64_t idx = i0; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / ld;
         const int c = (int)(idx - i * ld);
-        const double v = c < ncols ? (double)rademacher_sign(seed, (uint64_t)(v0 + c), (uint64_t)i) : 0.0;
+        const uint64_t gi = rows ? (uint64_t)rows[i] : (uint64_t)i;
+        const double v = c < ncols ? (double)rademacher_sign(seed, (uint64_t)(v0 + c), gi) : 0.0;
         Z[2 * idx] = v;
         Z[2 * idx + 1] = 0.0;
     }
@@ -522,6 +525,14 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
     kpm_status st = kpm_prepare_csr(ctx, Ain, KPM_FP64, &A, "");
     if (st != KPM_OK) return st;
     if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
+    // KPM_FLAG_LOCALITY: Lanczos on P A P^T from P v gives the same T
+    const int32_t* rows = nullptr;
+    if (o->flags & KPM_FLAG_LOCALITY) {
+        if (!Ain->on_device) kpm_locality_free(ctx);
+        CsrDev R;
+        if ((st = kpm_locality_view(ctx, A, &R, &rows)) != KPM_OK) return st;
+        A = R;
+    }
 
     const double c = 0.5 * (lb + ub), d = 0.5 * (ub - lb);
     const int M = o->M, nvec = o->nvec;
@@ -561,7 +572,7 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
         const int ib = (int)std::min<int64_t>(4096, (total + 255) / 256);
         slq_init_kernel<<<dim3(std::max(ib, 1), S), 256, 0, ctx->stream>>>(
             o->seed, vec0, (int)(nvec - vec0), g.ld, A.n, sqrt((double)A.n), (double*)Z0, (int64_t)(zbytes / 8),
-            (double*)coef, cstride);
+            (double*)coef, cstride, rows);
         KPM_HIP(ctx, hipGetLastError());
         char* Z[2] = {(char*)Z0, (char*)Z1};
         SlqParams p;

@@ -129,3 +129,25 @@ def test_c2_full_size_sampled(ctx):
     D = dev(A, "f32")
     lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
     _check(A, "f32", lb, ub, 100, 64, 2002, vec_ids=[0, 31, 63], ctx=ctx, dos_sigma=0.02)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_locality_renumbering_parity(ctx, dtype):
+    """KPM_FLAG_LOCALITY: the Lanczos runs on the matrix renumbered along its
+    grid's Morton curve from the same probes (generated at the original row
+    indices) give the oracle's coefficients on the original matrix, 3D
+    Anderson 20^3 plus long-range pairs, two probe blocks of 8."""
+    A = synth.config_matrix("c5", scale=20)
+    Ao = A if dtype == "f64" else A.rounded_f32()
+    D = dev(A, dtype)
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 9, 0.01)
+    c, d = oracle.rescale(lb, ub)
+    M, nvec, seed = 60, 16, 41
+    _, _, used, al, be = kpm.kpm_slq(ctx, D, lb, ub, M, nvec, seed, block=8, coefficients=True, locality=True)
+    _, _, used0, al0, be0 = kpm.kpm_slq(ctx, D, lb, ub, M, nvec, seed, block=8, coefficients=True)
+    assert np.array_equal(used, used0)
+    assert np.max(np.abs(al - al0)) < 1e-11 and np.max(np.abs(be - be0)) < 1e-11
+    for l in (0, 7, 8, 15):
+        ra, rb = oracle.lanczos_tridiag(Ao, c, d, M, 1, seed, vec0=l)
+        assert np.max(np.abs(al[l] - ra[0])) < 1e-11, l
+        assert np.max(np.abs(be[l] - rb[0])) < 1e-11, l
