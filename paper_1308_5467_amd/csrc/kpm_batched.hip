@@ -42,6 +42,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -712,14 +713,16 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // LDS bytes one workgroup may use on `device` (queried once per device).
 static size_t lds_per_workgroup(int device) {
-    static size_t cache[64] = {};
+    static std::atomic<size_t> cache[64];
     if (device < 0 || device >= 64) return 0;
-    if (!cache[device]) {
+    size_t v = cache[device].load(std::memory_order_relaxed);
+    if (!v) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
-        cache[device] = prop.sharedMemPerBlock;
+        v = prop.sharedMemPerBlock;
+        cache[device].store(v, std::memory_order_relaxed);
     }
-    return cache[device];
+    return v;
 }
 
 // Lower bound on the table entries (workgroups) per mv when there are more

@@ -406,6 +406,7 @@ static kpm_status moments_collect(kpm_ctx* ctx, const MomentsPending& P, double*
     KPM_HIP(ctx, hipMemcpyAsync(sz, P.zout, nz * 8, hipMemcpyDeviceToHost, ctx->stream));
     if (extra && extra_n) KPM_HIP(ctx, hipMemcpyAsync(sx, extra, extra_n * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;
+    if ((st = kpm_locality_check(ctx)) != KPM_OK) return st;
     if (mu) memcpy(mu, sm, nm * 8);
     if (extra && extra_n) memcpy(extra_host, sx, extra_n * 8);
     std::vector<double>& hz = ctx->host_scratch;

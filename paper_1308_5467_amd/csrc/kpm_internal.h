@@ -152,6 +152,10 @@ void kpm_batch_free(kpm_ctx* ctx);
 // original index of each of its rows), else *out = A and *orig = NULL.
 kpm_status kpm_locality_view(kpm_ctx* ctx, const kpm::CsrDev& A, kpm::CsrDev* out, const int32_t** orig);
 void kpm_locality_free(kpm_ctx* ctx);
+// After a call that used kpm_locality_view has been waited for: KPM_ERR_ARG
+// (and the cached copy dropped) when the matrix's structure at the cached
+// address is not the one the copy was built from.
+kpm_status kpm_locality_check(kpm_ctx* ctx);
 
 // Learned damping (damping network on the device); host mu/g arrays.
 kpm_status kpm_learned_damping(kpm_ctx* ctx, int M, const double* mu, double* g);

@@ -43,6 +43,45 @@ uint64_t morton3(uint64_t x, uint64_t y, uint64_t z) {
     return key;
 }
 
+// Order-free checksum of a CSR structure (row offsets and columns): a
+// wrapping sum of SplitMix64-finalised (index, entry) words, the same on
+// the host and the device.
+__host__ __device__ inline uint64_t structure_word(uint64_t tag, uint64_t idx, uint32_t v) {
+    uint64_t z = tag + ((idx << 32) ^ (uint64_t)v) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kTagRp = 0x1, kTagCi = 0x2;
+
+uint64_t structure_sum_host(const int32_t* rp, int64_t n, const int32_t* ci, int64_t nnz) {
+    uint64_t s = 0;
+    for (int64_t i = 0; i <= n; ++i) s += structure_word(kTagRp, (uint64_t)i, (uint32_t)rp[i]);
+    for (int64_t k = 0; k < nnz; ++k) s += structure_word(kTagCi, (uint64_t)k, (uint32_t)ci[k]);
+    return s;
+}
+
+__global__ void clear_sum_kernel(unsigned long long* out) { out[0] = 0ull; }
+
+__global__ __launch_bounds__(256) void structure_sum_kernel(const int32_t* __restrict__ rp, int64_t n,
+                                                            const int32_t* __restrict__ ci, int64_t nnz,
+                                                            unsigned long long* out) {
+    __shared__ unsigned long long sh[256];
+    uint64_t s = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride)
+        s += structure_word(kTagRp, (uint64_t)i, (uint32_t)rp[i]);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride)
+        s += structure_word(kTagCi, (uint64_t)k, (uint32_t)ci[k]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, sh[0]);
+}
+
 template <typename T>
 __global__ void gather_values_kernel(const T* __restrict__ src_val, const int32_t* __restrict__ src,
                                      int64_t nnz, T* __restrict__ out) {
@@ -103,9 +142,12 @@ struct kpm_locality_state {
     const int32_t* ci = nullptr;
     int64_t n = 0, nnz = 0;
     bool structured = false;
-    void* mem = nullptr;  // rp2 | ci2 | src | orig | val2
+    uint64_t sum = 0;     // structure checksum when the plan was built
+    void* mem = nullptr;  // rp2 | ci2 | src | orig | val2 | sum
     int32_t *rp2 = nullptr, *ci2 = nullptr, *src = nullptr, *orig = nullptr;
     void* val2 = nullptr;
+    unsigned long long* d_sum = nullptr;  // checksum of the current call's structure
+    bool check_pending = false;
 };
 
 void kpm_locality_free(kpm_ctx* ctx) {
@@ -139,6 +181,7 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
         }
         L->structured = dims[0] > 0;
         if (!L->structured) return KPM_OK;
+        L->sum = structure_sum_host(rp.data(), A.n, ci.data(), A.nnz);
         // the renumbered structure: row r is row perm[r] of A, its columns
         // renumbered and sorted, src[k] the entry of A it came from
         std::vector<int32_t> inv((size_t)A.n), rp2((size_t)A.n + 1), ci2((size_t)A.nnz), src((size_t)A.nnz);
@@ -161,7 +204,8 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
         const size_t vsz = A.val_f64 ? 8 : 4;
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         const size_t b_rp = al((size_t)(A.n + 1) * 4), b_ci = al((size_t)A.nnz * 4 + 4), b_or = al((size_t)A.n * 4);
-        const size_t total = b_rp + 2 * b_ci + b_or + al((size_t)A.nnz * vsz + vsz);
+        const size_t b_val = al((size_t)A.nnz * vsz + vsz);
+        const size_t total = b_rp + 2 * b_ci + b_or + b_val + 256;
         if (hipMalloc(&L->mem, total) != hipSuccess) {
             L->mem = nullptr;
             kpm_locality_free(ctx);
@@ -173,6 +217,7 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
         L->src = reinterpret_cast<int32_t*>(p + b_rp + b_ci);
         L->orig = reinterpret_cast<int32_t*>(p + b_rp + 2 * b_ci);
         L->val2 = p + b_rp + 2 * b_ci + b_or;
+        L->d_sum = reinterpret_cast<unsigned long long*>(p + b_rp + 2 * b_ci + b_or + b_val);
         KPM_HIP(ctx, hipMemcpyAsync(L->rp2, rp2.data(), rp2.size() * 4, hipMemcpyHostToDevice, ctx->stream));
         if (A.nnz > 0) {
             KPM_HIP(ctx, hipMemcpyAsync(L->ci2, ci2.data(), ci2.size() * 4, hipMemcpyHostToDevice, ctx->stream));
@@ -186,6 +231,13 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
         }
     }
     if (!L->structured) return KPM_OK;
+    // the checksum of the current structure, compared with the plan's when
+    // the results are collected (kpm_locality_check)
+    clear_sum_kernel<<<1, 1, 0, ctx->stream>>>(L->d_sum);
+    structure_sum_kernel<<<(int)std::min<int64_t>(2048, (A.nnz + A.n + 256) / 256), 256, 0, ctx->stream>>>(
+        A.rp, A.n, A.ci, A.nnz, L->d_sum);
+    KPM_HIP(ctx, hipGetLastError());
+    L->check_pending = true;
     // the current values, in the renumbered order
     if (A.nnz > 0) {
         const int64_t blocks = std::min<int64_t>(8192, (A.nnz + 255) / 256);
@@ -201,5 +253,21 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
     out->ci = L->ci2;
     out->val = L->val2;
     *orig = L->orig;
+    return KPM_OK;
+}
+
+kpm_status kpm_locality_check(kpm_ctx* ctx) {
+    kpm_locality_state* L = ctx->loc;
+    if (!L || !L->check_pending) return KPM_OK;
+    L->check_pending = false;
+    unsigned long long got = 0;
+    KPM_HIP(ctx, hipMemcpyAsync(&got, L->d_sum, 8, hipMemcpyDeviceToHost, ctx->stream));
+    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if ((uint64_t)got != L->sum) {
+        kpm_locality_free(ctx);  // rebuilt from the current structure on the next call
+        return kpm_fail(ctx, KPM_ERR_ARG,
+                        "the matrix's sparsity structure changed since its renumbered copy was built (same address "
+                        "and sizes): call again to rebuild it");
+    }
     return KPM_OK;
 }

@@ -622,6 +622,7 @@ extern "C" kpm_status kpm_slq(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doubl
     kpm_prof_end(ctx, "slq_step", launches);
     KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
     kpm_prof_collect(ctx);
+    if ((st = kpm_locality_check(ctx)) != KPM_OK) return st;
     if (alpha_out) memcpy(alpha_out, al.data(), al.size() * 8);
     if (beta_out) memcpy(beta_out, be.data(), be.size() * 8);
     if (!theta) {  // coefficients only (Haydock's method needs no Ritz values)

@@ -459,3 +459,26 @@ def test_locality_without_grid_and_other_entry_points(ctx):
     p0, m0, _, _ = kpm.kpm_dos_pipeline(ctx, D, 64, 16, 5, x, lanczos_seed=3)
     assert np.max(np.abs(m1 - m0)) < TOL32
     assert np.max(np.abs(p1 - p0)) < 1e-3 * np.max(np.abs(p0))
+
+
+def test_locality_detects_changed_structure(ctx):
+    """The renumbered copy is cached per matrix address.  A device matrix
+    rewritten in place with another structure of the same sizes (a 30 x 20
+    periodic grid replaced by a 20 x 30 one) is detected when the results are
+    collected (KPM_ERR_ARG); the next call rebuilds the copy and matches the
+    oracle on the new matrix."""
+    import torch
+    A = synth.add_diagonal_disorder(synth.laplacian2d_periodic(30, 20), 2.0, 6)
+    B = synth.add_diagonal_disorder(synth.laplacian2d_periodic(20, 30), 2.0, 7)
+    assert A.n == B.n and A.nnz == B.nnz and not np.array_equal(A.col_idx, B.col_idx)
+    D = dev(A, "f64")
+    lb, ub = -1.5, 10.5
+    kpm.kpm_moments(ctx, D, lb, ub, 20, 4, 3, precision="f64", locality=True)
+    D.row_ptr.copy_(torch.as_tensor(B.row_ptr, device="cuda"))
+    D.col_idx.copy_(torch.as_tensor(B.col_idx, device="cuda"))
+    D.val.copy_(torch.as_tensor(B.val, device="cuda"))
+    with pytest.raises(kpm.KpmError) as e:
+        kpm.kpm_moments(ctx, D, lb, ub, 20, 4, 3, precision="f64", locality=True)
+    assert e.value.status == -1 and "structure" in e.value.message
+    _, pv = kpm.kpm_moments(ctx, D, lb, ub, 20, 4, 3, precision="f64", per_vector=True, locality=True)
+    assert np.max(np.abs(pv - oracle_per_vec(B, lb, ub, 20, 4, 3))) < TOL64
