@@ -336,3 +336,23 @@ def test_on_chip_plan_detects_changed_structure(ctx):
     for m, X in enumerate([A, Bm]):
         ref = oracle_mu(X, lb[m], ub[m], 20, 8, 3 + m, "f32")
         assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_on_chip_high_degree(ctx, dtype, tol):
+    """The on-chip path at a high degree (301: 151 steps in one launch) on
+    matrices of several families and sizes (3D Anderson 6^3..10^3, 2D
+    Anderson, random sparse), ragged probe blocks: every matrix against the
+    oracle."""
+    mats = [synth.add_diagonal_disorder(synth.laplacian3d_periodic(L), 8.0, 60 + L) for L in (6, 8, 10)]
+    mats.append(synth.add_diagonal_disorder(synth.laplacian2d_periodic(20, 30), 4.0, 61))
+    mats.append(synth.random_sparse_symmetric(900, 4.5, 62))
+    lb, ub = bounds_of(mats, dtype)
+    D = [dev(A, dtype) for A in mats]
+    M, nvec = 301, 11
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 900, precision=dtype, path="resident")
+    mu_s = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 900, precision=dtype, path="stream")
+    for m, A in enumerate(mats):
+        ref = oracle_mu(A, lb[m], ub[m], M, nvec, 900 + m, dtype)
+        assert np.max(np.abs(mu[m] - ref)) < tol, m
+        assert np.max(np.abs(mu[m] - mu_s[m])) < tol, m

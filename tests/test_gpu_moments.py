@@ -299,17 +299,20 @@ def test_delta_function_example(ctx):
 
 
 # ---------------------------------------------------------------- full-size workloads, sampled
-def test_c2_full_size_sampled(ctx):
+@pytest.mark.parametrize("locality", [False, True])
+def test_c2_full_size_sampled(ctx, locality):
     """c2 at full size (64^3 Anderson, M = 256, 64 probes, FP32), in the
-    launch configuration the benchmark times; the oracle recomputes probes
-    0, 31 and 63 one by one."""
-    _say("c2 full size")
+    launch configuration the benchmark times (with and without the locality
+    renumbering, which the benchmark uses); the oracle recomputes probes 0,
+    31 and 63 one by one on the original matrix."""
+    _say(f"c2 full size, locality={locality}")
     A = synth.config_matrix("c2")
     D = dev(A, "f32")
     lb, ub = kpm.kpm_bounds(ctx, D, 20, 3002, 0.01)
     # 7-point periodic Laplacian spectrum [0, 12] shifted by disorder in [-8, 8]
     assert -8.0 - 1.0 < lb < 0.0 and 12.0 < ub < 20.0 + 1.0
-    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 256, 64, 2002, precision="f32", validate=False, per_vector=True)
+    mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 256, 64, 2002, precision="f32", validate=False, per_vector=True,
+                             locality=locality)
     Ao = A.rounded_f32()
     c, d = oracle.rescale(lb, ub)
     for l in (0, 31, 63):
@@ -334,7 +337,8 @@ def _c5_golden():
 def test_c5_full_size_sampled(ctx):
     """c5 at full size: 3D Anderson 128^3 plus random long-range hoppings
     (n = 2,097,152, nnz ~ 23M), degree 1000, 256 probes in blocks of 64,
-    FP32 -- the configuration the benchmark times.  Probes 254 and 255 (the
+    FP32 -- the configuration the benchmark times, plain and with the
+    locality renumbering the benchmark uses.  Probes 254 and 255 (the
     last block) against the oracle at every degree up to 1000, 1e-5; the
     oracle's bounds are used on both sides and the library's own bounds must
     agree with them (1e-9 relative); invariants on every probe; the first
@@ -359,6 +363,16 @@ def test_c5_full_size_sampled(ctx):
     mu2, pv2 = kpm.kpm_moments(ctx, D, lb, ub, 200, 256, 2005, precision="f32", block=64,
                                validate=False, per_vector=True)
     assert np.array_equal(pv[:, :201], pv2)
+    # the configuration the benchmark times: the library's locality renumbering
+    _say("c5 moments M=1000 with the locality renumbering")
+    mu3, pv3 = kpm.kpm_moments(ctx, D, lb, ub, 1000, 256, 2005, precision="f32", block=64,
+                               validate=False, per_vector=True, locality=True)
+    assert mu3[0] == 1.0 and np.all(np.abs(pv3) <= 1 + 1e-5)
+    err3 = np.abs(pv3[254:256] - z)
+    _say(f"c5 locality, probes 254, 255: max |dmu| {err3.max():.2e}; mean moments vs plain "
+         f"{np.abs(mu3 - mu).max():.2e}")
+    assert err3.max() < TOL32
+    assert np.abs(mu3 - mu).max() < TOL32
 
 
 def test_anderson32_longrange_fp32_degree1000_all_probes(ctx):
