@@ -209,6 +209,9 @@ def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, w
         roof["traffic_source"] = rec["source"]
         roof["traffic_over_algorithmic"] = round(rec["bytes"] / bytes_per_launch, 3)
         roof["traffic_rate_gbs"] = round(rec["bytes"] / (avg_ms * 1e-3) / 1e9, 1)
+        # the counters' bytes (L2 fetches and writes to memory) over the live
+        # launch time, against the same 8 TB/s peak
+        roof["traffic_frac_of_peak"] = round(roof["traffic_rate_gbs"] / HBM_PEAK_GBS, 4)
     else:
         roof["traffic_note"] = why
     return {
