@@ -687,6 +687,7 @@ void free_plan(BatchPlan& P) {
     if (P.graph) hipGraphDestroy(P.graph);
     if (P.mem) hipFree(P.mem);
     if (P.sell_mem) hipFree(P.sell_mem);
+    P.shape = BatchShape();  // a plan is reused only once its build has completed
     P.exec = nullptr;
     P.graph = nullptr;
     P.mem = nullptr;
@@ -824,7 +825,6 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
     if (!reuse) {
         KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
         free_plan(P);
-        P.shape = shape;
         P.nmat = nmat;
         P.M = M;
         P.K = (M + 1) / 2;
@@ -1102,6 +1102,9 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         KPM_HIP(ctx, hipMemcpyAsync(P.d_e1, e1.data(), (size_t)P.nmv * 4, hipMemcpyHostToDevice, P.gstream));
         KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
     }
+    // the plan is complete: later calls of the same shape reuse it (a build
+    // that failed part way left the shape empty, so it is rebuilt)
+    if (!reuse) P.shape = shape;
     // per-call scalars
     for (int m = 0; m < nmat; ++m) {
         const double c = 0.5 * (lb[m] + ub[m]), d = 0.5 * (ub[m] - lb[m]);
@@ -1124,6 +1127,10 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
     kpm_prof_begin_on(ctx, "batched", P.gstream);
     if (use_graph) {
         if (!P.exec) {
+            if (P.graph) {  // left by an instantiation that failed
+                hipGraphDestroy(P.graph);
+                P.graph = nullptr;
+            }
             KPM_HIP(ctx, hipStreamBeginCapture(P.gstream, hipStreamCaptureModeThreadLocal));
             hipError_t e = enqueue_plan(P.gstream, P);
             hipGraph_t gr = nullptr;

@@ -141,6 +141,7 @@ struct kpm_locality_state {
     const int32_t* rp = nullptr;  // the matrix the plan belongs to
     const int32_t* ci = nullptr;
     int64_t n = 0, nnz = 0;
+    bool val_f64 = false;  // the values' type the value buffer is sized for
     bool structured = false;
     uint64_t sum = 0;     // structure checksum when the plan was built
     void* mem = nullptr;  // rp2 | ci2 | src | orig | val2 | sum
@@ -161,26 +162,35 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
     *out = A;
     *orig = nullptr;
     kpm_locality_state*& L = ctx->loc;
-    if (!L || L->rp != A.rp || L->ci != A.ci || L->n != A.n || L->nnz != A.nnz) {
+    if (!L || L->rp != A.rp || L->ci != A.ci || L->n != A.n || L->nnz != A.nnz || L->val_f64 != A.val_f64) {
         KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
         kpm_locality_free(ctx);
         L = new kpm_locality_state();
         L->rp = A.rp;
         L->ci = A.ci;
-        L->n = A.n;
+        L->n = -1;  // matches no matrix until the build below has completed
         L->nnz = A.nnz;
+        L->val_f64 = A.val_f64;
         std::vector<int32_t> rp((size_t)A.n + 1), ci((size_t)A.nnz), perm((size_t)A.n);
         KPM_HIP(ctx, hipMemcpyAsync(rp.data(), A.rp, rp.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
         if (A.nnz > 0) KPM_HIP(ctx, hipMemcpyAsync(ci.data(), A.ci, ci.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
         KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        // the whole structure is read on the host below: check it first
+        bool ok = rp[0] == 0 && rp[(size_t)A.n] == A.nnz;
+        for (int64_t i = 0; ok && i < A.n; ++i) ok = rp[(size_t)i] <= rp[(size_t)i + 1];
+        for (int64_t k = 0; ok && k < A.nnz; ++k) ok = ci[(size_t)k] >= 0 && ci[(size_t)k] < A.n;
         int32_t dims[3];
-        kpm_status st = kpm_locality_order(A.n, A.nnz, rp.data(), ci.data(), perm.data(), dims);
+        const kpm_status st = ok ? kpm_locality_order(A.n, A.nnz, rp.data(), ci.data(), perm.data(), dims)
+                                 : KPM_ERR_ARG;
         if (st != KPM_OK) {
             kpm_locality_free(ctx);
-            return kpm_fail(ctx, st, "locality renumbering: malformed row offsets");
+            return kpm_fail(ctx, st, "locality renumbering: malformed CSR (row offsets or column indices)");
         }
         L->structured = dims[0] > 0;
-        if (!L->structured) return KPM_OK;
+        if (!L->structured) {
+            L->n = A.n;
+            return KPM_OK;
+        }
         L->sum = structure_sum_host(rp.data(), A.n, ci.data(), A.nnz);
         // the renumbered structure: row r is row perm[r] of A, its columns
         // renumbered and sorted, src[k] the entry of A it came from
@@ -229,6 +239,7 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
             kpm_locality_free(ctx);
             return kpm_hip_fail(ctx, e, "renumbered matrix upload");
         }
+        L->n = A.n;
     }
     if (!L->structured) return KPM_OK;
     // the checksum of the current structure, compared with the plan's when

@@ -496,3 +496,40 @@ def test_locality_detects_changed_structure(ctx):
     assert e.value.status == -1 and "structure" in e.value.message
     _, pv = kpm.kpm_moments(ctx, D, lb, ub, 20, 4, 3, precision="f64", per_vector=True, locality=True)
     assert np.max(np.abs(pv - oracle_per_vec(B, lb, ub, 20, 4, 3))) < TOL64
+
+
+def test_locality_value_types_sharing_one_structure(ctx):
+    """Two device matrices sharing the same row-offset and column arrays,
+    one with FP32 and one with FP64 values: the renumbered copy is keyed on
+    the values' type too (its value buffer is sized for it), so each call
+    matches the oracle -- FP32 path on FP32 values, FP64 path and FP32 path
+    on FP64 values, then FP32 again."""
+    import torch
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(12), 8.0, 21)
+    D32 = dev(A, "f32")
+    D64 = kpm.DeviceCSR(D32.n, D32.row_ptr, D32.col_idx, D32.val.to(torch.float64))
+    lb, ub = kpm.kpm_bounds(ctx, D32, 20, 5, 0.01)
+    ref = oracle_per_vec(A, lb, ub, 40, 6, 9, dtype="f32")  # values rounded to FP32 on both
+    for D, prec, tol in ((D32, "f32", TOL32), (D64, "f64", TOL64), (D64, "f32", TOL32), (D32, "f32", TOL32)):
+        _, pv = kpm.kpm_moments(ctx, D, lb, ub, 40, 6, 9, precision=prec, per_vector=True, locality=True)
+        assert np.max(np.abs(pv - ref)) < tol, prec
+
+
+def test_locality_refuses_malformed_structure_on_the_host(ctx):
+    """With the renumbering the whole structure is read on the host: a column
+    index past n or decreasing row offsets are refused there (KPM_ERR_ARG)
+    even without validation, before any kernel reads the matrix; a valid
+    matrix afterwards runs normally."""
+    A = synth.add_diagonal_disorder(synth.laplacian2d_periodic(16, 12), 2.0, 3)
+    bad_ci = A.col_idx.copy()
+    bad_ci[37] = A.n
+    bad_rp = A.row_ptr.copy()
+    bad_rp[50] = bad_rp[52]
+    for rp, ci in ((A.row_ptr, bad_ci), (bad_rp, A.col_idx)):
+        D = kpm.DeviceCSR.from_host(A.n, rp, ci, A.val.astype(np.float32), "f32")
+        with pytest.raises(kpm.KpmError) as e:
+            kpm.kpm_moments(ctx, D, -1.0, 9.0, 10, 4, 1, validate=False, locality=True)
+        assert e.value.status == -1 and "malformed" in e.value.message
+    D = dev(A, "f32")
+    _, pv = kpm.kpm_moments(ctx, D, -1.5, 9.5, 10, 4, 1, per_vector=True, locality=True)
+    assert np.max(np.abs(pv - oracle_per_vec(A, -1.5, 9.5, 10, 4, 1, dtype="f32"))) < TOL32
