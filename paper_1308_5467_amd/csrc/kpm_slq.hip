@@ -41,6 +41,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -392,8 +393,10 @@ SlqGeom slq_geom(int64_t n, int ncols, int hint) {
 }
 
 int slq_grid(bool f64vals, int npanels) {
-    static int res[2] = {-1, -1};
-    int& r = res[f64vals ? 1 : 0];
+    // resident workgroups per kernel variant, found once (threads that race
+    // here compute and store the same value)
+    static std::atomic<int> res[2] = {{-1}, {-1}};
+    int r = res[f64vals ? 1 : 0].load(std::memory_order_relaxed);
     if (r < 0) {
         int dev = 0, per_cu = 0;
         hipDeviceProp_t prop;
@@ -404,6 +407,7 @@ int slq_grid(bool f64vals, int npanels) {
             r = per_cu * prop.multiProcessorCount;
         else
             r = 0;
+        res[f64vals ? 1 : 0].store(r, std::memory_order_relaxed);
     }
     return r > 0 && r < npanels ? r : npanels;
 }
