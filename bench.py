@@ -300,6 +300,7 @@ def main():
             print(json.dumps({"legendre_dgl": legendre_leg(kpm, ctx, D2, x, 256, 64, 64, "f32")}))
         return
 
+    _progress(f"headline workload {args.workload}")
     A, D, w = load_workload(kpm, synth, args.workload, args.precision)
     M = args.M or w["M"]
     nvec = args.nvec or w["nvec"]
@@ -338,15 +339,18 @@ def main():
             unc / (out["roofline"]["avg_launch_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     lb, ub = head["lb_ub"]
     if locality and not args.no_extras:
+        _progress("headline in the caller's numbering")
         out["plain_order"] = plain_order_leg(kpm, ctx, A, D, args.workload, dict(w, M=M, nvec=nvec, block=block),
                                              3, 1, args.precision)
 
     if not args.no_extras:
         x = np.linspace(-10.0, 22.0, 200)
         if args.workload == HEADLINE:
+            _progress("large workload at equal accuracy")
             out["large_equal_accuracy"] = large_equal_accuracy_leg(kpm, ctx, A, D, synth)
             del D
             torch.cuda.empty_cache()
+        _progress("64^3 workload")
         A2, D2, w2 = load_workload(kpm, synth, "anderson3d_64^3_periodic_W16")
         leg = throughput_leg(kpm, ctx, A2, D2, "anderson3d_64^3_periodic_W16", w2["M"], w2["nvec"], w2["block"],
                              w2["seed"], w2["lz_seed"], 20, 3, locality=w2["locality"])
@@ -355,19 +359,26 @@ def main():
         if w2["locality"]:
             out["anderson3d_64"]["plain_order"] = plain_order_leg(kpm, ctx, A2, D2, "anderson3d_64^3_periodic_W16",
                                                                   w2, 10, 2)
+        _progress("64^3 workload at equal accuracy")
         out["fp32_learned_vs_fp64_jackson"] = equal_accuracy_leg(kpm, ctx, A2, D2, x)
+        _progress("uneven batch")
         setup = batched_uneven_setup(kpm, ctx, synth)
         out["batched_uneven_48"] = batched_leg(kpm, ctx, setup, tune=not args.no_autotune)
         out["batched_equal_accuracy"] = batched_equal_accuracy_leg(kpm, ctx, setup)
         del setup
+        _progress("stochastic Lanczos")
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A2, D2, x)
+        _progress("Legendre expansions")
         out["legendre_dgl"] = legendre_leg(kpm, ctx, D2, x, w2["M"], w2["nvec"], w2["block"], "f32")
+        _progress("damping network's training set")
         out["training_set"] = training_set_leg(kpm, ctx, synth)
         if not args.no_autotune:
             l2, u2 = leg["lb_ub"]
+            _progress("autotuner")
             out["autotune"] = autotune_leg(kpm, ctx, D2, l2, u2, w2["nvec"], leg["roofline"])
 
     if not args.no_cpu_baseline:
+        _progress("oracle on the host (CPU baseline)")
         out["cpu_baseline"] = cpu_baseline_leg(A, lb, ub, M, nvec, w["seed"], args, M)
     print(json.dumps(out))
 
@@ -402,6 +413,11 @@ def load_damping_network(kpm, ctx):
         raise RuntimeError(f"{kpm.DAMPING_WEIGHTS} is missing")
     kpm.kpm_mlp_load(ctx, kpm.DAMPING_WEIGHTS)
     return os.path.relpath(kpm.DAMPING_WEIGHTS, ROOT)
+
+
+def _progress(msg):
+    """One line on stderr as each part starts (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def _time_ms(fn, reps):
