@@ -375,7 +375,7 @@ def main():
         if not args.no_autotune:
             l2, u2 = leg["lb_ub"]
             _progress("autotuner")
-            out["autotune"] = autotune_leg(kpm, ctx, D2, l2, u2, w2["nvec"], leg["roofline"])
+            out["autotune"] = autotune_leg(kpm, ctx, D2, l2, u2, w2["nvec"], leg["roofline"], w2["locality"])
 
     if not args.no_cpu_baseline:
         _progress("oracle on the host (CPU baseline)")
@@ -632,11 +632,12 @@ def legendre_leg(kpm, ctx, D, x, M, nvec, block, precision, reps=5):
             "ms_heat_capacity_50_temperatures": round(t_cv, 3)}
 
 
-def autotune_leg(kpm, ctx, D, lb, ub, nvec, roof):
-    """The measured geometry choice for this workload next to the fixed
-    default the timed steps use (block 64, library panel height, gather 7)."""
-    t = kpm.kpm_autotune(ctx, D, lb, ub, nvec, seed=2002, precision="f32")
-    return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")},
+def autotune_leg(kpm, ctx, D, lb, ub, nvec, roof, locality):
+    """The measured geometry choice for this workload (in the numbering the
+    timed steps use) next to the fixed default those steps use (block 64,
+    library panel height, gather 7)."""
+    t = kpm.kpm_autotune(ctx, D, lb, ub, nvec, seed=2002, precision="f32", locality=locality)
+    return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")}, "locality_renumbering": locality,
             "us_per_step_chosen": round(t["us_per_step"], 2),
             "us_per_step_default": roof.get("avg_launch_us")}
 

@@ -242,15 +242,19 @@ kpm_status kpm_locality_order(int64_t n, int64_t nnz, const int32_t* row_ptr, co
  * measurement: for each candidate probe-block width (opts->block if set,
  * else 32/64/128 for KPM_FP32, 16/32/64 for KPM_FP64, capped at nvec), row
  * panel height (opts->rows_per_block if set, else the library's choice and
- * half and twice it) and gather batch (4, 7 or 8 CSR entries), time 6 fused
- * recurrence steps (section 3.1.1, eq. (3term)) on the context's stream and
+ * half and twice it) and gather batch (4, 7 or 8 CSR entries), time 16 fused
+ * recurrence steps (section 3.1.1, eq. (3term); after 8 untimed ones) on the
+ * context's stream and
  * keep the fastest per probe.  *best = *opts with block, rows_per_block and
  * the KPM_FLAG_GATHER4 / 7 / 8 bit set to the winner (pass it to
  * kpm_moments; results depend on the geometry only through rounding, and are
  * bitwise reproducible for a fixed geometry).  *us_per_step (nullable): the
  * winner's time per recurrence step for all nvec probes, in microseconds.
  * The choice is a measurement: repeated calls may pick different winners
- * among near-equal candidates.
+ * among near-equal candidates.  With KPM_FLAG_LOCALITY in opts->flags the
+ * steps run on the renumbered matrix kpm_moments uses under that flag (the
+ * flag stays set in *best); a structure changed since the renumbered copy
+ * was built is reported as for kpm_moments (KPM_ERR_ARG).
  */
 kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* A, double lb, double ub, const kpm_moment_opts* opts,
                         kpm_moment_opts* best, double* us_per_step);

@@ -520,9 +520,10 @@ def kpm_tridiag_eig(alpha, beta):
 
 
 def kpm_autotune(ctx: Context, A, lb: float, ub: float, nvec: int, seed: int = 0, precision="f32",
-                 block: int = 0, rows_per_block: int = 0) -> dict:
-    """Measured choice of block, rows_per_block and gather for kpm_moments on A."""
-    o = _opts(16, nvec, seed, precision, block, False, rows_per_block)
+                 block: int = 0, rows_per_block: int = 0, locality: bool = False) -> dict:
+    """Measured choice of block, rows_per_block and gather for kpm_moments on A
+    (on the renumbered matrix with locality=True: KPM_FLAG_LOCALITY)."""
+    o = _opts(16, nvec, seed, precision, block, False, rows_per_block, KPM_FLAG_LOCALITY if locality else 0)
     best = kpm_moment_opts()
     us = ctypes.c_double()
     c = A.as_c()

@@ -594,8 +594,10 @@ extern "C" kpm_status kpm_legendre_moments(kpm_ctx* ctx, const kpm_csr* A, doubl
 // ---------------------------------------------------------------- autotuner
 // Times the fused step on A for candidate (probe-block width, row-panel
 // height, gather batch) triples and returns the fastest per probe.  Each
-// candidate runs the first step and 2 warm-up steps, then kTuneSteps timed
-// steps between two events on the context's stream.
+// candidate runs the first step and kTuneWarm - 1 warm-up steps, then
+// kTuneSteps timed steps between two events on the context's stream.  With
+// KPM_FLAG_LOCALITY the steps run on the renumbered matrix kpm_moments would
+// use, and the flag stays set in the returned options.
 extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, double ub,
                                    const kpm_moment_opts* o, kpm_moment_opts* best, double* us_per_step) {
     if (!ctx) return KPM_ERR_ARG;
@@ -614,6 +616,13 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
     kpm_status st = kpm_prepare_csr(ctx, Ain, o->precision, &A, "");
     if (st != KPM_OK) return st;
     if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
+    const int32_t* rows = nullptr;
+    if (o->flags & KPM_FLAG_LOCALITY) {
+        if (!Ain->on_device) kpm_locality_free(ctx);  // host matrices live in reused workspace
+        CsrDev R;
+        if ((st = kpm_locality_view(ctx, A, &R, &rows)) != KPM_OK) return st;
+        A = R;
+    }
 
     const int nvec = o->nvec;
     std::vector<int> blocks;
@@ -628,7 +637,7 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
     const int esz = o->precision == KPM_FP64 ? 8 : 4;
     int ldmax = 0;
     for (int b : blocks) ldmax = std::max(ldmax, make_geom(A.n, b, o->precision, 0).ld);
-    constexpr int kTuneSteps = 6;
+    constexpr int kTuneWarm = 8, kTuneSteps = 16;
     void *X0, *X1, *part;
     if ((st = kpm_ws(ctx, "X0", (size_t)A.n * ldmax * esz, &X0)) != KPM_OK) return st;
     if ((st = kpm_ws(ctx, "X1", (size_t)A.n * ldmax * esz, &X1)) != KPM_OK) return st;
@@ -651,10 +660,10 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
                 g.gather = G;
                 const int grid = cheb_step_grid(A, o->precision, g);
                 if ((rs = kpm_ws(ctx, "partial", (size_t)grid * 2 * g.ld * 8, &part)) != KPM_OK) break;
-                hipError_t he = launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A.n, o->precision, 1, X0);
+                hipError_t he = launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A.n, o->precision, 1, X0, rows);
                 void* X[2] = {X0, X1};
-                for (int k = 0; he == hipSuccess && k < 3 + kTuneSteps; ++k) {
-                    if (k == 3) he = hipEventRecord(e0, ctx->stream);
+                for (int k = 0; he == hipSuccess && k < kTuneWarm + kTuneSteps; ++k) {
+                    if (k == kTuneWarm) he = hipEventRecord(e0, ctx->stream);
                     if (he == hipSuccess)
                         he = launch_cheb_step(ctx->stream, A, o->precision, k == 0, g, grid, X[k & 1], X[(k + 1) & 1],
                                               alpha, beta, (double*)part, (k & 1) != 0);
@@ -681,6 +690,7 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rs != KPM_OK) return rs;
+    if ((st = kpm_locality_check(ctx)) != KPM_OK) return st;
     *best = bo;
     if (us_per_step) *us_per_step = best_t * 1000.0 * nvec;
     return KPM_OK;

@@ -67,6 +67,14 @@ def test_autotune_single_matrix(ctx):
     # a fixed block width is kept; FP64 candidates
     t64 = kpm.kpm_autotune(ctx, dev(A, "f64"), lb, ub, 40, precision="f64", block=16)
     assert t64["block"] == 16
+    # on the renumbered matrix (KPM_FLAG_LOCALITY): the chosen geometry with
+    # the flag gives the oracle's moments
+    tl = kpm.kpm_autotune(ctx, D, lb, ub, 64, seed=5, locality=True)
+    _say(f"chosen with the locality renumbering {tl}")
+    assert tl["block"] in (32, 64) and tl["gather"] in (4, 7, 8) and tl["us_per_step"] > 0
+    mul = kpm.kpm_moments(ctx, D, lb, ub, 64, 64, 5, block=tl["block"], rows_per_block=tl["rows_per_block"],
+                          gather=tl["gather"], locality=True)
+    assert np.max(np.abs(mul - ref)) < 1e-5
 
 
 def test_autotune_batched(ctx):
