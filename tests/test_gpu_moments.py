@@ -533,3 +533,35 @@ def test_locality_refuses_malformed_structure_on_the_host(ctx):
     D = dev(A, "f32")
     _, pv = kpm.kpm_moments(ctx, D, -1.5, 9.5, 10, 4, 1, per_vector=True, locality=True)
     assert np.max(np.abs(pv - oracle_per_vec(A, -1.5, 9.5, 10, 4, 1, dtype="f32"))) < TOL32
+
+
+def test_probe_blocks_beyond_4_gib(ctx):
+    """Probe blocks of 4 GiB and more take the step kernel's 64-bit offsets:
+    3D Anderson 168^3 (n = 4,741,632, nnz = 33.2M) with one block of 256
+    FP32 probes (4.86 GB) and one of 128 FP64 probes (4.86 GB), degree 12;
+    probes 0, 1, 254 / 126, 127 against the oracle per probe at every degree
+    (1e-5 / 1e-12), every probe within |mu| <= 1, and the same probes in
+    blocks of 64 (32-bit offsets) agreeing with the wide block.  The batched
+    path refuses blocks of 4 GiB (its offsets are 32-bit)."""
+    A = synth.add_diagonal_disorder(synth.laplacian3d_periodic(168), 16.0, 1168)
+    assert A.n * 256 * 4 >= 1 << 32
+    lb, ub = -8.2, 20.2  # encloses [0 - 8, 12 + 8] (Gershgorin)
+    Ao = A.rounded_f32()
+    c, d = oracle.rescale(lb, ub)
+    for prec, nvec, tol, probes in (("f32", 256, TOL32, (0, 1, 254)), ("f64", 128, TOL64, (126, 127))):
+        D = dev(A, prec)
+        _say(f"168^3, one block of {nvec} {prec} probes")
+        mu, pv = kpm.kpm_moments(ctx, D, lb, ub, 12, nvec, 77, precision=prec, block=nvec, validate=False,
+                                 per_vector=True)
+        assert np.all(np.abs(pv) <= 1 + 1e-5) and mu[0] == 1.0
+        for l in probes:
+            z = oracle.moments_per_vector(Ao if prec == "f32" else A, c, d, 12, 1, 77, vec0=l, nthreads=2)[0] / A.n
+            assert np.max(np.abs(pv[l] - z)) < tol, (prec, l)
+        _, pv64 = kpm.kpm_moments(ctx, D, lb, ub, 12, nvec, 77, precision=prec, block=64 if prec == "f32" else 32,
+                                  validate=False, per_vector=True)
+        assert np.max(np.abs(pv64 - pv)) < tol
+        if prec == "f32":
+            with pytest.raises(kpm.KpmError) as e:
+                kpm.kpm_moments_batched(ctx, [D], [lb], [ub], 12, 256, 77, block=256)
+            assert e.value.status == -6
+        del D
