@@ -565,3 +565,35 @@ def test_probe_blocks_beyond_4_gib(ctx):
                 kpm.kpm_moments_batched(ctx, [D], [lb], [ub], 12, 256, 77, block=256)
             assert e.value.status == -6
         del D
+
+
+def _arrow(n, seed):
+    """Random sparse symmetric (about 10 entries per row) plus a dense row
+    and column 0 (an arrow): one row of n entries, every other row one more."""
+    import scipy.sparse as sp
+    R = synth.random_sparse_symmetric(n, 4.5, seed).to_scipy().tolil()
+    rng = np.random.default_rng(seed)
+    v = rng.normal(0.0, 0.3, n - 1)
+    R[0, 1:] = v
+    R[1:, 0] = v[:, None]
+    return synth._from_scipy(sp.csr_matrix(R))
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", TOL32), ("f64", TOL64)])
+def test_long_rows_take_the_unstaged_path(ctx, prec, tol):
+    """Row panels whose CSR slice does not fit the step's LDS staging read
+    the CSR directly: an arrow matrix (n = 3,000, one row of 3,000 entries,
+    the others about 11: staged panels beside one unstaged panel) and a
+    random symmetric matrix with about 200 entries in every row (every
+    panel unstaged); per-probe moments against the oracle, degree 60."""
+    mats = [_arrow(3000, 41), synth.random_sparse_symmetric(3000, 100.0, 42, off_scale=0.1)]
+    assert mats[0].row_ptr[1] - mats[0].row_ptr[0] == 3000
+    assert np.min(np.diff(mats[1].row_ptr)) > 120
+    for A in mats:
+        D = dev(A, prec)
+        lb, ub = kpm.kpm_bounds(ctx, D, 20, 3, 0.01)
+        lam = np.linalg.eigvalsh(A.dense())
+        if not (lb <= lam[0] and lam[-1] <= ub):  # a 20-step run can miss an outlying edge
+            lb, ub = lam[0] - 0.05 * (lam[-1] - lam[0]), lam[-1] + 0.05 * (lam[-1] - lam[0])
+        _, pv = kpm.kpm_moments(ctx, D, lb, ub, 60, 10, 9, precision=prec, per_vector=True)
+        assert np.max(np.abs(pv - oracle_per_vec(A, lb, ub, 60, 10, 9, dtype=prec))) < tol
