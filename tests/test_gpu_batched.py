@@ -356,3 +356,36 @@ def test_on_chip_high_degree(ctx, dtype, tol):
         ref = oracle_mu(A, lb[m], ub[m], M, nvec, 900 + m, dtype)
         assert np.max(np.abs(mu[m] - ref)) < tol, m
         assert np.max(np.abs(mu[m] - mu_s[m])) < tol, m
+
+
+def _arrow(n, seed):
+    """Random sparse symmetric (about 10 entries per row) plus a dense row and
+    column 0: one row of n entries beside short ones."""
+    import scipy.sparse as sp
+    R = synth.random_sparse_symmetric(n, 4.5, seed).to_scipy().tolil()
+    v = np.random.default_rng(seed).normal(0.0, 0.3, n - 1)
+    R[0, 1:] = v
+    R[1:, 0] = v[:, None]
+    return synth._from_scipy(sp.csr_matrix(R))
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("f64", 1e-12)])
+@pytest.mark.parametrize("path,block", [("stream", 0), ("resident", 4)])
+def test_long_rows(ctx, dtype, tol, path, block):
+    """Long rows on both device paths: an arrow matrix (one row of 2,000
+    entries beside short rows: streaming panels staged in LDS beside one
+    read directly; on chip a first slice 2,000 slots wide) and a random
+    symmetric matrix with about 200 entries in every row, against the
+    oracle."""
+    mats = [_arrow(2000, 61), synth.random_sparse_symmetric(2000, 100.0, 62, off_scale=0.1),
+            synth.laplacian2d_dirichlet(20)]
+    lb, ub = [], []
+    for A in mats:
+        lam = np.linalg.eigvalsh(A.dense())
+        w = lam[-1] - lam[0]
+        lb.append(lam[0] - 0.02 * w)
+        ub.append(lam[-1] + 0.02 * w)
+    D = [dev(A, dtype) for A in mats]
+    mu = kpm.kpm_moments_batched(ctx, D, lb, ub, 45, 6, 70, precision=dtype, block=block, validate=True, path=path)
+    for m, A in enumerate(mats):
+        assert np.max(np.abs(mu[m] - oracle_mu(A, lb[m], ub[m], 45, 6, 70 + m, dtype))) < tol, m

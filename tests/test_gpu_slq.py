@@ -151,3 +151,30 @@ def test_locality_renumbering_parity(ctx, dtype):
         ra, rb = oracle.lanczos_tridiag(Ao, c, d, M, 1, seed, vec0=l)
         assert np.max(np.abs(al[l] - ra[0])) < 1e-11, l
         assert np.max(np.abs(be[l] - rb[0])) < 1e-11, l
+
+
+def _arrow(n, seed):
+    """Random sparse symmetric (about 10 entries per row) plus a dense row and
+    column 0: one row of n entries beside short ones."""
+    import scipy.sparse as sp
+    R = synth.random_sparse_symmetric(n, 4.5, seed).to_scipy().tolil()
+    v = np.random.default_rng(seed).normal(0.0, 0.3, n - 1)
+    R[0, 1:] = v
+    R[1:, 0] = v[:, None]
+    return synth._from_scipy(sp.csr_matrix(R))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_long_rows_take_the_unstaged_path(ctx, dtype):
+    """Row panels whose CSR slice does not fit the LDS staging read the CSR
+    directly: an arrow matrix (one row of 2,500 entries beside short rows)
+    and a random symmetric matrix with about 200 entries in every row.  The
+    arrow's isolated extreme eigenvalue converges within a few steps, after
+    which the plain recurrence (no re-orthogonalisation, section 3.2.1)
+    amplifies rounding by about ten per step (from step 20 on two summation
+    orders part at 1e-14, growing to O(1) by step 30), so it is compared
+    over 12 steps; the other matrix over 40."""
+    for A, M in ((_arrow(2500, 51), 12), (synth.random_sparse_symmetric(2500, 100.0, 52, off_scale=0.1), 40)):
+        lam = np.linalg.eigvalsh(A.dense())
+        w = lam[-1] - lam[0]
+        _check(A, dtype, lam[0] - 0.02 * w, lam[-1] + 0.02 * w, M, 6, 11, block=4, ctx=ctx)
