@@ -567,9 +567,14 @@ kpm_status kpm_mlp_load(kpm_ctx* ctx, const char* path);
 kpm_status kpm_hbm_copy_probe(kpm_ctx* ctx, int64_t bytes, int iters, double* gbs);
 
 /* ---- device timing of the library's own kernels ----
- * When enabled, every launch of the listed kernels is bracketed by HIP
- * events on the context's stream.  kernel: "cheb_step" (fused recurrence
- * step, the dominant kernel), "cheb_first", "lanczos", "batched". */
+ * When enabled, the launches of the listed kernels are bracketed by HIP
+ * events on the stream they run on.  kernel: "cheb_step" (fused recurrence
+ * steps, the dominant kernel: one record per run of steps, counting its
+ * launches), "cheb_first" (first steps), "lanczos" (a bounds run),
+ * "batched" (one batched call's launch sequence), "slq_step" (a stochastic
+ * Lanczos run's steps), "copy_probe".  Query waits for the context's stream
+ * and returns the launches and their total time since the last reset (a
+ * name never timed reads 0 launches). */
 kpm_status kpm_profile_enable(kpm_ctx* ctx, int enable);
 kpm_status kpm_profile_query(kpm_ctx* ctx, const char* kernel, int64_t* launches, double* total_ms);
 kpm_status kpm_profile_reset(kpm_ctx* ctx);
