@@ -440,26 +440,33 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
     nvec = 64
 
     # both forms as one library call each (bounds, moments, damping, density)
-    def fp64_jackson(block=0):
+    def fp64_jackson(block=0, locality=False):
         return kpm.kpm_dos_pipeline(ctx, D64, M_FP64_JACKSON, nvec, 2002, x, precision="f64",
-                                    damping=kpm.KPM_DAMP_JACKSON, block=block)[0]
+                                    damping=kpm.KPM_DAMP_JACKSON, block=block, locality=locality)[0]
 
-    def fp32_learned():
+    def fp32_learned(locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_FP32_LEARNED, nvec, 2002, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_LEARNED)[0]
+                                    damping=kpm.KPM_DAMP_LEARNED, locality=locality)[0]
 
-    def fp32_none():
+    def fp32_none(locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_FP32_NONE, nvec, 2002, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_NONE)[0]
+                                    damping=kpm.KPM_DAMP_NONE, locality=locality)[0]
 
     lb, ub = kpm.kpm_bounds(ctx, D32, 20, 3002, 0.01)
     # the FP64 baseline at its faster probe block (32 is the default; 64 wins on
     # matrices whose gathers miss the caches anyway)
-    t64_by_block = {b: _time_ms(lambda b=b: fp64_jackson(b), reps) for b in (32, 64)}
-    b64 = min(t64_by_block, key=t64_by_block.get)
-    t64 = t64_by_block[b64]
-    t32 = _time_ms(fp32_learned, reps)
-    t32n = _time_ms(fp32_none, reps)
+    # every form at its own best options: probe block (FP64) and the
+    # library's locality renumbering (which gathers the values into the
+    # renumbered copy and checks the structure at every call)
+    t64_by = {f"{b}{'+locality' if loc else ''}": _time_ms(lambda b=b, loc=loc: fp64_jackson(b, loc), reps)
+              for loc in (False, True) for b in (32, 64)}
+    t32_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_learned(loc), reps)
+              for loc in (False, True)}
+    t32n_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_none(loc), reps)
+               for loc in (False, True)}
+    best64 = min(t64_by, key=t64_by.get)
+    t64, t32, t32n = t64_by[best64], min(t32_by.values()), min(t32n_by.values())
+    b64 = int(best64.split("+")[0])
     m64 = _time_ms(lambda: kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64",
                                            block=b64, validate=False), reps)
     m32 = _time_ms(lambda: kpm.kpm_moments(ctx, D32, lb, ub, M_FP32_LEARNED, nvec, 2002, precision="f32",
@@ -477,8 +484,12 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
             "M_fp64_jackson": M_FP64_JACKSON, "M_fp32_learned": M_FP32_LEARNED, "M_fp32_none": M_FP32_NONE,
             "ms_fp64_jackson_pipeline": round(t64, 3), "ms_fp32_learned_pipeline": round(t32, 3),
             "ms_fp32_none_pipeline": round(t32n, 3),
-            "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 3) for b, t in t64_by_block.items()},
+            "ms_fp64_jackson_pipeline_by_option": {k: round(t, 3) for k, t in t64_by.items()},
+            "ms_fp32_learned_pipeline_by_option": {k: round(t, 3) for k, t in t32_by.items()},
+            "ms_fp32_none_pipeline_by_option": {k: round(t, 3) for k, t in t32n_by.items()},
             "speedup_pipeline": round(t64 / t32, 2), "speedup_pipeline_fp32_none": round(t64 / t32n, 2),
+            "speedup_pipeline_same_options": {k: round(t64_by[f"{b64}{'+locality' if k == 'locality' else ''}"]
+                                                       / t32_by[k], 2) for k in t32_by},
             "ms_fp64_moments": round(m64, 3), "ms_fp32_moments": round(m32, 3),
             "speedup_moments": round(m64 / m32, 2),
             "fp64_block": b64, "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
@@ -555,23 +566,30 @@ def large_equal_accuracy_leg(kpm, ctx, A, D32, synth, reps=3):
     nvec = 256
     weights = load_damping_network(kpm, ctx)
 
-    def fp64_jackson(block=0):
+    def fp64_jackson(block=0, locality=False):
         phi, _, _, _ = kpm.kpm_dos_pipeline(ctx, D64, M_LARGE_FP64_JACKSON, nvec, 2005, x, precision="f64",
-                                            damping=kpm.KPM_DAMP_JACKSON, lanczos_seed=3005, block=block)
+                                            damping=kpm.KPM_DAMP_JACKSON, lanczos_seed=3005, block=block,
+                                            locality=locality)
         return phi
 
-    def fp32_learned():
+    def fp32_learned(locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_LEARNED, nvec, 2005, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005)[0]
+                                    damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005, locality=locality)[0]
 
-    def fp32_none():
+    def fp32_none(locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_NONE, nvec, 2005, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_NONE, lanczos_seed=3005)[0]
+                                    damping=kpm.KPM_DAMP_NONE, lanczos_seed=3005, locality=locality)[0]
 
-    t64_by_block = {b: _time_ms(lambda b=b: fp64_jackson(b), reps) for b in (32, 64)}  # the faster is the baseline
-    t64 = min(t64_by_block.values())
-    t32 = _time_ms(fp32_learned, reps)
-    t32n = _time_ms(fp32_none, reps)
+    # every form at its own best options (probe block for FP64, locality
+    # renumbering or not)
+    t64_by = {f"{b}{'+locality' if loc else ''}": _time_ms(lambda b=b, loc=loc: fp64_jackson(b, loc), reps)
+              for loc in (False, True) for b in (32, 64)}
+    t32_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_learned(loc), reps)
+              for loc in (False, True)}
+    t32n_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_none(loc), reps)
+               for loc in (False, True)}
+    best64 = min(t64_by, key=t64_by.get)
+    t64, t32, t32n = t64_by[best64], min(t32_by.values()), min(t32n_by.values())
     del D64
     return {"criterion": "L1(sigma=0.02) <= 1e-2 against the FP64 oracle's degree-512 series, same probes",
             "accuracy_source": "tests/test_gpu_accuracy.py::test_fp32_learned_vs_fp64_jackson_on_large",
@@ -580,7 +598,9 @@ def large_equal_accuracy_leg(kpm, ctx, A, D32, synth, reps=3):
             "M_fp32_none": M_LARGE_FP32_NONE,
             "ms_fp64_jackson_pipeline": round(t64, 2), "ms_fp32_learned_pipeline": round(t32, 2),
             "ms_fp32_none_pipeline": round(t32n, 2),
-            "ms_fp64_jackson_pipeline_by_block": {str(b): round(t, 2) for b, t in t64_by_block.items()},
+            "ms_fp64_jackson_pipeline_by_option": {k: round(t, 2) for k, t in t64_by.items()},
+            "ms_fp32_learned_pipeline_by_option": {k: round(t, 2) for k, t in t32_by.items()},
+            "ms_fp32_none_pipeline_by_option": {k: round(t, 2) for k, t in t32n_by.items()},
             "speedup_pipeline": round(t64 / t32, 2), "speedup_pipeline_fp32_none": round(t64 / t32n, 2)}
 
 

@@ -462,7 +462,8 @@ static kpm_status moments_impl(kpm_ctx* ctx, const kpm_csr* Ain, double lb, doub
         // not trusted across calls
         if (!Ain->on_device) kpm_locality_free(ctx);
         CsrDev R;
-        if ((st = kpm_locality_view(ctx, A, &R, &rows)) != KPM_OK) return st;
+        // the pipeline's prefill of the first block refreshed the view already
+        if ((st = kpm_locality_view(ctx, A, &R, &rows, !block0_filled)) != KPM_OK) return st;
         A = R;
     }
 
@@ -616,11 +617,11 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
     kpm_status st = kpm_prepare_csr(ctx, Ain, o->precision, &A, "");
     if (st != KPM_OK) return st;
     if (o->validate && (st = kpm_validate_csr(ctx, A)) != KPM_OK) return st;
-    const int32_t* rows = nullptr;
+    const int32_t* orig_rows = nullptr;  // original index of each renumbered row
     if (o->flags & KPM_FLAG_LOCALITY) {
         if (!Ain->on_device) kpm_locality_free(ctx);  // host matrices live in reused workspace
         CsrDev R;
-        if ((st = kpm_locality_view(ctx, A, &R, &rows)) != KPM_OK) return st;
+        if ((st = kpm_locality_view(ctx, A, &R, &orig_rows)) != KPM_OK) return st;
         A = R;
     }
 
@@ -660,7 +661,8 @@ extern "C" kpm_status kpm_autotune(kpm_ctx* ctx, const kpm_csr* Ain, double lb, 
                 g.gather = G;
                 const int grid = cheb_step_grid(A, o->precision, g);
                 if ((rs = kpm_ws(ctx, "partial", (size_t)grid * 2 * g.ld * 8, &part)) != KPM_OK) break;
-                hipError_t he = launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A.n, o->precision, 1, X0, rows);
+                hipError_t he =
+                    launch_rademacher(ctx->stream, o->seed, 0, b, g.ld, A.n, o->precision, 1, X0, orig_rows);
                 void* X[2] = {X0, X1};
                 for (int k = 0; he == hipSuccess && k < kTuneWarm + kTuneSteps; ++k) {
                     if (k == kTuneWarm) he = hipEventRecord(e0, ctx->stream);

@@ -150,7 +150,11 @@ void kpm_batch_free(kpm_ctx* ctx);
 // KPM_FLAG_LOCALITY: the matrix renumbered along a Morton curve of its grid
 // when kpm_locality_order finds one (*out = the renumbered view, *orig = the
 // original index of each of its rows), else *out = A and *orig = NULL.
-kpm_status kpm_locality_view(kpm_ctx* ctx, const kpm::CsrDev& A, kpm::CsrDev* out, const int32_t** orig);
+// Each refresh enqueues a checksum of the current structure and gathers the
+// current values; refresh = false returns the copy as refreshed earlier in
+// the same call (nothing enqueued).
+kpm_status kpm_locality_view(kpm_ctx* ctx, const kpm::CsrDev& A, kpm::CsrDev* out, const int32_t** orig,
+                             bool refresh = true);
 void kpm_locality_free(kpm_ctx* ctx);
 // After a call that used kpm_locality_view has been waited for: KPM_ERR_ARG
 // (and the cached copy dropped) when the matrix's structure at the cached

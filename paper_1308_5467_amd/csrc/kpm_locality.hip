@@ -148,17 +148,20 @@ struct kpm_locality_state {
     int32_t *rp2 = nullptr, *ci2 = nullptr, *src = nullptr, *orig = nullptr;
     void* val2 = nullptr;
     unsigned long long* d_sum = nullptr;  // checksum of the current call's structure
+    unsigned long long* h_sum = nullptr;  // its copy in page-locked host memory
     bool check_pending = false;
 };
 
 void kpm_locality_free(kpm_ctx* ctx) {
     if (!ctx->loc) return;
+    if (ctx->loc->mem || ctx->loc->h_sum) hipStreamSynchronize(ctx->stream);  // a pending copy may target h_sum
     if (ctx->loc->mem) hipFree(ctx->loc->mem);
+    if (ctx->loc->h_sum) hipHostFree(ctx->loc->h_sum);
     delete ctx->loc;
     ctx->loc = nullptr;
 }
 
-kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const int32_t** orig) {
+kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const int32_t** orig, bool refresh) {
     *out = A;
     *orig = nullptr;
     kpm_locality_state*& L = ctx->loc;
@@ -221,6 +224,11 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
             kpm_locality_free(ctx);
             return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the renumbered matrix failed");
         }
+        if (hipHostMalloc((void**)&L->h_sum, sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+            L->h_sum = nullptr;
+            kpm_locality_free(ctx);
+            return kpm_fail(ctx, KPM_ERR_ALLOC, "hipHostMalloc for the structure checksum failed");
+        }
         char* p = static_cast<char*>(L->mem);
         L->rp2 = reinterpret_cast<int32_t*>(p);
         L->ci2 = reinterpret_cast<int32_t*>(p + b_rp);
@@ -242,12 +250,22 @@ kpm_status kpm_locality_view(kpm_ctx* ctx, const CsrDev& A, CsrDev* out, const i
         L->n = A.n;
     }
     if (!L->structured) return KPM_OK;
-    // the checksum of the current structure, compared with the plan's when
-    // the results are collected (kpm_locality_check)
+    if (!refresh && L->check_pending) {
+        // refreshed earlier in the same call (checksum and values enqueued)
+        out->rp = L->rp2;
+        out->ci = L->ci2;
+        out->val = L->val2;
+        *orig = L->orig;
+        return KPM_OK;
+    }
+    // the checksum of the current structure, copied to page-locked host
+    // memory behind it and compared with the plan's once the caller has
+    // waited for its results (kpm_locality_check)
     clear_sum_kernel<<<1, 1, 0, ctx->stream>>>(L->d_sum);
     structure_sum_kernel<<<(int)std::min<int64_t>(2048, (A.nnz + A.n + 256) / 256), 256, 0, ctx->stream>>>(
         A.rp, A.n, A.ci, A.nnz, L->d_sum);
     KPM_HIP(ctx, hipGetLastError());
+    KPM_HIP(ctx, hipMemcpyAsync(L->h_sum, L->d_sum, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
     L->check_pending = true;
     // the current values, in the renumbered order
     if (A.nnz > 0) {
@@ -271,10 +289,8 @@ kpm_status kpm_locality_check(kpm_ctx* ctx) {
     kpm_locality_state* L = ctx->loc;
     if (!L || !L->check_pending) return KPM_OK;
     L->check_pending = false;
-    unsigned long long got = 0;
-    KPM_HIP(ctx, hipMemcpyAsync(&got, L->d_sum, 8, hipMemcpyDeviceToHost, ctx->stream));
-    KPM_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if ((uint64_t)got != L->sum) {
+    // the caller has waited for its stream, and so for the checksum's copy
+    if ((uint64_t)*L->h_sum != L->sum) {
         kpm_locality_free(ctx);  // rebuilt from the current structure on the next call
         return kpm_fail(ctx, KPM_ERR_ARG,
                         "the matrix's sparsity structure changed since its renumbered copy was built (same address "
