@@ -425,10 +425,32 @@ def kpm_slq_heat_capacity(ctx: Context, theta, tau2, T) -> np.ndarray:
     return cv
 
 
+class MatrixBatch:
+    """The device matrices of batched calls with their C descriptors built
+    once: calls that pass the same MatrixBatch skip rebuilding them (for
+    thousands of matrices that costs tens of ms per call).  The descriptors
+    hold the tensors' addresses: after replacing a matrix's tensors, build
+    a new MatrixBatch (values changed in place need nothing)."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        self.arr = (kpm_csr * len(self.mats))(*[m.as_c() for m in self.mats])
+
+    def __len__(self):
+        return len(self.mats)
+
+
+def _batch_arr(mats):
+    if isinstance(mats, MatrixBatch):
+        return mats.arr
+    return (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+
+
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",
                         block: int = 0, validate: bool = False, graph: bool = True, rows_per_block: int = 0,
                         return_max_abs: bool = False, path: str = "auto"):
-    """Moments [nmat, M+1] of several device-resident matrices.
+    """Moments [nmat, M+1] of several device-resident matrices (a list of
+    DeviceCSR or a MatrixBatch).
 
     path: "auto" (the on-chip path when block is 0 and every matrix fits it,
     else streaming), "stream" or "resident" (KPM_FLAG_BATCH_STREAM /
@@ -440,7 +462,7 @@ def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int
     if not graph:
         flags |= KPM_FLAG_NO_GRAPH
     o = _opts(M, nvec, seed, precision, block, validate, rows_per_block, flags)
-    arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+    arr = _batch_arr(mats)
     lbv, ubv = _f64(lb), _f64(ub)
     mu = np.zeros((len(mats), M + 1))
     mx = np.zeros(len(mats))
@@ -538,7 +560,7 @@ def kpm_autotune_batched(ctx: Context, mats, lb, ub, nvec: int, seed: int = 0, p
                          block: int = 0, rows_per_block: int = 0) -> dict:
     """Measured choice of block and rows_per_block for kpm_moments_batched."""
     o = _opts(16, nvec, seed, precision, block, False, rows_per_block)
-    arr = (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+    arr = _batch_arr(mats)
     lbv, ubv = _f64(lb), _f64(ub)
     best = kpm_moment_opts()
     us = ctypes.c_double()

@@ -389,3 +389,24 @@ def test_long_rows(ctx, dtype, tol, path, block):
     mu = kpm.kpm_moments_batched(ctx, D, lb, ub, 45, 6, 70, precision=dtype, block=block, validate=True, path=path)
     for m, A in enumerate(mats):
         assert np.max(np.abs(mu[m] - oracle_mu(A, lb[m], ub[m], 45, 6, 70 + m, dtype))) < tol, m
+
+
+def test_matrix_batch_descriptors_built_once(ctx):
+    """A MatrixBatch (descriptors built once) gives bitwise the moments of the
+    plain list, on both paths; values changed in place are seen by the next
+    call through the same MatrixBatch."""
+    import torch
+    mats = small_set()
+    lb, ub = bounds_of(mats, "f32")
+    D = [dev(A, "f32") for A in mats]
+    batch = kpm.MatrixBatch(D)
+    assert len(batch) == len(D)
+    for path in ("stream", "resident"):
+        a = kpm.kpm_moments_batched(ctx, D, lb, ub, 30, 8, 3, path=path)
+        b = kpm.kpm_moments_batched(ctx, batch, lb, ub, 30, 8, 3, path=path)
+        assert np.array_equal(a, b), path
+    D[0].val.mul_(0.5)
+    A0 = synth.CSR(mats[0].n, mats[0].row_ptr, mats[0].col_idx, mats[0].val * 0.5)
+    mu = kpm.kpm_moments_batched(ctx, batch, lb, ub, 30, 8, 3)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(mu[0] - oracle_mu(A0, lb[0], ub[0], 30, 8, 3, "f32"))) < 1e-5
