@@ -16,8 +16,10 @@ density and the blurred exact density, on npts midpoints of [-1, 1]:
     phi_tilde_sigma = K (g * mu),   K[i, k] = <w_k T_k / (pi sqrt(1-t^2)), g_sigma(t_i - .)>
 
 with w_0 = 1, w_k = 2 (eq. (expmu) and (tdosFinal), blurred as in section 4).
-Parity of this part with the paper is unpinned (the paper has no learned
-part); it is pinned by finite differences and by plain library calls.
+Parity unpinned (against the paper): the paper has no learned part.  The
+oracle is pinned instead by central finite differences (backward), plain
+torch CPU layers (forward) and hand-worked steps of the published Adam
+algorithm (Kingma & Ba 2015) for the update.
 """
 from __future__ import annotations
 
