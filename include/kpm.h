@@ -105,16 +105,24 @@ enum {
     KPM_FLAG_LOCALITY = 128,      /* kpm_moments, kpm_legendre_moments,
                               kpm_dos_pipeline, kpm_slq (the Lanczos run on
                               P A P^T from P v has the same tridiagonal
-                              matrix): when the matrix comes from a
-                              2D or 3D grid numbered lexicographically (found
-                              by kpm_locality_order), run on it renumbered
-                              along the grid's Morton curve, probes at the
-                              original indices: the same moments up to
-                              rounding, plane-apart neighbours close in the
-                              probe block.  The renumbered structure is
-                              cached per matrix address in the context
-                              (values are re-read at every call; the
-                              structure at an address must not change)     */
+                              matrix), kpm_autotune: when the matrix comes
+                              from a 2D or 3D grid numbered lexicographically
+                              (found by kpm_locality_order), run on it
+                              renumbered along the grid's Morton curve,
+                              probes at the original indices: the same
+                              moments up to rounding, plane-apart neighbours
+                              close in the probe block.  The renumbered
+                              structure is built on the host (the whole CSR
+                              is checked there first: KPM_ERR_ARG if
+                              malformed) and cached in the context per
+                              matrix address, sizes and value type; values
+                              are re-read at every call.  A structure
+                              rewritten in place at the same address is
+                              detected by a checksum when the call's results
+                              are collected (KPM_ERR_ARG) and the copy is
+                              rebuilt on the next call.  Not accepted by
+                              kpm_moments_noalloc (the copy is allocated) or
+                              with KPM_FLAG_LEGENDRE_RECURRENCE              */
     KPM_FLAG_LEGENDRE_RECURRENCE = 16 /* kpm_legendre_moments: run the
                               Legendre three-term recurrence of Algorithm DGL
                               (M sparse products per block) instead of
