@@ -366,6 +366,8 @@ def main():
         out["batched_uneven_48"] = batched_leg(kpm, ctx, setup, tune=not args.no_autotune)
         out["batched_equal_accuracy"] = batched_equal_accuracy_leg(kpm, ctx, setup)
         del setup
+        _progress("small workload")
+        out["small_lap2d_32"] = small_matrix_leg(kpm, ctx, synth)
         _progress("stochastic Lanczos")
         out["stochastic_lanczos"] = slq_leg(kpm, ctx, A2, D2, x)
         _progress("Legendre expansions")
@@ -660,6 +662,33 @@ def autotune_leg(kpm, ctx, D, lb, ub, nvec, roof, locality):
     return {"chosen": {k: t[k] for k in ("block", "rows_per_block", "gather")}, "locality_renumbering": locality,
             "us_per_step_chosen": round(t["us_per_step"], 2),
             "us_per_step_default": roof.get("avg_launch_us")}
+
+
+def small_matrix_leg(kpm, ctx, synth, reps=50):
+    """The small workload: 2D Dirichlet Laplacian 32 x 32 (n = 1,024), degree
+    100, 20 FP64 probes -- bound by latency, not memory (its probe blocks are
+    a few hundred KB).  Timed: the moment call on the single-matrix path (one
+    launch per recurrence step) and the same matrix through the batched call
+    on its on-chip path (one launch for all steps: the vectors stay in LDS),
+    with the descriptors built once; the whole path (bounds, moments,
+    Jackson, density at 200 points) as one call."""
+    A = synth.config_matrix("c1")
+    D = kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val, "f64")
+    lb, ub = kpm.kpm_bounds(ctx, D, 20, 3001, 0.01)
+    M, nvec = 100, 20
+    batch = kpm.MatrixBatch([D])
+    x = np.linspace(lb, ub, 200)
+    t_single = _time_ms(lambda: kpm.kpm_moments(ctx, D, lb, ub, M, nvec, 2001, precision="f64", validate=False),
+                        reps)
+    t_onchip = _time_ms(lambda: kpm.kpm_moments_batched(ctx, batch, [lb], [ub], M, nvec, 2001, precision="f64",
+                                                        path="resident"), reps)
+    t_pipe = _time_ms(lambda: kpm.kpm_dos_pipeline(ctx, D, M, nvec, 2001, x, precision="f64", lanczos_seed=3001),
+                      reps)
+    units = A.nnz * M * nvec
+    return {"workload": "lap2d_dirichlet_32x32", "n": A.n, "nnz": A.nnz, "M": M, "nvec": nvec, "precision": "f64",
+            "ms_moments_single_matrix_path": round(t_single, 4), "ms_moments_on_chip_path": round(t_onchip, 4),
+            "units_per_s_single": units / (t_single * 1e-3), "units_per_s_on_chip": units / (t_onchip * 1e-3),
+            "ms_pipeline": round(t_pipe, 4)}
 
 
 def batched_uneven_bounds(kpm, ctx, D):
