@@ -250,7 +250,8 @@ def cpu_baseline_leg(A, lb, ub, M, nvec, seed, args, full_M):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
     nv = min(nvec, args.cpu_sample_vectors or cores)
-    Ms = args.cpu_sample_degree or (100 if full_M > 256 else full_M)
+    # degree 200 of the large workload's 1000: about 15 s of host work
+    Ms = args.cpu_sample_degree or (200 if full_M > 256 else full_M)
     Ao = A.rounded_f32()
     c, d = oracle.rescale(lb, ub)
     ts = time.perf_counter()
