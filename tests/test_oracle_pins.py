@@ -9,6 +9,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 from scipy import integrate
 
 import oracle
@@ -31,6 +32,16 @@ def _read_golden(name):
 def test_splitmix64_published_outputs():
     for k, hexval in _read_golden("splitmix64_seed0.txt"):
         assert oracle.splitmix64_nth(0, int(k)) == int(hexval, 16)
+
+
+def test_probe_signs_from_published_outputs():
+    """Entry i of probe 0 of seed 0 is the sign of output i + 1 of SplitMix64
+    from state 0 (-1 when its top bit is set): the probe definition checked
+    against the published outputs, not against the oracle's own generator."""
+    rows = _read_golden("splitmix64_seed0.txt")
+    expect = [-1.0 if int(hexval, 16) >> 63 else 1.0 for _, hexval in rows]
+    assert [int(k) for k, _ in rows] == list(range(1, len(rows) + 1))
+    assert list(oracle.rademacher(0, 0, len(rows))) == expect
 
 
 def test_rademacher_statistics():
@@ -188,6 +199,50 @@ def test_lanczos_full_length_gives_eigenvalues():
     b = oracle.lanczos_bounds(A, 12, 8, margin=0.0)
     lam = np.linalg.eigvalsh(A.dense())
     assert np.allclose(np.sort(b["theta"]), lam, atol=1e-9)
+
+
+def test_lanczos_bounds_are_ritz_values_widened_by_their_residuals():
+    """[lb0, ub0] = [theta_1 - r_1, theta_m + r_m] with r_j the residual norm
+    ||A u_j - theta_j u_j|| of the Ritz pair: checked against Rayleigh-Ritz
+    on an orthonormal basis of the same Krylov space built independently
+    (QR of [q, Aq, ..., A^{m-1} q]) and residuals computed directly."""
+    A = synth.random_sparse_symmetric(40, 3.0, 12)
+    m = 8
+    b = oracle.lanczos_bounds(A, m, 5)
+    assert b["steps"] == m and not b["breakdown"]
+    S = A.dense()
+    q = oracle.rademacher(5, oracle.LANCZOS_START_ID, A.n)
+    K = np.empty((A.n, m))
+    K[:, 0] = q / np.linalg.norm(q)
+    for j in range(1, m):
+        K[:, j] = S @ K[:, j - 1]
+        K[:, j] /= np.linalg.norm(K[:, j])
+    Q, _ = np.linalg.qr(K)
+    theta, Z = np.linalg.eigh(Q.T @ S @ Q)
+    U = Q @ Z
+    r = np.linalg.norm(S @ U - U * theta, axis=0)
+    width = theta[-1] - theta[0]
+    assert abs(b["lb0"] - (theta[0] - r[0])) < 1e-7 * width
+    assert abs(b["ub0"] - (theta[-1] + r[-1])) < 1e-7 * width
+
+
+def test_lanczos_breakdown_merges_the_gershgorin_hull():
+    """An eigenvector orthogonal to the start vector is invisible to Lanczos:
+    A couples two coordinates i, j where the start vector has equal signs
+    (eigenvalues +1 along e_i + e_j, -1 along e_i - e_j) and is diagonal in
+    [0.5, 2] elsewhere.  The run breaks down without seeing -1; the merged
+    Gershgorin hull [-1, ...] restores the enclosure."""
+    n, seed = 6, 3
+    v = oracle.rademacher(seed, oracle.LANCZOS_START_ID, n)
+    i, j = next((a, b) for a in range(n) for b in range(a + 1, n) if v[a] == v[b])
+    D = np.diag(np.linspace(0.5, 2.0, n))
+    D[i, i] = D[j, j] = 0.0
+    D[i, j] = D[j, i] = 1.0
+    A = synth._from_scipy(sp.csr_matrix(D))
+    assert abs(np.linalg.eigvalsh(D)[0] + 1.0) < 1e-12
+    b = oracle.lanczos_bounds(A, 20, seed)
+    assert b["breakdown"]
+    assert b["lb"] <= -1.0 and b["ub"] >= 2.0
 
 
 def test_lanczos_breakdown_on_diagonal_uses_gershgorin():
