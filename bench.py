@@ -122,6 +122,8 @@ def parse():
                          "Gershgorin hull widened by 1 %% (fewer launches when profiling)")
     ap.add_argument("--legendre-only", action="store_true",
                     help="only the Legendre / Delta-Gauss-Legendre leg")
+    ap.add_argument("--small-only", action="store_true",
+                    help="only the small 32 x 32 Laplacian workload (FP64, degree 100, 20 probes)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the 48-matrix batched leg (profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -284,6 +286,9 @@ def main():
         setup = batched_uneven_setup(kpm, ctx, synth)
         print(json.dumps({"batched_uneven_48": batched_leg(kpm, ctx, setup, tune=not args.no_autotune),
                           "batched_equal_accuracy": batched_equal_accuracy_leg(kpm, ctx, setup)}))
+        return
+    if args.small_only:
+        print(json.dumps({"small_lap2d_32": small_matrix_leg(kpm, ctx, synth)}))
         return
     if args.copy_probe_only:
         out = {f"copy_gbs_{sz >> 20}MiB": kpm.kpm_hbm_copy_probe(ctx, sz, 5) for sz in (1 << 30, 1 << 26)}
