@@ -31,6 +31,7 @@ __all__ = [
     "add_long_range",
     "diagonal_matrix",
     "batched_uneven_set",
+    "lattice_family_matrix",
     "damping_training_set",
     "config_matrix",
     "CONFIGS",
@@ -204,6 +205,18 @@ def anderson3d_family_matrix(j: int, L: int = 12, seed_base: int = 14000) -> CSR
     resolves in well under a second.  Seed seed_base + j."""
     W = 1.0 + 15.0 * ((j * GOLDEN_RATIO_FRAC) % 1.0)
     return add_diagonal_disorder(laplacian3d_periodic(L), W, seed_base + j)
+
+
+def lattice_family_matrix(j: int, seed_base: int = 15000) -> CSR:
+    """Member j of a family of nearly clean lattice Laplacians, whose spectra
+    are a few high peaks: even j a 3D periodic 7-point Laplacian of side
+    12 + (j/2 mod 5), odd j a 2D Dirichlet 5-point Laplacian of side
+    40 + (j/2 mod 25), both with uniform diagonal disorder of width
+    W = 2 frac(j * golden ratio) in [0, 2).  Seed seed_base + j."""
+    W = 2.0 * ((j * GOLDEN_RATIO_FRAC) % 1.0)
+    if j % 2 == 0:
+        return add_diagonal_disorder(laplacian3d_periodic(12 + (j // 2) % 5), W, seed_base + j)
+    return add_diagonal_disorder(laplacian2d_dirichlet(40 + (j // 2) % 25), W, seed_base + j)
 
 
 def damping_training_set(n_random: int = 8192, n_anderson: int = 1024, seed_base: int = 4000) -> list[CSR]:

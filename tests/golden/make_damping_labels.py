@@ -8,6 +8,9 @@ Matrices (generators in synth/, no method arithmetic):
   family 1: synth.damping_training_matrix(8,192 + j) -- 2D Anderson 32 x 64;
             training j = 0..255, held out j = 992..1,023;
   family 2: synth.anderson3d_family_matrix(j) -- 3D Anderson 12^3;
+            training j = 0..255, held out j = 256..287;
+  family 3: synth.lattice_family_matrix(j) -- nearly clean 3D periodic and
+            2D Dirichlet Laplacians (W < 2, spectra of a few high peaks);
             training j = 0..255, held out j = 256..287.
 Values are rounded to FP32, as the FP32 path reads them.
 
@@ -41,6 +44,7 @@ SPLITS = [  # (family, indices, split: 0 = training, 1 = held out)
     (0, range(0, 1792), 0), (0, range(8000, 8192), 1),
     (1, range(0, 256), 0), (1, range(992, 1024), 1),
     (2, range(0, 256), 0), (2, range(256, 288), 1),
+    (3, range(0, 256), 0), (3, range(256, 288), 1),
 ]
 
 
@@ -49,7 +53,9 @@ def matrix(family: int, i: int):
         return synth.damping_training_matrix(i)
     if family == 1:
         return synth.damping_training_matrix(synth.DAMPING_N_RANDOM + i)
-    return synth.anderson3d_family_matrix(i)
+    if family == 2:
+        return synth.anderson3d_family_matrix(i)
+    return synth.lattice_family_matrix(i)
 
 
 def label(job):

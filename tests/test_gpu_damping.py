@@ -7,9 +7,11 @@ midpoints of [-1, 1]) from dense eigh of each matrix -- the density the
 paper compares approximations with in section 4 -- so both the truncation
 error and the probes' trace-estimation noise count.  Labels and bounds come
 from tests/golden/damping_labels.npz (written by make_damping_labels.py
-with the oracle alone): 2,304 training matrices (1,792 random sparse
+with the oracle alone): 2,560 training matrices (1,792 random sparse
 symmetric n = 2,048 and 256 2D Anderson 32 x 64 of the training family,
-256 3D Anderson 12^3) and 256 held-out ones (192 / 32 / 32, disjoint).
+256 3D Anderson 12^3, 256 nearly clean 3D periodic and 2D Dirichlet
+Laplacians whose spectra are a few high peaks) and 288 held-out ones
+(192 / 32 / 32 / 32, disjoint).
 
 Moments: the library's batched path, degree 127, 256 FP32 probes per
 matrix (the configured probe count of the family).  Training: the library's
@@ -59,7 +61,9 @@ def _matrix(family, i):
         return synth.damping_training_matrix(int(i))
     if family == 1:
         return synth.damping_training_matrix(synth.DAMPING_N_RANDOM + int(i))
-    return synth.anderson3d_family_matrix(int(i))
+    if family == 2:
+        return synth.anderson3d_family_matrix(int(i))
+    return synth.lattice_family_matrix(int(i))
 
 
 @pytest.fixture(scope="module")
@@ -121,13 +125,16 @@ def _evaluate(ctx, mu, lab, fam):
         row = dict(M=M, **{k: float(v.mean()) for k, v in e.items()},
                    learned_beats_jackson_frac=float(np.mean(e["learned"] < e["jackson"])),
                    learned_beats_none_frac=float(np.mean(e["learned"] < e["none"])))
-        for f, name in ((0, "random"), (1, "anderson2d"), (2, "anderson3d")):
+        for f, name in ((0, "random"), (1, "anderson2d"), (2, "anderson3d"), (3, "lattice")):
             sel = fam == f
             row[name] = {k: float(v[sel].mean()) for k, v in e.items()}
         rows.append(row)
         _say("M=%3d held-out mean L1: learned %.5f  jackson %.5f  none %.5f  (learned < jackson on %.0f %%, "
              "< none on %.0f %%)" % (M, row["learned"], row["jackson"], row["none"],
                                      100 * row["learned_beats_jackson_frac"], 100 * row["learned_beats_none_frac"]))
+        for name in ("random", "anderson2d", "anderson3d", "lattice"):
+            f = row[name]
+            _say("      %-10s learned %.5f  jackson %.5f  none %.5f" % (name, f["learned"], f["jackson"], f["none"]))
     return rows
 
 

@@ -186,10 +186,10 @@ def test_damping_labels_file_matches_its_recipe():
         sys.path.remove(here)
     z = np.load(os.path.join(here, "damping_labels.npz"))
     fam, idx, split = z["family"], z["index"], z["split"]
-    assert len(fam) == 2560 and int(np.sum(split == 0)) == 2304 and float(z["sigma"]) == 0.02
+    assert len(fam) == 2848 and int(np.sum(split == 0)) == 2560 and float(z["sigma"]) == 0.02
     keys = {(int(f), int(i)) for f, i in zip(fam, idx)}
     assert len(keys) == len(fam)
-    for f in (0, 1, 2):
+    for f in (0, 1, 2, 3):
         for s in (0, 1):
             k = int(np.flatnonzero((fam == f) & (split == s))[0])
             lb, ub, phi = mk.label((int(fam[k]), int(idx[k])))
