@@ -475,14 +475,16 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
     best64 = min(t64_by, key=t64_by.get)
     t64, t32, t32n = t64_by[best64], min(t32_by.values()), min(t32n_by.values())
     b64 = int(best64.split("+")[0])
+    loc64 = best64.endswith("+locality")
     m64 = _time_ms(lambda: kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64",
-                                           block=b64, validate=False), reps)
+                                           block=b64, validate=False, locality=loc64), reps)
     m32 = _time_ms(lambda: kpm.kpm_moments(ctx, D32, lb, ub, M_FP32_LEARNED, nvec, 2002, precision="f32",
                                            validate=False), reps)
     # the FP64 step kernel against the HBM roofline (values, V, U in FP64)
     kpm.kpm_profile_reset(ctx)
     kpm.kpm_profile_enable(ctx, True)
-    kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", block=b64, validate=False)
+    kpm.kpm_moments(ctx, D64, lb, ub, M_FP64_JACKSON, nvec, 2002, precision="f64", block=b64, validate=False,
+                    locality=loc64)
     kpm.kpm_profile_enable(ctx, False)
     nl, ms = kpm.kpm_profile_query(ctx, "cheb_step")
     us64 = ms / max(nl, 1) * 1000.0  # one launch per probe block of b64 probes
@@ -500,7 +502,7 @@ def equal_accuracy_leg(kpm, ctx, A, D32, x, reps=20):
                                                        / t32_by[k], 2) for k in t32_by},
             "ms_fp64_moments": round(m64, 3), "ms_fp32_moments": round(m32, 3),
             "speedup_moments": round(m64 / m32, 2),
-            "fp64_block": b64, "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
+            "fp64_block": b64, "fp64_locality_renumbering": loc64, "fp64_step_us": round(us64, 2), "fp64_step_algorithmic_bytes": int(bytes64),
             "fp64_step_frac_of_hbm_peak": round(bytes64 / (us64 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
