@@ -699,25 +699,33 @@ def small_matrix_leg(kpm, ctx, synth, reps=50):
             "ms_pipeline": round(t_pipe, 4)}
 
 
-def batched_uneven_bounds(kpm, ctx, D):
-    """Bounds of the uneven batch's matrices: 20-step Lanczos each, then for
-    any matrix whose moments (degree 200, 32 probes) escape, the margin x4
-    and then the Gershgorin hull.  Returns lb, ub and the first estimates."""
-    bl = [kpm.kpm_bounds(ctx, d, 20, 3003, 0.01) for d in D]
-    lb = np.array([b[0] for b in bl])
-    ub = np.array([b[1] for b in bl])
+def batched_bounds_with_recovery(kpm, ctx, D, lz_seed, M, nvec, seed):
+    """Bounds of a batch of matrices: the 20-step Lanczos bounds of all of
+    them in one batched call, then for any matrix whose moments (degree M,
+    nvec probes) escape, the margin x4 (one batched call over those
+    matrices) and then the Gershgorin hull.  Returns lb, ub and the first
+    estimates ([nmat, 2])."""
+    lb, ub = kpm.kpm_bounds_batched(ctx, D, 20, lz_seed, 0.01)
+    bl = np.stack([lb, ub], axis=1)
+    lb, ub = lb.copy(), ub.copy()
     for attempt in range(3):
-        _, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, 200, 32, 2003, return_max_abs=True)
+        _, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, seed, return_max_abs=True)
         bad = [m for m in range(len(D)) if not mx[m] <= 1 + 1e-4]
         if not bad:
             break
-        for m in bad:
-            if attempt == 0:
-                lb[m], ub[m] = kpm.kpm_bounds(ctx, D[m], 20, 3003, 0.04)
-            else:
-                lo, hi = kpm.kpm_gershgorin(ctx, D[m])
+        mats = D.mats if isinstance(D, kpm.MatrixBatch) else D
+        if attempt == 0:
+            lb[bad], ub[bad] = kpm.kpm_bounds_batched(ctx, [mats[m] for m in bad], 20, lz_seed, 0.04)
+        else:
+            for m in bad:
+                lo, hi = kpm.kpm_gershgorin(ctx, mats[m])
                 lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
     return lb, ub, bl
+
+
+def batched_uneven_bounds(kpm, ctx, D):
+    """Bounds of the uneven batch (degree 200, 32 probes for the escape test)."""
+    return batched_bounds_with_recovery(kpm, ctx, D, 3003, 200, 32, 2003)
 
 
 def batched_uneven_setup(kpm, ctx, synth):
@@ -735,6 +743,14 @@ def batched_leg(kpm, ctx, setup, reps=5, tune=True):
     Gershgorin hull) before timing."""
     mats, D, lb, ub, bl = setup
     batch = kpm.MatrixBatch(D)  # the matrices' C descriptors built once for the timed calls
+    # the bounds: one batched Lanczos call against one kpm_bounds call per matrix
+    kpm.kpm_bounds_batched(ctx, batch, 20, 3003, 0.01)
+    kpm.kpm_profile_reset(ctx)
+    kpm.kpm_profile_enable(ctx, True)
+    ms_bounds = _time_ms(lambda: kpm.kpm_bounds_batched(ctx, batch, 20, 3003, 0.01), reps)
+    kpm.kpm_profile_enable(ctx, False)
+    nb_dev, b_dev_ms = kpm.kpm_profile_query(ctx, "lanczos_batched")
+    ms_bounds_single = _time_ms(lambda: [kpm.kpm_bounds(ctx, d, 20, 3003, 0.01) for d in D], 2)
     kpm.kpm_profile_reset(ctx)
     kpm.kpm_profile_enable(ctx, True)
     ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, batch, lb, ub, 200, 32, 2003), reps)
@@ -760,6 +776,10 @@ def batched_leg(kpm, ctx, setup, reps=5, tune=True):
             "units_per_s": nnz * 200 * 32 / (ms * 1e-3),
             "algorithmic_gbs_device": round(byts / (dev_avg * 1e-3) / 1e9, 1),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
+            "bounds": {"ms_batched_call": round(ms_bounds, 3),
+                       "device_ms_batched_call": round(b_dev_ms / max(nb_dev, 1), 3),
+                       "ms_one_call_per_matrix": round(ms_bounds_single, 3),
+                       "speedup": round(ms_bounds_single / ms_bounds, 2)},
             "autotuned": tuned_out}
 
 
@@ -769,7 +789,8 @@ def batched_equal_accuracy_leg(kpm, ctx, setup, reps=3):
     reaches L1 <= 1e-2 (tests/test_gpu_accuracy.py derives the degrees);
     32 probes per matrix as in the uneven-batch leg.  Timed: the batched
     moments (wall and device time), then damping factors and the density of
-    every matrix at 200 points of its own [lb, ub]."""
+    every matrix at 200 points of its own [lb, ub]; the bounds (common to
+    both forms) separately, and the ratio with them added to both."""
     mats, D32, lb, ub, _ = setup
     D64 = [kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64), "f64")
            for A in mats]
@@ -800,6 +821,12 @@ def batched_equal_accuracy_leg(kpm, ctx, setup, reps=3):
         nd, dms = kpm.kpm_profile_query(ctx, "batched")
         out[f"device_ms_{key}_moments"] = round(dms / max(nd, 1), 3)
     out["speedup"] = round(out["ms_fp64_jackson"] / out["ms_fp32_none"], 2)
+    # the bounds (one batched Lanczos call for the 48 matrices, the same for
+    # both forms) timed on their own and added to each form
+    batch = kpm.MatrixBatch(D32)
+    ms_b = _time_ms(lambda: kpm.kpm_bounds_batched(ctx, batch, 20, 3003, 0.01), reps)
+    out["ms_bounds_batched"] = round(ms_b, 3)
+    out["speedup_including_bounds"] = round((out["ms_fp64_jackson"] + ms_b) / (out["ms_fp32_none"] + ms_b), 2)
     out["speedup_moments_device"] = round(out["device_ms_fp64_jackson_moments"] / out["device_ms_fp32_none_moments"], 2)
     return out
 
@@ -818,34 +845,32 @@ def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
     mats = synth.damping_training_set()
     t_gen = time.perf_counter() - t0
     D = [kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32), "f32") for A in mats]
+    M, nvec = 127, 256
+    # the 9,216 matrices' C descriptors built once for the timed calls
+    batch = kpm.MatrixBatch(D)
     t1 = time.perf_counter()
     if bounds == "lanczos":
-        bl = [kpm.kpm_bounds(ctx, d, 20, 3004, 0.01) for d in D]
+        lb, ub, bl = batched_bounds_with_recovery(kpm, ctx, batch, 3004, M, nvec, 2004)
+        kpm.kpm_profile_reset(ctx)
+        kpm.kpm_profile_enable(ctx, True)
+        ms_bounds = _time_ms(lambda: kpm.kpm_bounds_batched(ctx, batch, 20, 3004, 0.01), reps)
+        kpm.kpm_profile_enable(ctx, False)
+        nb_dev, b_dev_ms = kpm.kpm_profile_query(ctx, "lanczos_batched")
+        bounds_out = {"ms_batched_call": round(ms_bounds, 2),
+                      "device_ms_batched_call": round(b_dev_ms / max(nb_dev, 1), 2)}
     else:
         bl = []
         for d in D:
             lo, hi = kpm.kpm_gershgorin(ctx, d)
             bl.append((lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)))
+        bl = np.array(bl)
+        lb, ub = bl[:, 0].copy(), bl[:, 1].copy()
+        bounds_out = None
     t_bounds = time.perf_counter() - t1
-    lb = np.array([b[0] for b in bl])
-    ub = np.array([b[1] for b in bl])
-    M, nvec = 127, 256
-    for attempt in range(3):
-        mu, mx = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2004, return_max_abs=True)
-        bad = [m for m in range(len(D)) if not mx[m] <= 1 + 1e-4]
-        if not bad:
-            break
-        for m in bad:
-            if attempt == 0:
-                lb[m], ub[m] = kpm.kpm_bounds(ctx, D[m], 20, 3004, 0.04)
-            else:
-                lo, hi = kpm.kpm_gershgorin(ctx, D[m])
-                lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
+    mu = kpm.kpm_moments_batched(ctx, batch, lb, ub, M, nvec, 2004)
     nnz = sum(A.nnz for A in mats)
     n = sum(A.n for A in mats)
     K = (M + 1) // 2
-    # the 9,216 matrices' C descriptors built once for the timed calls
-    batch = kpm.MatrixBatch(D)
 
     def timed(block):
         kpm.kpm_profile_reset(ctx)
@@ -884,7 +909,8 @@ def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
             "speedup_over_streaming": round(dev_s / dev_avg, 2),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
             "network_inference_ms_9216": round(ms_inf, 3),
-            "host_generation_s": round(t_gen, 1), "bounds": bounds, "bounds_s": round(t_bounds, 1)}
+            "host_generation_s": round(t_gen, 1), "bounds": bounds,
+            "bounds_with_recovery_s": round(t_bounds, 2), "lanczos_bounds": bounds_out}
 
 
 if __name__ == "__main__":

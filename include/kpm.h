@@ -154,11 +154,31 @@ const char* kpm_last_error(const kpm_ctx* ctx);
  * residual norm beta_k |z_{k,j}|.  On breakdown the Gershgorin hull is merged
  * in.  The interval [lb0, ub0] is finally widened so that it maps into
  * [-(1 - margin), 1 - margin]:  c = (lb0+ub0)/2,  d = (ub0-lb0)/(2(1-margin)),
- * d >= margin * max(|c|, 1);  *lb = c - d,  *ub = c + d.
+ * d >= margin * max(|c|, 1);  *lb = c - d,  *ub = c + d (with margin 0, an
+ * interval of zero width -- a 1 x 1 matrix, say -- gets d = 1 instead).
  * steps in [1, 32] (capped at n); margin in [0, 0.5).
  */
 kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_t seed,
                       double margin, double* lb, double* ub);
+
+/*
+ * kpm_bounds_batched -- kpm_bounds for nmat matrices in one launch sequence
+ * (section 3.1.1, as for kpm_bounds): lb[m], ub[m] are bitwise the values
+ * kpm_bounds(A[m], steps, seed, margin) returns (every matrix uses the same
+ * start-vector seed; same per-matrix arithmetic and summation order).  Per
+ * Lanczos step, one launch of each kind covers all matrices of like size
+ * class and value type, instead of four launches per matrix; the m x m
+ * tridiagonal problems are solved on up to 16 host threads.  A[m].on_device
+ * must be 1 (value types may differ between matrices); lb, ub: host
+ * [nmat].  nmat in [1, 2^20]; steps in [1, 32] (capped at each n); margin in
+ * [0, 0.5).  Device memory kept by the context (grow-only): the Lanczos
+ * vectors of all matrices, sum of min(steps, n_m) * n_m doubles (3 GB for
+ * 9,216 matrices of n = 2,048 at 20 steps), plus 2 n_m doubles each.  Errors
+ * as kpm_bounds, the message naming the first failing matrix; no output is
+ * written then.
+ */
+kpm_status kpm_bounds_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int steps, uint64_t seed,
+                              double margin, double* lb, double* ub);
 
 /*
  * kpm_gershgorin -- the Gershgorin hull [min_i a_ii - sum_j!=i |a_ij|,
@@ -579,6 +599,8 @@ kpm_status kpm_hbm_copy_probe(kpm_ctx* ctx, int64_t bytes, int iters, double* gb
  * events on the stream they run on.  kernel: "cheb_step" (fused recurrence
  * steps, the dominant kernel: one record per run of steps, counting its
  * launches), "cheb_first" (first steps), "lanczos" (a bounds run),
+ * "lanczos_batched" (a kpm_bounds_batched call's launch sequence, one
+ * record per call),
  * "batched" (one batched call's launch sequence), "slq_step" (a stochastic
  * Lanczos run's steps), "copy_probe".  Query waits for the context's stream
  * and returns the launches and their total time since the last reset (a

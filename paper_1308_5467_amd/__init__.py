@@ -40,7 +40,7 @@ EXPORTS = [
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
-    "kpm_gershgorin", "kpm_moments_robust",
+    "kpm_gershgorin", "kpm_moments_robust", "kpm_bounds_batched",
 ]
 
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "kpm_set_stream": ([P, P], I32),
         "kpm_last_error": ([P], ctypes.c_char_p),
         "kpm_bounds": ([P, P, I32, U64, D, P, P], I32),
+        "kpm_bounds_batched": ([P, I32, P, I32, U64, D, P, P], I32),
         "kpm_moments": ([P, P, D, D, P, P, P], I32),
         "kpm_moments_noalloc": ([P, P, D, D, P, P, P], I32),
         "kpm_moments_batched": ([P, I32, P, P, P, P, P, P], I32),
@@ -444,6 +445,18 @@ def _batch_arr(mats):
     if isinstance(mats, MatrixBatch):
         return mats.arr
     return (kpm_csr * len(mats))(*[m.as_c() for m in mats])
+
+
+def kpm_bounds_batched(ctx: Context, mats, steps: int = 20, seed: int = 0, margin: float = 0.01):
+    """kpm_bounds for every matrix of a list of device matrices (or a
+    MatrixBatch) in one launch sequence: arrays lb, ub [nmat], bitwise the
+    values of per-matrix kpm_bounds calls with the same arguments."""
+    arr = _batch_arr(mats)
+    lb = np.zeros(len(mats))
+    ub = np.zeros(len(mats))
+    ctx.check(ctx.lib.kpm_bounds_batched(ctx.handle, len(mats), arr, steps, seed, margin,
+                                         lb.ctypes.data_as(ctypes.c_void_p), ub.ctypes.data_as(ctypes.c_void_p)))
+    return lb, ub
 
 
 def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int, precision="f32",

@@ -21,6 +21,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "kpm_internal.h"
 
 namespace kpm {
@@ -51,6 +54,7 @@ struct LzArgs {
     double* part;    // [3 kinds][LZ_SLOTS][nblk]
     uint64_t seed;
     int32_t n, nblk, chunk;
+    int32_t m;       // Lanczos steps of this matrix
 };
 
 __device__ __forceinline__ double* part_slot(const LzArgs& a, int kind, int t) {
@@ -63,11 +67,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Store this workgroup's J partial sums (wavefront sums in sh[wave][t]).
-__device__ __forceinline__ void lz_store_partials(const LzArgs& a, int kind, int J, double (*sh)[LZ_SLOTS]) {
+__device__ __forceinline__ void lz_store_partials(const LzArgs& a, int kind, int J, int blk,
+                                                  double (*sh)[LZ_SLOTS]) {
     __syncthreads();
     if ((int)threadIdx.x < J) {
         const int t = threadIdx.x;
-        part_slot(a, kind, t)[blockIdx.x] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+        part_slot(a, kind, t)[blk] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
     }
 }
 
@@ -76,9 +81,8 @@ __device__ __forceinline__ void lz_store_partials(const LzArgs& a, int kind, int
 // partials of launch A, 2 norm partials of launch B.  Workgroup t: each
 // thread adds workgroups tid, tid+256, ... in order, then a fixed tree.
 template <int MODE>
-__global__ __launch_bounds__(LZ_THREADS) void lz_reduce(LzArgs a, int kind, int j, double* out) {
-    __shared__ double sh[LZ_THREADS / 64];
-    const int t = blockIdx.x;
+__device__ __forceinline__ void lz_reduce_body(const LzArgs& a, int kind, int t, int j, double* out,
+                                               double* sh) {
     const double* p = part_slot(a, kind, t);
     double s = 0.0;
     for (int b = threadIdx.x; b < a.nblk; b += LZ_THREADS) s += p[b];
@@ -97,13 +101,21 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_reduce(LzArgs a, int kind, int 
     }
 }
 
-// A: normalise, w = A q_j, first projection h = Q^T w.
+template <int MODE>
+__global__ __launch_bounds__(LZ_THREADS) void lz_reduce(LzArgs a, int kind, int j, double* out) {
+    __shared__ double sh[LZ_THREADS / 64];
+    lz_reduce_body<MODE>(a, kind, blockIdx.x, j, out, sh);
+}
+
+// A: normalise, w = A q_j, first projection h = Q^T w (workgroup `blk` of
+// the matrix's row chunks).
 template <typename TA, int R>
-__global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
-    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+__device__ __forceinline__ void lz_spmv_project_body(const LzArgs& a, int blk, int j, double (*sh)[LZ_SLOTS]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double* __restrict__ wr = a.W[(j + 1) & 1];
-    double* __restrict__ ww = a.W[j & 1];
+    // selects, not an index into W: an indexed member array of a struct
+    // read from memory (the many-matrix form) would be copied to scratch
+    const double* __restrict__ wr = (j & 1) ? a.W[0] : a.W[1];
+    double* __restrict__ ww = (j & 1) ? a.W[1] : a.W[0];
     const TA* __restrict__ val = static_cast<const TA*>(a.val);
     const double inv_sqrt_n = 1.0 / sqrt((double)a.n);
     double inv = 0.0;
@@ -113,7 +125,7 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
     }
     const int64_t n = a.n;
     double* __restrict__ qj = a.Q + (int64_t)j * n;
-    const int64_t i0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x;
+    const int64_t i0 = (int64_t)blk * a.chunk + threadIdx.x;
     double x[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -182,22 +194,27 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
             if (lane == 0) sh[wave][t0 + u] = acc;
         }
     }
-    lz_store_partials(a, 0, j + 1, sh);
+    lz_store_partials(a, 0, j + 1, blk, sh);
+}
+
+template <typename TA, int R>
+__global__ __launch_bounds__(LZ_THREADS) void lz_spmv_project(LzArgs a, int j) {
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+    lz_spmv_project_body<TA, R>(a, blockIdx.x, j, sh);
 }
 
 // B: w -= Q h (h from A's reduction); partial of ||w||^2 (-> beta_j).
 template <int R>
-__global__ __launch_bounds__(LZ_THREADS) void lz_orth(LzArgs a, int j) {
-    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
-    __shared__ double hs[LZ_SLOTS];
+__device__ __forceinline__ void lz_orth_body(const LzArgs& a, int blk, int j, double (*sh)[LZ_SLOTS],
+                                             double* hs) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int J = j + 1;
-    double* __restrict__ ww = a.W[j & 1];
+    double* __restrict__ ww = (j & 1) ? a.W[1] : a.W[0];
     if ((int)threadIdx.x < J) hs[threadIdx.x] = a.coef[128 + threadIdx.x];
     __syncthreads();
     const int64_t n = a.n;
     const double* __restrict__ Q = a.Q;
-    const int64_t i0 = (int64_t)blockIdx.x * a.chunk + threadIdx.x;
+    const int64_t i0 = (int64_t)blk * a.chunk + threadIdx.x;
     double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -212,7 +229,14 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_orth(LzArgs a, int j) {
     }
     acc = wave_sum(acc);
     if (lane == 0) sh[wave][0] = acc;
-    lz_store_partials(a, 2, 1, sh);
+    lz_store_partials(a, 2, 1, blk, sh);
+}
+
+template <int R>
+__global__ __launch_bounds__(LZ_THREADS) void lz_orth(LzArgs a, int j) {
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+    __shared__ double hs[LZ_SLOTS];
+    lz_orth_body<R>(a, blockIdx.x, j, sh, hs);
 }
 
 template <int R>
@@ -250,6 +274,7 @@ hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, 
     a.n = A.n;
     a.nblk = W.nblk;
     a.chunk = W.chunk;
+    a.m = m;
     switch (W.chunk / LZ_THREADS) {
         case 1: lz_launch_steps<1>(s, A, m, a); break;
         case 2: lz_launch_steps<2>(s, A, m, a); break;
@@ -258,6 +283,183 @@ hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, 
         case 16: lz_launch_steps<16>(s, A, m, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- many matrices
+// The same run for many matrices at once (kpm_bounds_batched).  Matrices are
+// grouped by (rows per thread, value type); per step, one launch of each of
+// the four kinds covers every matrix of a group.  Workgroup b of a group's
+// A or B launch runs row chunk tab[b].y of matrix tab[b].x with the
+// single-matrix code above, and the reductions add each matrix's partials in
+// the single-matrix order, so every matrix gets bitwise the coefficients of
+// its own launch_lanczos run.  A matrix with fewer steps (n < steps) leaves
+// the later launches at once (a workgroup-uniform test).
+
+template <typename TA, int R>
+__global__ __launch_bounds__(LZ_THREADS) void lzb_spmv_project(const LzArgs* __restrict__ mats,
+                                                               const int2* __restrict__ tab, int j) {
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+    const int2 e = tab[blockIdx.x];
+    const LzArgs a = mats[e.x];
+    if (j >= a.m) return;
+    lz_spmv_project_body<TA, R>(a, e.y, j, sh);
+}
+
+template <int R>
+__global__ __launch_bounds__(LZ_THREADS) void lzb_orth(const LzArgs* __restrict__ mats,
+                                                       const int2* __restrict__ tab, int j) {
+    __shared__ double sh[LZ_THREADS / 64][LZ_SLOTS];
+    __shared__ double hs[LZ_SLOTS];
+    const int2 e = tab[blockIdx.x];
+    const LzArgs a = mats[e.x];
+    if (j >= a.m) return;
+    lz_orth_body<R>(a, e.y, j, sh, hs);
+}
+
+// Workgroup b reduces coefficient b % J of matrix mlist[b / J] (J = j + 1
+// projections for MODE 0, the one norm for MODE 2).
+template <int MODE>
+__global__ __launch_bounds__(LZ_THREADS) void lzb_reduce(const LzArgs* __restrict__ mats,
+                                                         const int* __restrict__ mlist, int J, int kind, int j) {
+    __shared__ double sh[LZ_THREADS / 64];
+    const LzArgs a = mats[mlist[blockIdx.x / J]];
+    if (j >= a.m) return;
+    lz_reduce_body<MODE>(a, kind, blockIdx.x % J, j, MODE == 2 ? a.coef + 64 + j : a.coef + 128, sh);
+}
+
+namespace {
+struct LzGroup {
+    int R = 1, f64 = 0, m_max = 0;
+    int64_t tab_off = 0, entries = 0;  // in the work table
+    int64_t list_off = 0, nmats = 0;   // in the matrix list
+};
+
+// Groups in a fixed order (R, then value type), matrices in index order.
+std::vector<LzGroup> lz_groups(int nmat, const CsrDev* A, const LanczosBatchLayout& L) {
+    std::vector<LzGroup> g;
+    int64_t tab = 0, list = 0;
+    for (int R = 1; R <= 16; R *= 2)
+        for (int f = 0; f < 2; ++f) {
+            LzGroup G;
+            G.R = R;
+            G.f64 = f;
+            G.tab_off = tab;
+            G.list_off = list;
+            for (int m = 0; m < nmat; ++m)
+                if (L.chunk[m] == LZ_THREADS * R && A[m].val_f64 == f) {
+                    G.entries += L.nblk[m];
+                    G.nmats += 1;
+                    G.m_max = std::max(G.m_max, L.m[m]);
+                }
+            if (G.nmats == 0) continue;
+            tab += G.entries;
+            list += G.nmats;
+            g.push_back(G);
+        }
+    return g;
+}
+
+template <int R>
+void lzb_launch_group(hipStream_t s, const LzGroup& G, int j, const LzArgs* mats, const int2* tab,
+                      const int* mlist) {
+    const int2* t = tab + G.tab_off;
+    const int* ml = mlist + G.list_off;
+    if (G.f64) lzb_spmv_project<double, R><<<(unsigned)G.entries, LZ_THREADS, 0, s>>>(mats, t, j);
+    else lzb_spmv_project<float, R><<<(unsigned)G.entries, LZ_THREADS, 0, s>>>(mats, t, j);
+    lzb_reduce<0><<<(unsigned)(G.nmats * (j + 1)), LZ_THREADS, 0, s>>>(mats, ml, j + 1, 0, j);
+    lzb_orth<R><<<(unsigned)G.entries, LZ_THREADS, 0, s>>>(mats, t, j);
+    lzb_reduce<2><<<(unsigned)G.nmats, LZ_THREADS, 0, s>>>(mats, ml, 1, 2, j);
+}
+}  // namespace
+
+void lanczos_batch_layout(int nmat, const CsrDev* A, int steps, LanczosBatchLayout* L) {
+    L->m.assign(nmat, 0);
+    L->nblk.assign(nmat, 0);
+    L->chunk.assign(nmat, 0);
+    L->q_off.assign(nmat, 0);
+    L->w_off.assign(nmat, 0);
+    L->part_off.assign(nmat, 0);
+    L->q_total = L->w_total = L->part_total = 0;
+    int64_t entries = 0;
+    for (int m = 0; m < nmat; ++m) {
+        const int64_t n = A[m].n;
+        L->m[m] = (int)std::min<int64_t>(steps, n);
+        L->chunk[m] = LZ_THREADS * lanczos_rows_per_thread(n);
+        L->nblk[m] = (int)((n + L->chunk[m] - 1) / L->chunk[m]);
+        L->q_off[m] = L->q_total;
+        L->w_off[m] = L->w_total;
+        L->part_off[m] = L->part_total;
+        L->q_total += (int64_t)L->m[m] * n;
+        L->w_total += 2 * n;
+        // projection and norm partials, then the Gershgorin hull's [2 x nblk]
+        L->part_total += (int64_t)3 * LZ_SLOTS * L->nblk[m] + 2 * L->nblk[m];
+        entries += L->nblk[m];
+    }
+    L->desc_bytes = ((size_t)nmat * sizeof(LzArgs) + 255) / 256 * 256;
+    L->tab_bytes = ((size_t)entries * sizeof(int2) + 255) / 256 * 256;
+    L->table_bytes = L->desc_bytes + L->tab_bytes + (size_t)nmat * sizeof(int);
+}
+
+int64_t lanczos_batch_gershgorin_off(const LanczosBatchLayout& L, int m) {
+    return L.part_off[m] + (int64_t)3 * LZ_SLOTS * L.nblk[m];
+}
+
+hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint64_t seed,
+                                  const LanczosBatchLayout& L, double* Q, double* w, double* coef, double* part,
+                                  void* dev_tables, void* host_stage, int* launches) {
+    // descriptors, work table and matrix lists, built in the staging buffer
+    char* h = static_cast<char*>(host_stage);
+    LzArgs* hd = reinterpret_cast<LzArgs*>(h);
+    int2* ht = reinterpret_cast<int2*>(h + L.desc_bytes);
+    int* hl = reinterpret_cast<int*>(h + L.desc_bytes + L.tab_bytes);
+    for (int m = 0; m < nmat; ++m) {
+        LzArgs& a = hd[m];
+        a.rp = A[m].rp;
+        a.ci = A[m].ci;
+        a.val = A[m].val;
+        a.Q = Q + L.q_off[m];
+        a.W[0] = w + L.w_off[m];
+        a.W[1] = w + L.w_off[m] + A[m].n;
+        a.coef = coef + (int64_t)256 * m;
+        a.part = part + L.part_off[m];
+        a.seed = seed;
+        a.n = A[m].n;
+        a.nblk = L.nblk[m];
+        a.chunk = L.chunk[m];
+        a.m = L.m[m];
+    }
+    const std::vector<LzGroup> groups = lz_groups(nmat, A, L);
+    int m_max = 0;
+    for (const LzGroup& G : groups) {
+        int64_t t = G.tab_off, l = G.list_off;
+        for (int m = 0; m < nmat; ++m) {
+            if (L.chunk[m] != LZ_THREADS * G.R || A[m].val_f64 != G.f64) continue;
+            hl[l++] = m;
+            for (int b = 0; b < L.nblk[m]; ++b) ht[t++] = make_int2(m, b);
+        }
+        m_max = std::max(m_max, G.m_max);
+    }
+    hipError_t e = hipMemcpyAsync(dev_tables, host_stage, L.table_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const LzArgs* dd = static_cast<const LzArgs*>(dev_tables);
+    const int2* dt = reinterpret_cast<const int2*>(static_cast<char*>(dev_tables) + L.desc_bytes);
+    const int* dl = reinterpret_cast<const int*>(static_cast<char*>(dev_tables) + L.desc_bytes + L.tab_bytes);
+    int count = 0;
+    for (int j = 0; j < m_max; ++j)
+        for (const LzGroup& G : groups) {
+            if (j >= G.m_max) continue;
+            switch (G.R) {
+                case 1: lzb_launch_group<1>(s, G, j, dd, dt, dl); break;
+                case 2: lzb_launch_group<2>(s, G, j, dd, dt, dl); break;
+                case 4: lzb_launch_group<4>(s, G, j, dd, dt, dl); break;
+                case 8: lzb_launch_group<8>(s, G, j, dd, dt, dl); break;
+                case 16: lzb_launch_group<16>(s, G, j, dd, dt, dl); break;
+                default: return hipErrorInvalidValue;
+            }
+            count += 4;
+        }
+    if (launches) *launches = count;
     return hipGetLastError();
 }
 

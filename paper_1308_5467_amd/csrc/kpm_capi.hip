@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <functional>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kpm_internal.h"
@@ -238,6 +239,73 @@ extern "C" const char* kpm_last_error(const kpm_ctx* ctx) {
 // The bounds of kpm_bounds.  `overlap` (nullable) enqueues more work on the
 // context's stream after the Lanczos coefficients' copy; the host then waits
 // for the copy alone, so that work runs while the host finishes the bounds.
+// [lb0, ub0] from the coefficients of an m-step Lanczos run (hc: alpha at
+// 0, beta at 64): the extreme Ritz values widened by their residual norms
+// (section 3.1.1).  *breakdown: the run stopped early on a vanishing
+// residual, after which the caller merges the Gershgorin hull.  Touches no
+// context (the many-matrix form runs it on several host threads); on error
+// *msg names the failure.
+static kpm_status lanczos_interval(const double* hc, int m, double* lb0, double* ub0, bool* breakdown,
+                                   const char** msg) {
+    // Breakdown test in step order: stop at the first residual below 1e-12 of
+    // the largest coefficient seen so far.
+    double scale = 0.0, beta_last = 0.0;
+    int k = m;
+    *breakdown = false;
+    for (int j = 0; j < m; ++j) {
+        const double a = hc[j], b = hc[64 + j];
+        if (!isfinite(a) || !isfinite(b)) {
+            *msg = "non-finite Lanczos coefficient (matrix values not finite?)";
+            return KPM_ERR_ARG;
+        }
+        scale = std::max(scale, std::max(fabs(a), b));
+        if (j == m - 1) {
+            beta_last = b;
+            break;
+        }
+        if (b <= 1e-12 * scale) {
+            *breakdown = true;
+            beta_last = b;
+            k = j + 1;
+            break;
+        }
+    }
+    // Ritz values and the last components s_k of the Ritz vectors: the last
+    // components of T's eigenvectors are the first components of those of
+    // the flipped matrix J T J (J the reversal), which the implicit QR solver
+    // accumulates in O(k^2) without forming eigenvectors.
+    std::vector<double> fa(k), fb(std::max(k - 1, 1), 0.0), theta(k), s2(k);
+    for (int j = 0; j < k; ++j) fa[j] = hc[k - 1 - j];
+    for (int j = 0; j + 1 < k; ++j) fb[j] = hc[64 + k - 2 - j];
+    const kpm_status es = kpm_tridiag_eig(k, fa.data(), fb.data(), theta.data(), s2.data());
+    if (es == KPM_ERR_NOCONV) {
+        *msg = "QR iteration on the Lanczos matrix did not converge";
+        return es;
+    }
+    if (es != KPM_OK) {
+        *msg = "Lanczos matrix eigenproblem failed";
+        return es;
+    }
+    // residual norms beta_k |s_k| of the extreme Ritz pairs
+    const double rlo = beta_last * sqrt(s2[0]);
+    const double rhi = beta_last * sqrt(s2[k - 1]);
+    *lb0 = theta[0] - rlo;
+    *ub0 = theta[k - 1] + rhi;
+    return KPM_OK;
+}
+
+// The margin: [lb0, ub0] maps into [-(1 - margin), 1 - margin], with a
+// half-width of at least margin * max(|c|, 1); a zero half-width (margin 0
+// on a 1 x 1 matrix) becomes 1, so that no rescaling divides by zero.
+static void widen_interval(double lb0, double ub0, double margin, double* lb, double* ub) {
+    const double c = 0.5 * (lb0 + ub0);
+    double d = 0.5 * (ub0 - lb0) / (1.0 - margin);
+    d = std::max(d, margin * std::max(fabs(c), 1.0));
+    if (!(d > 0.0)) d = 1e-300 > d ? 1.0 : d;
+    *lb = c - d;
+    *ub = c + d;
+}
+
 static kpm_status bounds_impl(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint64_t seed, double margin,
                               double* lb, double* ub, const std::function<kpm_status()>& overlap) {
     if (!lb || !ub) return kpm_fail(ctx, KPM_ERR_ARG, "lb/ub output is NULL");
@@ -276,43 +344,11 @@ static kpm_status bounds_impl(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint6
     } else if ((st = sync(ctx)) != KPM_OK) {
         return st;
     }
-    std::vector<double> hc((const double*)stage, (const double*)stage + 256);
-    // Breakdown test in step order: stop at the first residual below 1e-12 of
-    // the largest coefficient seen so far.
-    double scale = 0.0, beta_last = 0.0;
-    int k = m;
-    bool breakdown = false;
-    for (int j = 0; j < m; ++j) {
-        const double a = hc[j], b = hc[64 + j];
-        if (!isfinite(a) || !isfinite(b))
-            return kpm_fail(ctx, KPM_ERR_ARG, "non-finite Lanczos coefficient (matrix values not finite?)");
-        scale = std::max(scale, std::max(fabs(a), b));
-        if (j == m - 1) {
-            beta_last = b;
-            break;
-        }
-        if (b <= 1e-12 * scale) {
-            breakdown = true;
-            beta_last = b;
-            k = j + 1;
-            break;
-        }
-    }
-    // Ritz values and the last components s_k of the Ritz vectors: the last
-    // components of T's eigenvectors are the first components of those of
-    // the flipped matrix J T J (J the reversal), which the implicit QR solver
-    // accumulates in O(k^2) without forming eigenvectors.
-    std::vector<double> fa(k), fb(std::max(k - 1, 1), 0.0), theta(k), s2(k);
-    for (int j = 0; j < k; ++j) fa[j] = hc[k - 1 - j];
-    for (int j = 0; j + 1 < k; ++j) fb[j] = hc[64 + k - 2 - j];
-    const kpm_status es = kpm_tridiag_eig(k, fa.data(), fb.data(), theta.data(), s2.data());
-    if (es == KPM_ERR_NOCONV)
-        return kpm_fail(ctx, KPM_ERR_NOCONV, "QR iteration on the Lanczos matrix did not converge");
-    if (es != KPM_OK) return kpm_fail(ctx, es, "Lanczos matrix eigenproblem failed");
-    // residual norms beta_k |s_k| of the extreme Ritz pairs
-    const double rlo = beta_last * sqrt(s2[0]);
-    const double rhi = beta_last * sqrt(s2[k - 1]);
-    double lb0 = theta[0] - rlo, ub0 = theta[k - 1] + rhi;
+    const double* hc = (const double*)stage;
+    double lb0, ub0;
+    bool breakdown;
+    const char* msg = nullptr;
+    if ((st = lanczos_interval(hc, m, &lb0, &ub0, &breakdown, &msg)) != KPM_OK) return kpm_fail(ctx, st, msg);
     if (breakdown) {
         const int gb = W.nblk;
         double* gout = (double*)part + (size_t)3 * 32 * W.nblk;
@@ -325,12 +361,7 @@ static kpm_status bounds_impl(kpm_ctx* ctx, const kpm_csr* Ain, int steps, uint6
             ub0 = std::max(ub0, hg[2 * b + 1]);
         }
     }
-    const double c = 0.5 * (lb0 + ub0);
-    double d = 0.5 * (ub0 - lb0) / (1.0 - margin);
-    d = std::max(d, margin * std::max(fabs(c), 1.0));
-    if (!(d > 0.0)) d = 1e-300 > d ? 1.0 : d;
-    *lb = c - d;
-    *ub = c + d;
+    widen_interval(lb0, ub0, margin, lb, ub);
     return KPM_OK;
 }
 
@@ -339,6 +370,97 @@ extern "C" kpm_status kpm_bounds(kpm_ctx* ctx, const kpm_csr* Ain, int steps, ui
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
     return bounds_impl(ctx, Ain, steps, seed, margin, lb, ub, nullptr);
+}
+
+extern "C" kpm_status kpm_bounds_batched(kpm_ctx* ctx, int nmat, const kpm_csr* Ain, int steps, uint64_t seed,
+                                         double margin, double* lb, double* ub) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!Ain || !lb || !ub) return kpm_fail(ctx, KPM_ERR_ARG, "A, lb or ub is NULL");
+    if (nmat < 1 || nmat > (1 << 20)) return kpm_fail(ctx, KPM_ERR_ARG, "nmat must be in [1, 2^20]");
+    if (steps < 1 || steps > 32) return kpm_fail(ctx, KPM_ERR_ARG, "steps must be in [1, 32]");
+    if (!(margin >= 0.0 && margin < 0.5)) return kpm_fail(ctx, KPM_ERR_ARG, "margin must be in [0, 0.5)");
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    std::vector<CsrDev> A(nmat);
+    kpm_status st;
+    for (int m = 0; m < nmat; ++m) {
+        if (!Ain[m].on_device)
+            return kpm_fail(ctx, KPM_ERR_ARG, "matrix " + std::to_string(m) + ": on_device must be 1");
+        if ((st = kpm_prepare_csr(ctx, &Ain[m], KPM_FP64, &A[m], "")) != KPM_OK) return st;
+    }
+    LanczosBatchLayout L;
+    lanczos_batch_layout(nmat, A.data(), steps, &L);
+    void *Q, *w, *coef, *part, *tab, *stage;
+    if ((st = kpm_ws(ctx, "lzb_Q", (size_t)L.q_total * 8, &Q)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lzb_w", (size_t)L.w_total * 8, &w)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lzb_coef", (size_t)nmat * 256 * 8, &coef)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lzb_part", (size_t)L.part_total * 8, &part)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "lzb_tab", L.table_bytes, &tab)) != KPM_OK) return st;
+    // one staging buffer for the tables' upload and the coefficients' copy
+    // back (ordered on the stream)
+    if ((st = kpm_pinned(ctx, std::max(L.table_bytes, (size_t)nmat * 256 * 8), &stage)) != KPM_OK) return st;
+    kpm_prof_begin(ctx, "lanczos_batched");
+    KPM_HIP(ctx, launch_lanczos_batched(ctx->stream, nmat, A.data(), seed, L, (double*)Q, (double*)w,
+                                        (double*)coef, (double*)part, tab, stage, nullptr));
+    kpm_prof_end(ctx, "lanczos_batched", 1);
+    KPM_HIP(ctx, hipMemcpyAsync(stage, coef, (size_t)nmat * 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if ((st = sync(ctx)) != KPM_OK) return st;
+    // the small tridiagonal problems, on up to 16 host threads
+    const double* hc = (const double*)stage;
+    std::vector<double> lb0(nmat), ub0(nmat);
+    std::vector<char> brk(nmat, 0);
+    std::vector<kpm_status> mst(nmat, KPM_OK);
+    std::vector<const char*> msg(nmat, nullptr);
+    auto solve = [&](int t0, int T) {
+        for (int m = t0; m < nmat; m += T) {
+            bool b = false;
+            mst[m] = lanczos_interval(hc + (size_t)256 * m, L.m[m], &lb0[m], &ub0[m], &b, &msg[m]);
+            brk[m] = b ? 1 : 0;
+        }
+    };
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::max(1, std::min(std::min((int)hw, 16), (nmat + 63) / 64));
+    if (T == 1) {
+        solve(0, 1);
+    } else {
+        std::vector<std::thread> pool;
+        pool.reserve(T - 1);
+        for (int t = 1; t < T; ++t) pool.emplace_back(solve, t, T);
+        solve(0, T);
+        for (std::thread& th : pool) th.join();
+    }
+    for (int m = 0; m < nmat; ++m)
+        if (mst[m] != KPM_OK) return kpm_fail(ctx, mst[m], "matrix " + std::to_string(m) + ": " + msg[m]);
+    // Gershgorin hulls of the matrices whose run broke down
+    std::vector<int> bm;
+    int64_t gtot = 0;
+    for (int m = 0; m < nmat; ++m)
+        if (brk[m]) {
+            bm.push_back(m);
+            gtot += 2 * L.nblk[m];
+        }
+    if (!bm.empty()) {
+        std::vector<double> hg((size_t)gtot);
+        int64_t o = 0;
+        for (int m : bm) {
+            double* gout = (double*)part + lanczos_batch_gershgorin_off(L, m);
+            KPM_HIP(ctx, launch_gershgorin(ctx->stream, A[m], gout, L.nblk[m]));
+            KPM_HIP(ctx, hipMemcpyAsync(hg.data() + o, gout, (size_t)2 * L.nblk[m] * 8, hipMemcpyDeviceToHost,
+                                        ctx->stream));
+            o += 2 * L.nblk[m];
+        }
+        if ((st = sync(ctx)) != KPM_OK) return st;
+        o = 0;
+        for (int m : bm) {
+            for (int b = 0; b < L.nblk[m]; ++b) {
+                lb0[m] = std::min(lb0[m], hg[o + 2 * b]);
+                ub0[m] = std::max(ub0[m], hg[o + 2 * b + 1]);
+            }
+            o += 2 * L.nblk[m];
+        }
+    }
+    for (int m = 0; m < nmat; ++m) widen_interval(lb0[m], ub0[m], margin, &lb[m], &ub[m]);
+    return KPM_OK;
 }
 
 extern "C" kpm_status kpm_gershgorin(kpm_ctx* ctx, const kpm_csr* Ain, double* lo, double* hi) {

@@ -93,6 +93,27 @@ int lanczos_rows_per_thread(int64_t n);
 hipError_t launch_lanczos(hipStream_t s, const CsrDev& A, int m, uint64_t seed, LanczosWork& W);
 hipError_t launch_gershgorin(hipStream_t s, const CsrDev& A, double* out /* [2 * nblk] */, int nblk);
 
+// The same Lanczos run for many matrices (kpm_bounds_batched).  Per matrix:
+// steps m = min(steps, n), row chunk and workgroup count as for one matrix,
+// and the offsets (in doubles) of its Lanczos vectors (m x n), residual
+// buffers (2 x n) and partials in buffers shared by all matrices; its
+// coefficients go to coef + 256 * index, laid out as for one matrix.  The
+// descriptor and work tables take table_bytes of device memory, built in a
+// host staging buffer of the same size (page-locked: the upload is
+// asynchronous).
+struct LanczosBatchLayout {
+    std::vector<int> m, nblk, chunk;
+    std::vector<int64_t> q_off, w_off, part_off;
+    int64_t q_total = 0, w_total = 0, part_total = 0;
+    size_t desc_bytes = 0, tab_bytes = 0, table_bytes = 0;
+};
+void lanczos_batch_layout(int nmat, const CsrDev* A, int steps, LanczosBatchLayout* L);
+// Offset in `part` of matrix m's free [2 x nblk] block (Gershgorin output).
+int64_t lanczos_batch_gershgorin_off(const LanczosBatchLayout& L, int m);
+hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint64_t seed,
+                                  const LanczosBatchLayout& L, double* Q, double* w, double* coef, double* part,
+                                  void* dev_tables, void* host_stage, int* launches);
+
 // ---------------------------------------------------------------- damping / density
 hipError_t launch_jackson(hipStream_t s, int M, double* g);
 hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, double c, double d,

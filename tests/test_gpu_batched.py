@@ -233,7 +233,8 @@ def test_training_set_full_size_sampled(ctx):
     Anderson 32 x 64 matrices, degree 127, 256 probes each, FP32: on the
     on-chip path (blocks of 8 probes, 294,912 (matrix, probe block) pairs,
     one workgroup each) and on the streaming path (4 blocks of 64, 36,864
-    pairs).  Bounds: 20-step Lanczos with the same escape recovery as the
+    pairs).  Bounds: 20-step Lanczos (one batched call, bitwise the
+    per-matrix calls on sampled matrices) with the same escape recovery as the
     uneven batch (random sparse matrices often have an outlying extreme
     eigenvalue the start vector barely sees).  The oracle checks matrices at
     both ends of each family and a few recovered ones over all 256 probes;
@@ -242,10 +243,10 @@ def test_training_set_full_size_sampled(ctx):
     mats = synth.damping_training_set()
     assert len(mats) == 9216 and all(A.n == 2048 for A in mats)
     D = [dev(A, "f32") for A in mats]
-    _say("training set: bounds")
-    bl = [kpm.kpm_bounds(ctx, d, 20, 3004, 0.01) for d in D]
-    lb = np.array([b[0] for b in bl])
-    ub = np.array([b[1] for b in bl])
+    _say("training set: bounds (one batched Lanczos call)")
+    lb, ub = kpm.kpm_bounds_batched(ctx, D, 20, 3004, 0.01)
+    for m in list(range(0, 9216, 577)) + [8191, 8192, 9215]:
+        assert (lb[m], ub[m]) == kpm.kpm_bounds(ctx, D[m], 20, 3004, 0.01), m
     recovered = []
     for attempt in range(3):
         _say(f"training set: batched moments, attempt {attempt}")
@@ -254,12 +255,13 @@ def test_training_set_full_size_sampled(ctx):
         if not bad:
             break
         recovered += bad
+        if attempt == 0:
+            lb[bad], ub[bad] = kpm.kpm_bounds_batched(ctx, [D[m] for m in bad], 20, 3004, 0.04)
+            assert (lb[bad[0]], ub[bad[0]]) == kpm.kpm_bounds(ctx, D[bad[0]], 20, 3004, 0.04)
+            continue
         for m in bad:
-            if attempt == 0:
-                lb[m], ub[m] = kpm.kpm_bounds(ctx, D[m], 20, 3004, 0.04)
-            else:
-                lo, hi = kpm.kpm_gershgorin(ctx, D[m])
-                lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
+            lo, hi = kpm.kpm_gershgorin(ctx, D[m])
+            lb[m], ub[m] = lo - 0.01 * (hi - lo), hi + 0.01 * (hi - lo)
     assert not bad
     mu2 = kpm.kpm_moments_batched(ctx, D, lb, ub, 127, 256, 2004)
     assert np.array_equal(mu, mu2)
