@@ -740,7 +740,9 @@ def batched_leg(kpm, ctx, setup, reps=5, tune=True):
     """48 uneven matrices (2D Dirichlet 64..512, 3D periodic 16..64, disorder
     W in {2, 8, 16}), M = 200, 32 probes each, FP32, one launch per step,
     graph replay.  Bounds: Lanczos with escape recovery (margin x4, then the
-    Gershgorin hull) before timing."""
+    Gershgorin hull) before timing the moments; the bounds alone (batched and
+    per matrix) and the whole path in one kpm_dos_pipeline_batched call
+    (bounds, moments with recovery, Jackson damping, densities) timed too."""
     mats, D, lb, ub, bl = setup
     batch = kpm.MatrixBatch(D)  # the matrices' C descriptors built once for the timed calls
     # the bounds: one batched Lanczos call against one kpm_bounds call per matrix
@@ -751,6 +753,12 @@ def batched_leg(kpm, ctx, setup, reps=5, tune=True):
     kpm.kpm_profile_enable(ctx, False)
     nb_dev, b_dev_ms = kpm.kpm_profile_query(ctx, "lanczos_batched")
     ms_bounds_single = _time_ms(lambda: [kpm.kpm_bounds(ctx, d, 20, 3003, 0.01) for d in D], 2)
+    # the whole path in one call: bounds, moments (the escaping matrix
+    # recovered), Jackson damping and each matrix's density at 200 points
+    xs = np.stack([np.linspace(lb[m], ub[m], 202)[1:-1] for m in range(len(D))])
+    pipe = lambda: kpm.kpm_dos_pipeline_batched(ctx, batch, 200, 32, 2003, xs, lanczos_seed=3003)
+    pipe()
+    ms_pipe = _time_ms(pipe, reps)
     kpm.kpm_profile_reset(ctx)
     kpm.kpm_profile_enable(ctx, True)
     ms = _time_ms(lambda: kpm.kpm_moments_batched(ctx, batch, lb, ub, 200, 32, 2003), reps)
@@ -776,6 +784,8 @@ def batched_leg(kpm, ctx, setup, reps=5, tune=True):
             "units_per_s": nnz * 200 * 32 / (ms * 1e-3),
             "algorithmic_gbs_device": round(byts / (dev_avg * 1e-3) / 1e9, 1),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
+            "ms_whole_path_per_call": round(ms_pipe, 3),
+            "units_per_s_whole_path": nnz * 200 * 32 / (ms_pipe * 1e-3),
             "bounds": {"ms_batched_call": round(ms_bounds, 3),
                        "device_ms_batched_call": round(b_dev_ms / max(nb_dev, 1), 3),
                        "ms_one_call_per_matrix": round(ms_bounds_single, 3),
@@ -787,20 +797,21 @@ def batched_equal_accuracy_leg(kpm, ctx, setup, reps=3):
     """The uneven batch at equal accuracy: FP64 + Jackson against FP32
     undamped, each at the degree where every one of the 48 matrices first
     reaches L1 <= 1e-2 (tests/test_gpu_accuracy.py derives the degrees);
-    32 probes per matrix as in the uneven-batch leg.  Timed: the batched
-    moments (wall and device time), then damping factors and the density of
-    every matrix at 200 points of its own [lb, ub]; the bounds (common to
-    both forms) separately, and the ratio with them added to both."""
+    32 probes per matrix as in the uneven-batch leg.  Timed: the whole path
+    in one kpm_dos_pipeline_batched call (the 48 matrices' Lanczos bounds,
+    the batched moments with the escaping matrix recovered, damping factors
+    and the density of every matrix at 200 points); the batched moments
+    alone (wall and device time); the bounds alone."""
     mats, D32, lb, ub, _ = setup
     D64 = [kpm.DeviceCSR.from_host(A.n, A.row_ptr, A.col_idx, A.val.astype(np.float32).astype(np.float64), "f64")
            for A in mats]
     nvec = 32
-    xs = [np.linspace(lb[m], ub[m], 202)[1:-1] for m in range(len(mats))]
+    xs = np.stack([np.linspace(lb[m], ub[m], 202)[1:-1] for m in range(len(mats))])
+    batches = {id(D32): kpm.MatrixBatch(D32), id(D64): kpm.MatrixBatch(D64)}
 
     def form(D, M, precision, damping):
-        mu = kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2003, precision=precision)
-        g = kpm.kpm_damping_factors(ctx, damping, M)
-        return [kpm.kpm_dos(ctx, mu[m], g, lb[m], ub[m], xs[m]) for m in range(len(mats))]
+        return kpm.kpm_dos_pipeline_batched(ctx, batches[id(D)], M, nvec, 2003, xs, precision=precision,
+                                            damping=damping, lanczos_seed=3003)
 
     def moments_only(D, M, precision):
         return kpm.kpm_moments_batched(ctx, D, lb, ub, M, nvec, 2003, precision=precision)
@@ -821,12 +832,8 @@ def batched_equal_accuracy_leg(kpm, ctx, setup, reps=3):
         nd, dms = kpm.kpm_profile_query(ctx, "batched")
         out[f"device_ms_{key}_moments"] = round(dms / max(nd, 1), 3)
     out["speedup"] = round(out["ms_fp64_jackson"] / out["ms_fp32_none"], 2)
-    # the bounds (one batched Lanczos call for the 48 matrices, the same for
-    # both forms) timed on their own and added to each form
-    batch = kpm.MatrixBatch(D32)
-    ms_b = _time_ms(lambda: kpm.kpm_bounds_batched(ctx, batch, 20, 3003, 0.01), reps)
-    out["ms_bounds_batched"] = round(ms_b, 3)
-    out["speedup_including_bounds"] = round((out["ms_fp64_jackson"] + ms_b) / (out["ms_fp32_none"] + ms_b), 2)
+    out["ms_bounds_batched"] = round(_time_ms(lambda: kpm.kpm_bounds_batched(ctx, batches[id(D32)], 20, 3003, 0.01),
+                                              reps), 3)
     out["speedup_moments_device"] = round(out["device_ms_fp64_jackson_moments"] / out["device_ms_fp32_none_moments"], 2)
     return out
 

@@ -401,6 +401,45 @@ kpm_status kpm_dos_pipeline(kpm_ctx* ctx, const kpm_csr* A, int lanczos_steps, u
                             int npts, double* phi, double* mu, double* lb, double* ub);
 
 /*
+ * kpm_dos_batched -- kpm_dos for nmat matrices in one launch: row m of phi
+ * (host [nmat * npts]) is the density of matrix m (series row m of mu, host
+ * [nmat * (M+1)]; interval lb[m], ub[m], host [nmat]) at its own points, row
+ * m of x (host [nmat * npts]).  g: host [M+1] shared by all matrices, or
+ * [nmat * (M+1)] one row per matrix when g_per_matrix != 0.  Each row is
+ * bitwise what kpm_dos returns for that matrix (same per-point arithmetic).
+ * nmat in [1, 65535].
+ */
+kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, const double* g, int g_per_matrix, int M,
+                           const double* lb, const double* ub, const double* x, int npts, double* phi);
+
+/*
+ * kpm_dos_pipeline_batched -- the whole path of section 3.1.1 for nmat
+ * matrices: the bounds of kpm_bounds_batched (lanczos_steps, lanczos_seed,
+ * margin); the moments of kpm_moments_batched (opts; matrix m's probes from
+ * seed opts->seed + m; A[m].on_device must be 1), with the escape recovery
+ * of kpm_moments_robust for the matrices whose moments escape: each is run
+ * again alone, with kpm_moments (same M, nvec, precision and its own seed
+ * opts->seed + m; the library's block and panel choice), on its bounds with
+ * margin 4x (capped at 0.4, all escaping matrices in one kpm_bounds_batched
+ * call), then on the Gershgorin hull widened by margin -- the intervals,
+ * attempts and moments kpm_moments_robust returns for that matrix; the
+ * other rows are those of the one kpm_moments_batched call; the damping
+ * factors (KPM_DAMP_LEARNED: one
+ * network inference over all nmat moment vectors, M <= 127, each row
+ * bitwise what kpm_damping_factors returns for that matrix); the density of
+ * every matrix at its own npts points as kpm_dos_batched.  x, phi: host
+ * [nmat * npts]; mu: host [nmat * (M+1)] or NULL; lb, ub: host [nmat],
+ * receive the interval each matrix's moments belong to; attempts: host
+ * [nmat] or NULL, the bound estimates each matrix needed (1 to 3).  Returns
+ * KPM_ERR_SPECTRUM (with lb, ub, mu and attempts written) if a matrix still
+ * escapes its Gershgorin interval; other errors as for the calls it makes.
+ */
+kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int lanczos_steps,
+                                    uint64_t lanczos_seed, double margin, const kpm_moment_opts* opts,
+                                    kpm_damping damping, const double* x, int npts, double* phi, double* mu,
+                                    double* lb, double* ub, int* attempts);
+
+/*
  * kpm_dgl_dos -- the Delta-Gauss-Legendre density (section 3.1.3, eq.
  * (dglexpansion)): at each point x_i (host, A's units),
  *   phi(x_i) = sum_{k <= m_i} (k + 1/2) gamma_k(t_i) mu_k / sqrt(2 pi s^2) / d,

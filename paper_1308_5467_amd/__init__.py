@@ -40,7 +40,7 @@ EXPORTS = [
     "kpm_mlp_param_count", "kpm_mlp_set_params", "kpm_mlp_get_params", "kpm_mlp_forward",
     "kpm_mlp_loss_grad", "kpm_mlp_train", "kpm_mlp_init", "kpm_mlp_save", "kpm_mlp_load",
     "kpm_profile_enable", "kpm_profile_query", "kpm_profile_reset", "kpm_hbm_copy_probe",
-    "kpm_gershgorin", "kpm_moments_robust", "kpm_bounds_batched",
+    "kpm_gershgorin", "kpm_moments_robust", "kpm_bounds_batched", "kpm_dos_batched", "kpm_dos_pipeline_batched",
 ]
 
 
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
         "kpm_slq_heat_capacity": ([P, P, P, I32, I32, P, I32, P], I32),
         "kpm_tridiag_eig": ([I32, P, P, P, P], I32),
         "kpm_dos": ([P, P, P, I32, D, D, P, I32, P], I32),
+        "kpm_dos_batched": ([P, I32, P, P, I32, I32, P, P, P, I32, P], I32),
+        "kpm_dos_pipeline_batched": ([P, I32, P, I32, U64, D, P, I32, P, I32, P, P, P, P, P], I32),
         "kpm_dos_bins": ([P, P, P, I32, D, D, P, I32, P], I32),
         "kpm_rademacher": ([P, U64, I64, I32, I64, I64, I32, P], I32),
         "kpm_mlp_param_count": ([], I64),
@@ -486,6 +488,45 @@ def kpm_moments_batched(ctx: Context, mats, lb, ub, M: int, nvec: int, seed: int
         return mu, mx
     ctx.check(st)
     return mu
+
+
+def kpm_dos_batched(ctx: Context, mu, g, lb, ub, x) -> np.ndarray:
+    """Densities phi [nmat, npts] of several matrices in one launch: mu
+    [nmat, M+1], g [M+1] (shared) or [nmat, M+1], lb, ub [nmat], x [nmat,
+    npts] (each matrix's own points)."""
+    mu = _f64(np.atleast_2d(mu))
+    nmat, M1 = mu.shape
+    g = _f64(g)
+    per = 1 if g.ndim == 2 else 0
+    x = _f64(np.atleast_2d(x))
+    lbv, ubv = _f64(lb), _f64(ub)
+    phi = np.zeros(x.shape)
+    ctx.check(ctx.lib.kpm_dos_batched(ctx.handle, nmat, _p(mu), _p(g), per, M1 - 1, _p(lbv), _p(ubv), _p(x),
+                                      x.shape[1], _p(phi)))
+    return phi
+
+
+def kpm_dos_pipeline_batched(ctx: Context, mats, M: int, nvec: int, seed: int, x, precision="f32", block: int = 0,
+                             damping: int = KPM_DAMP_JACKSON, lanczos_steps: int = 20, lanczos_seed: int = 3003,
+                             margin: float = 0.01, rows_per_block: int = 0, path: str = "auto"):
+    """The whole path for several device matrices (a list of DeviceCSR or a
+    MatrixBatch) in one call, escapes recovered per matrix: (phi [nmat,
+    npts], mu [nmat, M+1], lb, ub, attempts [nmat]); x [nmat, npts]."""
+    flags = {"auto": 0, "stream": KPM_FLAG_BATCH_STREAM, "resident": KPM_FLAG_BATCH_RESIDENT}[path]
+    o = _opts(M, nvec, seed, precision, block, False, rows_per_block, flags)
+    arr = _batch_arr(mats)
+    n = len(mats)
+    x = _f64(np.atleast_2d(x))
+    if x.shape[0] != n:
+        raise ValueError("x needs one row of points per matrix")
+    phi = np.zeros(x.shape)
+    mu = np.zeros((n, M + 1))
+    lb, ub = np.zeros(n), np.zeros(n)
+    att = np.zeros(n, dtype=np.int32)
+    ctx.check(ctx.lib.kpm_dos_pipeline_batched(ctx.handle, n, arr, lanczos_steps, lanczos_seed, margin,
+                                               ctypes.byref(o), damping, _p(x), x.shape[1], _p(phi), _p(mu),
+                                               _p(lb), _p(ub), _p(att)))
+    return phi, mu, lb, ub, att
 
 
 def kpm_slq(ctx: Context, A, lb: float, ub: float, M: int, nvec: int, seed: int, block: int = 0,

@@ -905,6 +905,129 @@ extern "C" kpm_status kpm_dos(kpm_ctx* ctx, const double* mu, const double* g, i
     return sync(ctx);
 }
 
+extern "C" kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, const double* g, int g_per_matrix,
+                                      int M, const double* lb, const double* ub, const double* x, int npts,
+                                      double* phi) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!mu || !g || !lb || !ub || !x || !phi || M < 0 || M > (1 << 20) || npts < 0 || nmat < 1 || nmat > 65535)
+        return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    for (int m = 0; m < nmat; ++m)
+        if (!(isfinite(lb[m]) && isfinite(ub[m]) && ub[m] > lb[m]))
+            return kpm_fail(ctx, KPM_ERR_ARG, "matrix " + std::to_string(m) + ": need finite lb < ub");
+    if (npts == 0) return KPM_OK;
+    KPM_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t nm = (size_t)nmat * (M + 1), ng = g_per_matrix ? nm : (size_t)M + 1;
+    const size_t np = (size_t)nmat * npts;
+    void *mud, *gd, *bd, *xd, *pd;
+    kpm_status st;
+    if ((st = kpm_ws(ctx, "dosb_mu", nm * 8, &mud)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dosb_g", ng * 8, &gd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dosb_b", (size_t)2 * nmat * 8, &bd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dosb_x", np * 8, &xd)) != KPM_OK) return st;
+    if ((st = kpm_ws(ctx, "dosb_phi", np * 8, &pd)) != KPM_OK) return st;
+    double* dlb = (double*)bd;
+    double* dub = dlb + nmat;
+    KPM_HIP(ctx, hipMemcpyAsync(mud, mu, nm * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(gd, g, ng * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(dlb, lb, (size_t)nmat * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(dub, ub, (size_t)nmat * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, hipMemcpyAsync(xd, x, np * 8, hipMemcpyHostToDevice, ctx->stream));
+    KPM_HIP(ctx, launch_dos_batched(ctx->stream, nmat, (const double*)mud, (const double*)gd,
+                                    g_per_matrix ? (int64_t)M + 1 : 0, M, dlb, dub, (const double*)xd, npts,
+                                    (double*)pd));
+    KPM_HIP(ctx, hipMemcpyAsync(phi, pd, np * 8, hipMemcpyDeviceToHost, ctx->stream));
+    return sync(ctx);
+}
+
+extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int lanczos_steps,
+                                               uint64_t lanczos_seed, double margin, const kpm_moment_opts* o,
+                                               kpm_damping damping, const double* x, int npts, double* phi,
+                                               double* mu, double* lb, double* ub, int* attempts) {
+    if (!ctx) return KPM_ERR_ARG;
+    ctx->err.clear();
+    if (!A || !o || !x || !phi || !lb || !ub || npts < 0 || nmat < 1 || nmat > 65535)
+        return kpm_fail(ctx, KPM_ERR_ARG, "bad argument");
+    if (damping != KPM_DAMP_NONE && damping != KPM_DAMP_JACKSON && damping != KPM_DAMP_LEARNED)
+        return kpm_fail(ctx, KPM_ERR_ARG, "unknown damping kind");
+    if (o->M < 0 || o->M > (1 << 20)) return kpm_fail(ctx, KPM_ERR_ARG, "bad M");
+    if (damping == KPM_DAMP_LEARNED && o->M > 127)
+        return kpm_fail(ctx, KPM_ERR_ARG, "learned damping is defined for M <= 127");
+    const int M = o->M;
+    kpm_status st = kpm_bounds_batched(ctx, nmat, A, lanczos_steps, lanczos_seed, margin, lb, ub);
+    if (st != KPM_OK) return st;
+    std::vector<int> tries((size_t)nmat, 1);
+    std::vector<double> hmu;
+    double* mup = mu;
+    if (!mup) {
+        hmu.assign((size_t)nmat * (M + 1), 0.0);
+        mup = hmu.data();
+    }
+    std::vector<double> mx((size_t)nmat);
+    st = kpm_moments_batched(ctx, nmat, A, lb, ub, o, mup, mx.data());
+    if (st == KPM_ERR_SPECTRUM) {
+        // Escape recovery as in kpm_moments_robust, for the escaping matrices
+        // only: each runs alone on the single-matrix path with its own
+        // probes (seed opts->seed + m), first on its bounds with margin 4x,
+        // then on its Gershgorin interval.
+        const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
+        std::vector<int> bad;
+        for (int m = 0; m < nmat; ++m)
+            if (!(mx[m] <= 1.0 + tol)) bad.push_back(m);
+        std::vector<kpm_csr> sub;
+        for (int m : bad) sub.push_back(A[m]);
+        std::vector<double> l2(bad.size()), u2(bad.size());
+        if ((st = kpm_bounds_batched(ctx, (int)bad.size(), sub.data(), lanczos_steps, lanczos_seed,
+                                     std::min(4.0 * margin, 0.4), l2.data(), u2.data())) != KPM_OK)
+            return st;
+        for (size_t i = 0; i < bad.size(); ++i) {
+            const int m = bad[i];
+            kpm_moment_opts om = *o;
+            om.seed = o->seed + (uint64_t)m;
+            om.block = 0;
+            om.rows_per_block = 0;
+            om.flags = 0;
+            double* mum = mup + (size_t)m * (M + 1);
+            lb[m] = l2[i];
+            ub[m] = u2[i];
+            tries[m] = 2;
+            st = kpm_moments(ctx, &A[m], lb[m], ub[m], &om, mum, nullptr);
+            if (st == KPM_ERR_SPECTRUM) {
+                double glo, ghi;
+                if ((st = kpm_gershgorin(ctx, &A[m], &glo, &ghi)) != KPM_OK) return st;
+                const double c = 0.5 * (glo + ghi);
+                double d = 0.5 * (ghi - glo) / (1.0 - margin);
+                d = std::max(d, std::max(margin, 1e-3) * std::max(fabs(c), 1.0));
+                lb[m] = c - d;
+                ub[m] = c + d;
+                tries[m] = 3;
+                st = kpm_moments(ctx, &A[m], lb[m], ub[m], &om, mum, nullptr);
+            }
+            if (st != KPM_OK) break;
+        }
+    }
+    if (attempts) memcpy(attempts, tries.data(), (size_t)nmat * sizeof(int));
+    if (st != KPM_OK) return st;
+    // damping factors: one shared row, or one per matrix for the network
+    std::vector<double> g;
+    if (damping == KPM_DAMP_LEARNED) {
+        constexpr int kIn = 128;
+        std::vector<float> xin((size_t)nmat * kIn, 0.0f), gf((size_t)nmat * kIn);
+        for (int m = 0; m < nmat; ++m)
+            for (int k = 0; k <= M; ++k) xin[(size_t)m * kIn + k] = (float)mup[(size_t)m * (M + 1) + k];
+        if ((st = kpm_mlp_forward(ctx, nmat, xin.data(), gf.data())) != KPM_OK) return st;
+        g.resize((size_t)nmat * (M + 1));
+        for (int m = 0; m < nmat; ++m) {
+            for (int k = 0; k <= M; ++k) g[(size_t)m * (M + 1) + k] = gf[(size_t)m * kIn + k];
+            g[(size_t)m * (M + 1)] = 1.0;
+        }
+    } else {
+        g.resize((size_t)M + 1);
+        if ((st = kpm_damping_factors(ctx, damping, M, nullptr, g.data())) != KPM_OK) return st;
+    }
+    return kpm_dos_batched(ctx, nmat, mup, g.data(), damping == KPM_DAMP_LEARNED ? 1 : 0, M, lb, ub, x, npts, phi);
+}
+
 extern "C" kpm_status kpm_dos_bins(kpm_ctx* ctx, const double* mu, const double* g, int M, double lb,
                                    double ub, const double* edges, int nbins, double* mass) {
     if (!ctx) return KPM_ERR_ARG;

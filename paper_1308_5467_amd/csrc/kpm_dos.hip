@@ -27,21 +27,19 @@ hipError_t launch_jackson(hipStream_t s, int M, double* g) {
 // t = (x - c)/d, the Chebyshev sum evaluated by Clenshaw's recurrence.  The
 // coefficients g_k mu_k are first staged in LDS when they fit.
 constexpr int kDosLds = 4096;
-__global__ __launch_bounds__(128) void dos_kernel(const double* __restrict__ mu, const double* __restrict__ g,
-                                                  int M, double c, double d, const double* __restrict__ x,
-                                                  int npts, double* __restrict__ phi) {
-    __shared__ double cf[kDosLds];
-    const bool lds = M + 1 <= kDosLds;
-    if (lds)
+
+__device__ __forceinline__ void dos_stage(const double* __restrict__ mu, const double* __restrict__ g, int M,
+                                          double* cf) {
+    if (M + 1 <= kDosLds)
         for (int k = threadIdx.x; k <= M; k += blockDim.x) cf[k] = g[k] * mu[k];
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
-    const double t = (x[i] - c) / d;
-    if (!(fabs(t) < 1.0)) {
-        phi[i] = 0.0;
-        return;
-    }
+}
+
+__device__ __forceinline__ double dos_point(const double* __restrict__ mu, const double* __restrict__ g, int M,
+                                            const double* cf, double c, double d, double x) {
+    const bool lds = M + 1 <= kDosLds;
+    const double t = (x - c) / d;
+    if (!(fabs(t) < 1.0)) return 0.0;
     double b1 = 0.0, b2 = 0.0;
     for (int k = M; k >= 1; --k) {
         const double ck = lds ? cf[k] : g[k] * mu[k];
@@ -50,12 +48,49 @@ __global__ __launch_bounds__(128) void dos_kernel(const double* __restrict__ mu,
         b1 = b0;
     }
     const double sum = g[0] * mu[0] + t * b1 - b2;
-    phi[i] = sum / (M_PI * d * sqrt(1.0 - t * t));
+    return sum / (M_PI * d * sqrt(1.0 - t * t));
+}
+
+__global__ __launch_bounds__(128) void dos_kernel(const double* __restrict__ mu, const double* __restrict__ g,
+                                                  int M, double c, double d, const double* __restrict__ x,
+                                                  int npts, double* __restrict__ phi) {
+    __shared__ double cf[kDosLds];
+    dos_stage(mu, g, M, cf);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    phi[i] = dos_point(mu, g, M, cf, c, d, x[i]);
 }
 
 hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, double c, double d,
                       const double* x, int npts, double* phi) {
     dos_kernel<<<(npts + 127) / 128, 128, 0, s>>>(mu, g, M, c, d, x, npts, phi);
+    return hipGetLastError();
+}
+
+// Many matrices: workgroup (i, m) evaluates points 128 i ... of matrix m,
+// whose series is row m of mu (and of g when g_stride > 0) and whose points
+// are row m of x; c and d from lb[m], ub[m] as on the host.
+__global__ __launch_bounds__(128) void dos_batched_kernel(const double* __restrict__ mu,
+                                                          const double* __restrict__ g, int64_t g_stride, int M,
+                                                          const double* __restrict__ lb,
+                                                          const double* __restrict__ ub,
+                                                          const double* __restrict__ x, int npts,
+                                                          double* __restrict__ phi) {
+    __shared__ double cf[kDosLds];
+    const int m = blockIdx.y;
+    mu += (int64_t)m * (M + 1);
+    g += g_stride * m;
+    dos_stage(mu, g, M, cf);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const double c = 0.5 * (lb[m] + ub[m]), d = 0.5 * (ub[m] - lb[m]);
+    phi[(int64_t)m * npts + i] = dos_point(mu, g, M, cf, c, d, x[(int64_t)m * npts + i]);
+}
+
+hipError_t launch_dos_batched(hipStream_t s, int nmat, const double* mu, const double* g, int64_t g_stride, int M,
+                              const double* lb, const double* ub, const double* x, int npts, double* phi) {
+    dim3 grid((npts + 127) / 128, nmat);
+    dos_batched_kernel<<<grid, 128, 0, s>>>(mu, g, g_stride, M, lb, ub, x, npts, phi);
     return hipGetLastError();
 }
 

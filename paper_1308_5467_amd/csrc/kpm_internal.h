@@ -118,6 +118,10 @@ hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint
 hipError_t launch_jackson(hipStream_t s, int M, double* g);
 hipError_t launch_dos(hipStream_t s, const double* mu, const double* g, int M, double c, double d,
                       const double* x, int npts, double* phi);
+// Densities of nmat matrices: rows of mu [nmat][M+1], g (row stride
+// g_stride, 0 for one shared row), x and phi [nmat][npts]; lb, ub [nmat].
+hipError_t launch_dos_batched(hipStream_t s, int nmat, const double* mu, const double* g, int64_t g_stride, int M,
+                              const double* lb, const double* ub, const double* x, int npts, double* phi);
 hipError_t launch_dos_bins(hipStream_t s, const double* mu, const double* g, int M, double c,
                            double d, const double* edges, int nbins, double* mass);
 
