@@ -846,8 +846,9 @@ def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
     per matrix and block of 8 probes, vectors in LDS for all 64 steps) and,
     for comparison, on the streaming path (4 blocks of 64 probes in device
     memory, one launch per step); then one network inference over all 9,216
-    moment vectors.  Bounds: Lanczos per matrix with escape recovery, before
-    timing."""
+    moment vectors, and the whole path with the learned damping in one
+    kpm_dos_pipeline_batched call.  Bounds: one batched Lanczos call with
+    escape recovery, before timing the moments."""
     t0 = time.perf_counter()
     mats = synth.damping_training_set()
     t_gen = time.perf_counter() - t0
@@ -903,6 +904,21 @@ def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
     load_damping_network(kpm, ctx)
     X = np.ascontiguousarray(mu[:, :128])
     ms_inf = _time_ms(lambda: kpm.kpm_mlp_forward(ctx, X), 5)
+    # the whole path with the learned damping in one call: bounds, moments
+    # (escaping matrices recovered one by one), one network inference over
+    # all moment vectors, each matrix's density at 200 points
+    whole = None
+    if bounds == "lanczos":
+        xs = np.stack([np.linspace(lb[m], ub[m], 202)[1:-1] for m in range(len(D))])
+        res = {}
+
+        def pipe():
+            res["out"] = kpm.kpm_dos_pipeline_batched(ctx, batch, M, nvec, 2004, xs, damping=kpm.KPM_DAMP_LEARNED,
+                                                      lanczos_seed=3004)
+        ms_pipe = _time_ms(pipe, 1)
+        att = res["out"][4]
+        whole = {"ms_per_call": round(ms_pipe, 1), "units_per_s": nnz * M * nvec / (ms_pipe * 1e-3),
+                 "matrices_recovered": int(np.sum(att > 1))}
     return {"matrices": len(mats), "sum_n": n, "sum_nnz": nnz, "M": M, "nvec": nvec,
             "path": "on-chip (LDS-resident vectors, one workgroup per matrix and 8-probe block)",
             "ms_per_call": round(ms, 2), "device_ms_per_call": round(dev_avg, 2),
@@ -916,6 +932,7 @@ def training_set_leg(kpm, ctx, synth, reps=3, bounds="lanczos"):
             "speedup_over_streaming": round(dev_s / dev_avg, 2),
             "bounds_recovered": int(np.sum(np.array(bl)[:, 1] != ub)),
             "network_inference_ms_9216": round(ms_inf, 3),
+            "whole_path_learned": whole,
             "host_generation_s": round(t_gen, 1), "bounds": bounds,
             "bounds_with_recovery_s": round(t_bounds, 2), "lanczos_bounds": bounds_out}
 

@@ -329,8 +329,9 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
  * KPM_ERR_SPECTRUM (after writing every output) if a matrix's spectrum is
  * not inside its [lb, ub].  nmat <= 65535, and at most 65535 (matrix, probe
  * block) pairs on the streaming path (2^26 on the on-chip path).  Device
- * memory (one allocation per shape, kept by the context until the shape
- * changes or kpm_destroy): on the streaming path two probe blocks of n_m x
+ * memory (one allocation per shape; the context keeps the plans of the two
+ * most recently used shapes until kpm_destroy, and releases the older one
+ * when a new plan does not fit beside it): on the streaming path two probe blocks of n_m x
  * ld values per pair, dot partials of two steps per workgroup (2 x 2 x ld
  * doubles each; a pair gets at least 16 workgroups when there are more
  * pairs than resident workgroups), K x 2 x ld doubles of dots per pair and
@@ -414,25 +415,30 @@ kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, const doubl
 
 /*
  * kpm_dos_pipeline_batched -- the whole path of section 3.1.1 for nmat
- * matrices: the bounds of kpm_bounds_batched (lanczos_steps, lanczos_seed,
- * margin); the moments of kpm_moments_batched (opts; matrix m's probes from
- * seed opts->seed + m; A[m].on_device must be 1), with the escape recovery
- * of kpm_moments_robust for the matrices whose moments escape: each is run
- * again alone, with kpm_moments (same M, nvec, precision and its own seed
- * opts->seed + m; the library's block and panel choice), on its bounds with
- * margin 4x (capped at 0.4, all escaping matrices in one kpm_bounds_batched
- * call), then on the Gershgorin hull widened by margin -- the intervals,
- * attempts and moments kpm_moments_robust returns for that matrix; the
- * other rows are those of the one kpm_moments_batched call; the damping
- * factors (KPM_DAMP_LEARNED: one
- * network inference over all nmat moment vectors, M <= 127, each row
- * bitwise what kpm_damping_factors returns for that matrix); the density of
- * every matrix at its own npts points as kpm_dos_batched.  x, phi: host
- * [nmat * npts]; mu: host [nmat * (M+1)] or NULL; lb, ub: host [nmat],
- * receive the interval each matrix's moments belong to; attempts: host
- * [nmat] or NULL, the bound estimates each matrix needed (1 to 3).  Returns
- * KPM_ERR_SPECTRUM (with lb, ub, mu and attempts written) if a matrix still
- * escapes its Gershgorin interval; other errors as for the calls it makes.
+ * matrices:
+ *  - the bounds of kpm_bounds_batched (lanczos_steps, lanczos_seed, margin);
+ *  - the moments of kpm_moments_batched (opts; matrix m's probes from seed
+ *    opts->seed + m; A[m].on_device must be 1);
+ *  - for the matrices whose moments escape, the recovery of
+ *    kpm_moments_robust, each matrix keeping its probes: its bounds again
+ *    with margin 4x (capped at 0.4; all of them in one batched bounds call)
+ *    and its moments -- in one batched moment call when 16 or more escape,
+ *    else one kpm_moments call each (same M, nvec and precision; the
+ *    library's block and panel choice; seed opts->seed + m); then, for any
+ *    that still escape, the Gershgorin hull widened by margin and
+ *    kpm_moments.  Intervals and attempts are those kpm_moments_robust
+ *    returns for that matrix;
+ *  - the damping factors (KPM_DAMP_LEARNED: one network inference over all
+ *    nmat moment vectors, M <= 127, each row bitwise what
+ *    kpm_damping_factors returns for that matrix);
+ *  - the density of every matrix at its own npts points, as
+ *    kpm_dos_batched.
+ * x, phi: host [nmat * npts]; mu: host [nmat * (M+1)] or NULL; lb, ub: host
+ * [nmat], receive the interval each matrix's moments belong to; attempts:
+ * host [nmat] or NULL, the bound estimates each matrix needed (1 to 3).
+ * Returns KPM_ERR_SPECTRUM (with lb, ub, mu and attempts written) if a
+ * matrix still escapes its Gershgorin interval; other errors as for the
+ * calls it makes.
  */
 kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int lanczos_steps,
                                     uint64_t lanczos_seed, double margin, const kpm_moment_opts* opts,

@@ -697,15 +697,21 @@ void free_plan(BatchPlan& P) {
 
 }  // namespace
 
+// The plans of the two most recently used shapes (a caller alternating
+// between two batches, or a batch and the sub-batch of its escaping
+// matrices, keeps both captured).
 struct kpm_batch_state {
-    BatchPlan plan;
+    BatchPlan plan[2];
+    int mru = 0;
 };
 
 void kpm_batch_free(kpm_ctx* ctx) {
     if (!ctx->batch) return;
-    hipStreamSynchronize(ctx->batch->plan.gstream ? ctx->batch->plan.gstream : ctx->stream);
-    free_plan(ctx->batch->plan);
-    if (ctx->batch->plan.gstream) hipStreamDestroy(ctx->batch->plan.gstream);
+    for (BatchPlan& P : ctx->batch->plan) {
+        hipStreamSynchronize(P.gstream ? P.gstream : ctx->stream);
+        free_plan(P);
+        if (P.gstream) hipStreamDestroy(P.gstream);
+    }
     delete ctx->batch;
     ctx->batch = nullptr;
 }
@@ -738,9 +744,8 @@ static size_t lds_per_workgroup(int device) {
 // it past one wave and cost 30 %.
 constexpr int kMinEntriesPerMv = 16;
 
-extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
-                                          const double* ub, const kpm_moment_opts* o, double* mu,
-                                          double* max_abs_mu) {
+kpm_status kpm_moments_batched_seeded(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb, const double* ub,
+                                     const kpm_moment_opts* o, const uint64_t* seeds, double* mu, double* max_abs_mu) {
     if (!ctx) return KPM_ERR_ARG;
     ctx->err.clear();
     if (nmat < 1 || nmat > 65535 || !A || !lb || !ub || !o || !mu)
@@ -819,9 +824,30 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
     shape.dims.insert(shape.dims.end(), tail, tail + 8);
 
     if (!ctx->batch) ctx->batch = new kpm_batch_state();
-    BatchPlan& P = ctx->batch->plan;
+    kpm_batch_state& S = *ctx->batch;
+    int pi = -1;
+    for (int i = 0; i < 2; ++i)
+        if (S.plan[i].mem && S.plan[i].shape == shape) pi = i;
+    const bool reuse = pi >= 0;
+    if (!reuse) pi = !S.plan[0].mem ? 0 : !S.plan[1].mem ? 1 : 1 - S.mru;  // an empty slot, else the older plan
+    S.mru = pi;
+    BatchPlan& P = S.plan[pi];
+    BatchPlan& other = S.plan[1 - pi];
     if (!P.gstream) KPM_HIP(ctx, hipStreamCreateWithFlags(&P.gstream, hipStreamNonBlocking));
-    const bool reuse = P.mem && P.shape == shape;
+    // A new plan's device memory: when it does not fit beside the other
+    // plan, that plan is released and the allocation tried once more.
+    auto plan_malloc = [&](void** ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, bytes) == hipSuccess) return true;
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        if (!other.mem && !other.sell_mem) return false;
+        hipStreamSynchronize(other.gstream ? other.gstream : ctx->stream);
+        free_plan(other);
+        if (hipMalloc(ptr, bytes) == hipSuccess) return true;
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return false;
+    };
     if (!reuse) {
         KPM_HIP(ctx, hipStreamSynchronize(P.gstream));
         free_plan(P);
@@ -886,7 +912,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         off += align256((size_t)nmat * (M + 1) * 8);
         const size_t o_max = off;
         off += align256((size_t)nmat * 8);
-        if (hipMalloc(&P.mem, off) != hipSuccess) {
+        if (!plan_malloc(&P.mem, off)) {
             P.mem = nullptr;
             return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the batched plan failed");
         }
@@ -952,7 +978,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
             }
         }
         const size_t pair_bytes = P.val_f64 ? 16 : 8;
-        if (hipMalloc(&P.sell_mem, std::max<size_t>(256, (size_t)slots * pair_bytes)) != hipSuccess) {
+        if (!plan_malloc(&P.sell_mem, std::max<size_t>(256, (size_t)slots * pair_bytes))) {
             P.sell_mem = nullptr;
             return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the sliced matrices failed");
         }
@@ -1067,7 +1093,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
         off += align256((size_t)nmat * (M + 1) * 8);
         const size_t o_max = off;
         off += align256((size_t)nmat * 8);
-        if (hipMalloc(&P.mem, off) != hipSuccess) {
+        if (!plan_malloc(&P.mem, off)) {
             P.mem = nullptr;
             return kpm_fail(ctx, KPM_ERR_ALLOC, "hipMalloc for the batched plan failed");
         }
@@ -1112,7 +1138,7 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
             BatchMvDev& x = P.mvs[m * nvb + vb];
             x.alpha = 2.0 / d;
             x.beta = -2.0 * c / d;
-            x.seed = o->seed + (uint64_t)m;
+            x.seed = seeds ? seeds[m] : o->seed + (uint64_t)m;
         }
     }
     // order after the caller's stream (the matrices may have been written there)
@@ -1168,6 +1194,12 @@ extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr*
             return kpm_fail(ctx, KPM_ERR_SPECTRUM, msg);
         }
     return KPM_OK;
+}
+
+extern "C" kpm_status kpm_moments_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb,
+                                          const double* ub, const kpm_moment_opts* o, double* mu,
+                                          double* max_abs_mu) {
+    return kpm_moments_batched_seeded(ctx, nmat, A, lb, ub, o, nullptr, mu, max_abs_mu);
 }
 
 // ---------------------------------------------------------------- autotuner

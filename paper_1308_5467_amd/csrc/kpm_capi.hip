@@ -940,6 +940,9 @@ extern "C" kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, 
     return sync(ctx);
 }
 
+// Escaping matrices recovered as one sub-batch from this many on.
+constexpr int kMinRecoveryBatch = 16;
+
 extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int lanczos_steps,
                                                uint64_t lanczos_seed, double margin, const kpm_moment_opts* o,
                                                kpm_damping damping, const double* x, int npts, double* phi,
@@ -967,43 +970,70 @@ extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm
     st = kpm_moments_batched(ctx, nmat, A, lb, ub, o, mup, mx.data());
     if (st == KPM_ERR_SPECTRUM) {
         // Escape recovery as in kpm_moments_robust, for the escaping matrices
-        // only: each runs alone on the single-matrix path with its own
-        // probes (seed opts->seed + m), first on its bounds with margin 4x,
-        // then on its Gershgorin interval.
+        // only, each with its own probes (seed opts->seed + m): first their
+        // bounds with margin 4x (one batched call) and their moments, as one
+        // sub-batch when at least kMinRecoveryBatch escape (a sub-batch of
+        // a few large matrices on the streaming path spreads each over so
+        // many workgroups that it runs slower than the single-matrix path:
+        // one 91,125-row matrix took 7 ms longer that way), else one by one;
+        // then, for any that still escape, the Gershgorin interval and the
+        // single-matrix path.
         const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
         std::vector<int> bad;
         for (int m = 0; m < nmat; ++m)
             if (!(mx[m] <= 1.0 + tol)) bad.push_back(m);
-        std::vector<kpm_csr> sub;
-        for (int m : bad) sub.push_back(A[m]);
-        std::vector<double> l2(bad.size()), u2(bad.size());
-        if ((st = kpm_bounds_batched(ctx, (int)bad.size(), sub.data(), lanczos_steps, lanczos_seed,
-                                     std::min(4.0 * margin, 0.4), l2.data(), u2.data())) != KPM_OK)
+        const int nb = (int)bad.size();
+        std::vector<kpm_csr> sub(nb);
+        std::vector<uint64_t> seeds(nb);
+        std::vector<double> l2(nb), u2(nb), mu2((size_t)nb * (M + 1)), mx2(nb);
+        for (int i = 0; i < nb; ++i) {
+            sub[i] = A[bad[i]];
+            seeds[i] = o->seed + (uint64_t)bad[i];
+        }
+        if ((st = kpm_bounds_batched(ctx, nb, sub.data(), lanczos_steps, lanczos_seed, std::min(4.0 * margin, 0.4),
+                                     l2.data(), u2.data())) != KPM_OK)
             return st;
-        for (size_t i = 0; i < bad.size(); ++i) {
-            const int m = bad[i];
+        auto single_opts = [&](int m) {
             kpm_moment_opts om = *o;
             om.seed = o->seed + (uint64_t)m;
             om.block = 0;
             om.rows_per_block = 0;
             om.flags = 0;
-            double* mum = mup + (size_t)m * (M + 1);
-            lb[m] = l2[i];
-            ub[m] = u2[i];
-            tries[m] = 2;
-            st = kpm_moments(ctx, &A[m], lb[m], ub[m], &om, mum, nullptr);
-            if (st == KPM_ERR_SPECTRUM) {
-                double glo, ghi;
-                if ((st = kpm_gershgorin(ctx, &A[m], &glo, &ghi)) != KPM_OK) return st;
-                const double c = 0.5 * (glo + ghi);
-                double d = 0.5 * (ghi - glo) / (1.0 - margin);
-                d = std::max(d, std::max(margin, 1e-3) * std::max(fabs(c), 1.0));
-                lb[m] = c - d;
-                ub[m] = c + d;
-                tries[m] = 3;
-                st = kpm_moments(ctx, &A[m], lb[m], ub[m], &om, mum, nullptr);
+            return om;
+        };
+        if (nb >= kMinRecoveryBatch) {
+            st = kpm_moments_batched_seeded(ctx, nb, sub.data(), l2.data(), u2.data(), o, seeds.data(), mu2.data(),
+                                            mx2.data());
+            if (st != KPM_OK && st != KPM_ERR_SPECTRUM) return st;
+            for (int i = 0; i < nb; ++i)
+                memcpy(mup + (size_t)bad[i] * (M + 1), mu2.data() + (size_t)i * (M + 1), (size_t)(M + 1) * 8);
+        } else {
+            for (int i = 0; i < nb; ++i) {
+                const kpm_moment_opts om = single_opts(bad[i]);
+                st = kpm_moments(ctx, &A[bad[i]], l2[i], u2[i], &om, mup + (size_t)bad[i] * (M + 1), nullptr);
+                if (st != KPM_OK && st != KPM_ERR_SPECTRUM) return st;
+                mx2[i] = st == KPM_OK ? 0.0 : HUGE_VAL;
             }
-            if (st != KPM_OK) break;
+        }
+        for (int i = 0; i < nb; ++i) {
+            lb[bad[i]] = l2[i];
+            ub[bad[i]] = u2[i];
+            tries[bad[i]] = 2;
+        }
+        st = KPM_OK;
+        for (int i = 0; i < nb && st == KPM_OK; ++i) {
+            if (mx2[i] <= 1.0 + tol) continue;
+            const int m = bad[i];
+            double glo, ghi;
+            if ((st = kpm_gershgorin(ctx, &A[m], &glo, &ghi)) != KPM_OK) return st;
+            const double c = 0.5 * (glo + ghi);
+            double d = 0.5 * (ghi - glo) / (1.0 - margin);
+            d = std::max(d, std::max(margin, 1e-3) * std::max(fabs(c), 1.0));
+            lb[m] = c - d;
+            ub[m] = c + d;
+            tries[m] = 3;
+            const kpm_moment_opts om = single_opts(m);
+            st = kpm_moments(ctx, &A[m], lb[m], ub[m], &om, mup + (size_t)m * (M + 1), nullptr);
         }
     }
     if (attempts) memcpy(attempts, tries.data(), (size_t)nmat * sizeof(int));

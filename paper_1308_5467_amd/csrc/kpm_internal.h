@@ -171,6 +171,11 @@ struct kpm_ctx {
 // FP64 values rounded to FP32 for the FP32 path) and its validation.
 kpm_status kpm_prepare_csr(kpm_ctx* ctx, const kpm_csr* A, int precision, kpm::CsrDev* out, const char* tag);
 kpm_status kpm_validate_csr(kpm_ctx* ctx, const kpm::CsrDev& D);
+// kpm_moments_batched with matrix m's probes drawn from seeds[m] (host
+// [nmat]) instead of opts->seed + m; seeds NULL gives the public call.
+kpm_status kpm_moments_batched_seeded(kpm_ctx* ctx, int nmat, const kpm_csr* A, const double* lb, const double* ub,
+                                     const kpm_moment_opts* o, const uint64_t* seeds, double* mu,
+                                     double* max_abs_mu);
 void kpm_batch_free(kpm_ctx* ctx);
 // KPM_FLAG_LOCALITY: the matrix renumbered along a Morton curve of its grid
 // when kpm_locality_order finds one (*out = the renumbered view, *orig = the

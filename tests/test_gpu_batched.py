@@ -412,3 +412,29 @@ def test_matrix_batch_descriptors_built_once(ctx):
     mu = kpm.kpm_moments_batched(ctx, batch, lb, ub, 30, 8, 3)
     torch.cuda.synchronize()
     assert np.max(np.abs(mu[0] - oracle_mu(A0, lb[0], ub[0], 30, 8, 3, "f32"))) < 1e-5
+
+
+def test_two_cached_plans_alternate_and_a_third_evicts(ctx):
+    """The context keeps the plans of the two most recently used shapes:
+    alternating between two batches (on both paths) reuses both captured
+    graphs, a third shape evicts the older plan, and every call gives
+    bitwise the moments of the first call of its shape; the results stay at
+    the oracle's bar."""
+    mats = small_set()
+    lb, ub = bounds_of(mats, "f32")
+    D = [dev(A, "f32") for A in mats]
+    shapes = [dict(mats=D, lb=lb, ub=ub, M=30, path="stream"),
+              dict(mats=D[:3], lb=lb[:3], ub=ub[:3], M=24, path="resident"),
+              dict(mats=D[2:], lb=lb[2:], ub=ub[2:], M=17, path="stream")]
+
+    def run(k):
+        x = shapes[k]
+        return kpm.kpm_moments_batched(ctx, x["mats"], x["lb"], x["ub"], x["M"], 8, 5, path=x["path"])
+
+    first = [run(k) for k in range(3)]
+    for k in (0, 1, 0, 1, 2, 0, 2, 1, 1, 0):
+        assert np.array_equal(run(k), first[k]), k
+    mu = first[2]
+    for i in (0, len(mats) - 3):
+        ref = oracle_mu(mats[2 + i], lb[2 + i], ub[2 + i], 17, 8, 5 + i, "f32")
+        assert np.max(np.abs(mu[i] - ref)) < 1e-5

@@ -5,7 +5,8 @@ Bars: kpm_dos_batched row by row bitwise equal to kpm_dos and within 1e-11
 of the maximum of the oracle's density; the pipeline bitwise equal to the
 separate calls it stands for (per-matrix bounds, one batched moment call,
 per-matrix damping factors and densities), its escape recovery equal to
-kpm_moments_robust's per matrix (intervals, attempts and moments), and its moments against
+kpm_moments_robust's per matrix (intervals and attempts; the moments
+bitwise on the single-matrix path, at the FP32 bar from a sub-batch), and its moments against
 the oracle at the bounds it chose (FP32 path 1e-5).
 """
 import sys
@@ -112,6 +113,8 @@ def test_pipeline_batched_escape_recovery_matches_robust(ctx):
         rmu, rlb, rub, ratt = kpm.kpm_moments_robust(ctx, d, M, nvec, seed + m, steps=1, lanczos_seed=7,
                                                      validate=False)
         assert (lb[m], ub[m], att[m]) == (rlb, rub, ratt), m
+        # fewer than 16 escaping matrices: recovered one by one on the
+        # single-matrix path, as kpm_moments_robust does
         assert np.array_equal(mu[m], rmu), m
         lam = np.linalg.eigvalsh(mats[m].rounded_f32().dense())
         assert lb[m] < lam[0] and ub[m] > lam[-1]
@@ -121,6 +124,45 @@ def test_pipeline_batched_escape_recovery_matches_robust(ctx):
     assert np.max(np.abs(mu[0] - ref)) < 1e-5
     g = kpm.kpm_damping_factors(ctx, kpm.KPM_DAMP_JACKSON, M)
     for m in range(len(D)):
+        assert np.array_equal(phi[m], kpm.kpm_dos(ctx, mu[m], g, lb[m], ub[m], x[m]))
+
+
+# 20 random sparse matrices (n = 300) whose 4-step Lanczos bounds with a 1 %
+# margin miss an extreme eigenvalue by 0.6 % of the half-width or more and
+# with a 4 % margin enclose the spectrum (found with the oracle's bounds and
+# dense eigh)
+_SUBBATCH_SEEDS = (105, 109, 118, 119, 125, 130, 131, 133, 136, 140, 146, 147, 154, 156, 159, 165, 168, 174,
+                   181, 184)
+
+
+def test_pipeline_batched_recovers_many_escapes_as_one_sub_batch(ctx):
+    """Sixteen or more escaping matrices are recovered in one sub-batch, each
+    with its own probes: intervals and attempts as kpm_moments_robust, the
+    moments bitwise those of a one-matrix batch call with seed + m (the
+    on-chip path runs every (matrix, probe block) pair in its own
+    workgroup), and at the oracle's bar."""
+    mats = [synth.random_sparse_symmetric(300, 4.5, sd) for sd in _SUBBATCH_SEEDS]
+    D = [dev(A, "f32") for A in mats]
+    M, nvec, seed = 120, 16, 9
+    x = np.stack([np.linspace(-8.0, 8.0, 40) for _ in D])
+    _say("pipeline batched: 20 escapes in one sub-batch")
+    phi, mu, lb, ub, att = kpm.kpm_dos_pipeline_batched(ctx, D, M, nvec, seed, x, lanczos_steps=4,
+                                                        lanczos_seed=7, damping=kpm.KPM_DAMP_NONE)
+    assert np.all(att == 2)
+    for m in range(len(D)):
+        rmu, rlb, rub, ratt = kpm.kpm_moments_robust(ctx, D[m], M, nvec, seed + m, steps=4, lanczos_seed=7,
+                                                     validate=False)
+        assert (lb[m], ub[m], att[m]) == (rlb, rub, ratt), m
+        assert np.max(np.abs(mu[m] - rmu)) < 1e-5, m
+        lam = np.linalg.eigvalsh(mats[m].rounded_f32().dense())
+        assert lb[m] < lam[0] and ub[m] > lam[-1], m
+    for m in (0, 7, 19):
+        one = kpm.kpm_moments_batched(ctx, [D[m]], lb[m:m + 1], ub[m:m + 1], M, nvec, seed + m)
+        assert np.array_equal(mu[m], one[0]), m
+        ref = oracle.moments(mats[m].rounded_f32(), lb[m], ub[m], M, nvec, seed + m)
+        assert np.max(np.abs(mu[m] - ref)) < 1e-5, m
+    g = np.ones(M + 1)
+    for m in (0, 19):
         assert np.array_equal(phi[m], kpm.kpm_dos(ctx, mu[m], g, lb[m], ub[m], x[m]))
 
 
@@ -143,6 +185,7 @@ def test_pipeline_batched_uneven_batch(ctx):
     # the other rows from the batched call, the recovered one from its own run
     rmu = kpm.kpm_moments_batched(ctx, D, lb, ub, 80, 32, 2003)
     assert np.array_equal(mu[keep], rmu[keep])
+    # matrix 41 recovered alone on the single-matrix path, with its own probes
     assert np.array_equal(mu[41], kpm.kpm_moments(ctx, D[41], lb[41], ub[41], 80, 32, 2003 + 41, validate=False))
     assert np.max(np.abs(mu[41] - rmu[41])) < 1e-5
     g = np.ones(81)
