@@ -407,7 +407,8 @@ int64_t lanczos_batch_gershgorin_off(const LanczosBatchLayout& L, int m) {
 
 hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint64_t seed,
                                   const LanczosBatchLayout& L, double* Q, double* w, double* coef, double* part,
-                                  void* dev_tables, void* host_stage, int* launches) {
+                                  void* dev_tables, void* host_stage, int* launches, hipStream_t s2,
+                                  hipEvent_t fork, hipEvent_t join) {
     // descriptors, work table and matrix lists, built in the staging buffer
     char* h = static_cast<char*>(host_stage);
     LzArgs* hd = reinterpret_cast<LzArgs*>(h);
@@ -445,20 +446,33 @@ hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint
     const LzArgs* dd = static_cast<const LzArgs*>(dev_tables);
     const int2* dt = reinterpret_cast<const int2*>(static_cast<char*>(dev_tables) + L.desc_bytes);
     const int* dl = reinterpret_cast<const int*>(static_cast<char*>(dev_tables) + L.desc_bytes + L.tab_bytes);
+    // Groups touch disjoint memory: with a second stream their chains run
+    // side by side (odd groups on s2, after the tables' upload).
+    const bool two = s2 && fork && join && groups.size() > 1;
+    if (two) {
+        if ((e = hipEventRecord(fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s2, fork, 0)) != hipSuccess) return e;
+    }
     int count = 0;
     for (int j = 0; j < m_max; ++j)
-        for (const LzGroup& G : groups) {
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const LzGroup& G = groups[gi];
             if (j >= G.m_max) continue;
+            hipStream_t sg = two && (gi & 1) ? s2 : s;
             switch (G.R) {
-                case 1: lzb_launch_group<1>(s, G, j, dd, dt, dl); break;
-                case 2: lzb_launch_group<2>(s, G, j, dd, dt, dl); break;
-                case 4: lzb_launch_group<4>(s, G, j, dd, dt, dl); break;
-                case 8: lzb_launch_group<8>(s, G, j, dd, dt, dl); break;
-                case 16: lzb_launch_group<16>(s, G, j, dd, dt, dl); break;
+                case 1: lzb_launch_group<1>(sg, G, j, dd, dt, dl); break;
+                case 2: lzb_launch_group<2>(sg, G, j, dd, dt, dl); break;
+                case 4: lzb_launch_group<4>(sg, G, j, dd, dt, dl); break;
+                case 8: lzb_launch_group<8>(sg, G, j, dd, dt, dl); break;
+                case 16: lzb_launch_group<16>(sg, G, j, dd, dt, dl); break;
                 default: return hipErrorInvalidValue;
             }
             count += 4;
         }
+    if (two) {
+        if ((e = hipEventRecord(join, s2)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) return e;
+    }
     if (launches) *launches = count;
     return hipGetLastError();
 }

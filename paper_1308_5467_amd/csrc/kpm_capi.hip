@@ -220,6 +220,12 @@ extern "C" kpm_status kpm_destroy(kpm_ctx* ctx) {
         for (hipEvent_t e : kv.second.ev) hipEventDestroy(e);
     if (ctx->pinned) hipHostFree(ctx->pinned);
     if (ctx->copy_done) hipEventDestroy(ctx->copy_done);
+    if (ctx->aux) {
+        hipStreamSynchronize(ctx->aux);
+        hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->aux_fork) hipEventDestroy(ctx->aux_fork);
+    if (ctx->aux_join) hipEventDestroy(ctx->aux_join);
     delete ctx;
     return KPM_OK;
 }
@@ -399,9 +405,15 @@ extern "C" kpm_status kpm_bounds_batched(kpm_ctx* ctx, int nmat, const kpm_csr* 
     // one staging buffer for the tables' upload and the coefficients' copy
     // back (ordered on the stream)
     if ((st = kpm_pinned(ctx, std::max(L.table_bytes, (size_t)nmat * 256 * 8), &stage)) != KPM_OK) return st;
+    if (!ctx->aux) {
+        KPM_HIP(ctx, hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        KPM_HIP(ctx, hipEventCreateWithFlags(&ctx->aux_fork, hipEventDisableTiming));
+        KPM_HIP(ctx, hipEventCreateWithFlags(&ctx->aux_join, hipEventDisableTiming));
+    }
     kpm_prof_begin(ctx, "lanczos_batched");
     KPM_HIP(ctx, launch_lanczos_batched(ctx->stream, nmat, A.data(), seed, L, (double*)Q, (double*)w,
-                                        (double*)coef, (double*)part, tab, stage, nullptr));
+                                        (double*)coef, (double*)part, tab, stage, nullptr, ctx->aux, ctx->aux_fork,
+                                        ctx->aux_join));
     kpm_prof_end(ctx, "lanczos_batched", 1);
     KPM_HIP(ctx, hipMemcpyAsync(stage, coef, (size_t)nmat * 256 * 8, hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync(ctx)) != KPM_OK) return st;

@@ -110,9 +110,12 @@ struct LanczosBatchLayout {
 void lanczos_batch_layout(int nmat, const CsrDev* A, int steps, LanczosBatchLayout* L);
 // Offset in `part` of matrix m's free [2 x nblk] block (Gershgorin output).
 int64_t lanczos_batch_gershgorin_off(const LanczosBatchLayout& L, int m);
+// With s2 (and its fork / join events) the launch groups alternate between
+// s and s2, whose chains are independent; s waits for s2 at the end.
 hipError_t launch_lanczos_batched(hipStream_t s, int nmat, const CsrDev* A, uint64_t seed,
                                   const LanczosBatchLayout& L, double* Q, double* w, double* coef, double* part,
-                                  void* dev_tables, void* host_stage, int* launches);
+                                  void* dev_tables, void* host_stage, int* launches, hipStream_t s2 = nullptr,
+                                  hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 
 // ---------------------------------------------------------------- damping / density
 hipError_t launch_jackson(hipStream_t s, int M, double* g);
@@ -153,6 +156,10 @@ struct kpm_ctx {
     void* pinned = nullptr;  // grow-only page-locked host staging for device-to-host copies
     size_t pinned_cap = 0;
     hipEvent_t copy_done = nullptr;  // marks a device-to-host copy the host waits for alone
+    // a second stream (default priority) for independent launch chains of
+    // one call, and the events that fork it from and join it to `stream`
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_fork = nullptr, aux_join = nullptr;
     // damping network
     bool mlp_ready = false;
     kpm_dev_buf mlp_params;
