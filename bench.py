@@ -52,7 +52,7 @@ WORKLOADS = {
     # name: (matrix config, degree, probes, block, probe seed, Lanczos seed,
     #        KPM_FLAG_LOCALITY: the library renumbers the grid matrix along its
     #        Morton curve, probes at the original indices -- the same moments)
-    "anderson3d_128^3_W16_longrange2": ("c5", 1000, 256, 64, 2005, 3005, True),
+    "anderson3d_128^3_W16_longrange2": ("c5", 1000, 256, 32, 2005, 3005, True),
     "anderson3d_64^3_periodic_W16": ("c2", 256, 64, 64, 2002, 3002, True),
 }
 HEADLINE = "anderson3d_128^3_W16_longrange2"
@@ -66,10 +66,11 @@ def step_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summaries (lines 'traffic_record: kernel=... workload=...
-    bytes_per_launch=... fetch_kib=... write_kib=... step_sources=...'),
+def counter_traffic(kernel: str, workload: str, block: int = 64):
+    """HBM bytes per launch of `kernel` on `workload` at probe-block width
+    `block` from the committed counter summaries (lines 'traffic_record:
+    kernel=... workload=... block=... bytes_per_launch=... fetch_kib=...
+    write_kib=... step_sources=...'; a record without block= is for 64),
     or (None, reason) when there is none for the current sources."""
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
@@ -84,6 +85,8 @@ def counter_traffic(kernel: str, workload: str):
                     continue
                 kv = dict(t.split("=", 1) for t in m.group(1).split())
                 if kv.get("kernel") != kernel.replace(" ", "") or kv.get("workload") != workload:
+                    continue
+                if int(kv.get("block", 64)) != block:
                     continue
                 if kv.get("step_sources") != cur:
                     stale = fn
@@ -202,7 +205,7 @@ def throughput_leg(kpm, ctx, A, D, name, M, nvec, block, seed, lz_seed, steps, w
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernel = ("cheb_step_kernel<float, float, false, true, 7, false>" if precision == "f32"
               else "cheb_step_kernel<double, double, false, true, 7, false>")
-    rec, why = counter_traffic(kernel, name)
+    rec, why = counter_traffic(kernel, name, b)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": rec["bytes"] if rec else None,
             "kernel": "cheb_step_kernel", "avg_launch_us": round(avg_ms * 1000, 2),
@@ -582,22 +585,23 @@ def large_equal_accuracy_leg(kpm, ctx, A, D32, synth, reps=3):
                                             locality=locality)
         return phi
 
-    def fp32_learned(locality=False):
+    def fp32_learned(block=0, locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_LEARNED, nvec, 2005, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005, locality=locality)[0]
+                                    damping=kpm.KPM_DAMP_LEARNED, lanczos_seed=3005, block=block,
+                                    locality=locality)[0]
 
-    def fp32_none(locality=False):
+    def fp32_none(block=0, locality=False):
         return kpm.kpm_dos_pipeline(ctx, D32, M_LARGE_FP32_NONE, nvec, 2005, x, precision="f32",
-                                    damping=kpm.KPM_DAMP_NONE, lanczos_seed=3005, locality=locality)[0]
+                                    damping=kpm.KPM_DAMP_NONE, lanczos_seed=3005, block=block, locality=locality)[0]
 
-    # every form at its own best options (probe block for FP64, locality
-    # renumbering or not)
+    # every form at its own best options (probe block, locality renumbering
+    # or not)
     t64_by = {f"{b}{'+locality' if loc else ''}": _time_ms(lambda b=b, loc=loc: fp64_jackson(b, loc), reps)
               for loc in (False, True) for b in (32, 64)}
-    t32_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_learned(loc), reps)
-              for loc in (False, True)}
-    t32n_by = {("locality" if loc else "plain"): _time_ms(lambda loc=loc: fp32_none(loc), reps)
-               for loc in (False, True)}
+    t32_by = {f"{b}{'+locality' if loc else ''}": _time_ms(lambda b=b, loc=loc: fp32_learned(b, loc), reps)
+              for loc in (False, True) for b in (32, 64)}
+    t32n_by = {f"{b}{'+locality' if loc else ''}": _time_ms(lambda b=b, loc=loc: fp32_none(b, loc), reps)
+               for loc in (False, True) for b in (32, 64)}
     best64 = min(t64_by, key=t64_by.get)
     t64, t32, t32n = t64_by[best64], min(t32_by.values()), min(t32n_by.values())
     del D64

@@ -336,10 +336,10 @@ def _c5_golden():
 
 def test_c5_full_size_sampled(ctx):
     """c5 at full size: 3D Anderson 128^3 plus random long-range hoppings
-    (n = 2,097,152, nnz ~ 23M), degree 1000, 256 probes in blocks of 64,
-    FP32 -- the configuration the benchmark times, plain and with the
-    locality renumbering the benchmark uses.  Probes 254 and 255 (the
-    last block) against the oracle at every degree up to 1000, 1e-5; the
+    (n = 2,097,152, nnz ~ 23M), degree 1000, 256 probes, FP32: in blocks of
+    64 in the caller's numbering, and in the configuration the benchmark
+    times, blocks of 32 with the locality renumbering.  Probes 254 and 255
+    (the last block) against the oracle at every degree up to 1000, 1e-5; the
     oracle's bounds are used on both sides and the library's own bounds must
     agree with them (1e-9 relative); invariants on every probe; the first
     201 moments equal a degree-200 run bitwise (the same launches)."""
@@ -363,9 +363,10 @@ def test_c5_full_size_sampled(ctx):
     mu2, pv2 = kpm.kpm_moments(ctx, D, lb, ub, 200, 256, 2005, precision="f32", block=64,
                                validate=False, per_vector=True)
     assert np.array_equal(pv[:, :201], pv2)
-    # the configuration the benchmark times: the library's locality renumbering
-    _say("c5 moments M=1000 with the locality renumbering")
-    mu3, pv3 = kpm.kpm_moments(ctx, D, lb, ub, 1000, 256, 2005, precision="f32", block=64,
+    # the configuration the benchmark times: blocks of 32, the library's
+    # locality renumbering
+    _say("c5 moments M=1000, blocks of 32, with the locality renumbering")
+    mu3, pv3 = kpm.kpm_moments(ctx, D, lb, ub, 1000, 256, 2005, precision="f32", block=32,
                                validate=False, per_vector=True, locality=True)
     assert mu3[0] == 1.0 and np.all(np.abs(pv3) <= 1 + 1e-5)
     err3 = np.abs(pv3[254:256] - z)

@@ -22,12 +22,12 @@ def test_more_than_one_gpu_is_refused():
 
 @pytest.mark.parametrize("workload", ["anderson3d_128^3_W16_longrange2", "anderson3d_64^3_periodic_W16"])
 def test_counter_records_match_the_current_step_kernel(workload):
-    """The benchmark's two workloads have a counter record for the current
-    step sources (a change to the step kernel leaves `traffic` null until the
+    """The benchmark's two workloads have a counter record, at the probe-block
+    width the benchmark runs them with, for the current step sources (a change to the step kernel leaves `traffic` null until the
     counters are taken again); the record's bytes are the calibrated
     FETCH_SIZE and WRITE_SIZE (factors 2 and 1, KiB; the KiB figures are
     recorded to 0.1 KiB)."""
-    rec, why = bench.counter_traffic(F32_STEP, workload)
+    rec, why = bench.counter_traffic(F32_STEP, workload, bench.WORKLOADS[workload][3])
     assert rec is not None, why
     assert rec["source"].startswith("profiles/") and os.path.exists(os.path.join(ROOT, rec["source"]))
     assert abs(rec["bytes"] - (2.0 * rec["fetch_kib"] + 1.0 * rec["write_kib"]) * 1024) <= 3 * 0.05 * 1024
