@@ -305,7 +305,8 @@ kpm_status kpm_moments_robust(kpm_ctx* ctx, const kpm_csr* A, int steps, uint64_
 
 /*
  * kpm_moments_batched -- the same moments for nmat independent matrices of
- * uneven size.  Two device paths:
+ * uneven size (it pays off for many (matrix, probe block) pairs; a few large
+ * matrices run faster as kpm_moments calls).  Two device paths:
  *  - on-chip: when opts->block is 0 and two blocks of N, 2N or 4N probes
  *    (N = 4 FP32, 2 FP64) of the largest matrix fit one workgroup's LDS
  *    (160 KB: n up to 2,048 with 8 FP32 probes), one workgroup owns each
