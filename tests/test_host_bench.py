@@ -33,6 +33,18 @@ def test_counter_records_match_the_current_step_kernel(workload):
     assert abs(rec["bytes"] - (2.0 * rec["fetch_kib"] + 1.0 * rec["write_kib"]) * 1024) <= 3 * 0.05 * 1024
 
 
+def test_records_are_kept_per_block_width():
+    """The large workload has records at probe blocks of 32 (the benchmark's
+    setting) and 64, each found only under its own width; a record without
+    a width is for 64."""
+    w = "anderson3d_128^3_W16_longrange2"
+    r32, _ = bench.counter_traffic(F32_STEP, w, 32)
+    r64, _ = bench.counter_traffic(F32_STEP, w, 64)
+    assert r32 is not None and r64 is not None and r32["bytes"] != r64["bytes"]
+    assert bench.counter_traffic(F32_STEP, w, 128)[0] is None
+    assert bench.counter_traffic(F32_STEP, "anderson3d_64^3_periodic_W16")[0] is not None
+
+
 def test_unknown_kernel_or_workload_has_no_record():
     rec, why = bench.counter_traffic(F32_STEP, "no_such_workload")
     assert rec is None and "no counter record" in why
