@@ -423,8 +423,9 @@ kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, const doubl
  *  - for the matrices whose moments escape, the recovery of
  *    kpm_moments_robust, each matrix keeping its probes: its bounds again
  *    with margin 4x (capped at 0.4; all of them in one batched bounds call)
- *    and its moments -- in one batched moment call when 16 or more escape,
- *    else one kpm_moments call each (same M, nvec and precision; the
+ *    and its moments -- in one batched moment call when 16 or more escape
+ *    and none has more than 131,072 rows, else one kpm_moments call each
+ *    (same M, nvec and precision; the
  *    library's block and panel choice; seed opts->seed + m); then, for any
  *    that still escape, the Gershgorin hull widened by margin and
  *    kpm_moments.  Intervals and attempts are those kpm_moments_robust

@@ -952,8 +952,14 @@ extern "C" kpm_status kpm_dos_batched(kpm_ctx* ctx, int nmat, const double* mu, 
     return sync(ctx);
 }
 
-// Escaping matrices recovered as one sub-batch from this many on.
+// Escaping matrices are recovered as one sub-batch from this many on, when
+// none has more rows than kMaxRecoveryBatchRows.  Measured on 16 copies of
+// one matrix (degree 200, 32 FP32 probes), one batched call against 16
+// single-matrix calls: 0.9 against 12.8 ms at n = 4,096, 7.5 against
+// 14.8 ms at 65,536, 16.0 against 19.6 ms at 110,592; eight copies of a
+// 262,144-row matrix ran slower batched (55.1 against 39.4 ms).
 constexpr int kMinRecoveryBatch = 16;
+constexpr int64_t kMaxRecoveryBatchRows = 131072;
 
 extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm_csr* A, int lanczos_steps,
                                                uint64_t lanczos_seed, double margin, const kpm_moment_opts* o,
@@ -984,10 +990,10 @@ extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm
         // Escape recovery as in kpm_moments_robust, for the escaping matrices
         // only, each with its own probes (seed opts->seed + m): first their
         // bounds with margin 4x (one batched call) and their moments, as one
-        // sub-batch when at least kMinRecoveryBatch escape (a sub-batch of
-        // a few large matrices on the streaming path spreads each over so
-        // many workgroups that it runs slower than the single-matrix path:
-        // one 91,125-row matrix took 7 ms longer that way), else one by one;
+        // sub-batch when enough of them escape and none is large (a
+        // sub-batch of a few large matrices spreads each over so many
+        // workgroups that it runs slower than the single-matrix path: one
+        // 91,125-row matrix took 7 ms longer that way), else one by one;
         // then, for any that still escape, the Gershgorin interval and the
         // single-matrix path.
         const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
@@ -1013,7 +1019,9 @@ extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm
             om.flags = 0;
             return om;
         };
-        if (nb >= kMinRecoveryBatch) {
+        int64_t nmax_bad = 0;
+        for (int m : bad) nmax_bad = std::max<int64_t>(nmax_bad, A[m].n);
+        if (nb >= kMinRecoveryBatch && nmax_bad <= kMaxRecoveryBatchRows) {
             st = kpm_moments_batched_seeded(ctx, nb, sub.data(), l2.data(), u2.data(), o, seeds.data(), mu2.data(),
                                             mx2.data());
             if (st != KPM_OK && st != KPM_ERR_SPECTRUM) return st;
