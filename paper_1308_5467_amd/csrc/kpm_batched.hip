@@ -74,11 +74,18 @@ __device__ __forceinline__ void bneumaier(double& s, double& c, double x) {
     s = u;
 }
 
-// Step k also finishes step k - 1's dots: the workgroup that runs an mv's
-// first table entry adds that mv's partials of step k - 1 (`prev`, the other
-// half of a two-step partial buffer) over its entries in order, with the
-// compensated sum of batched_reduce_kernel, so only two steps of partials
-// are ever stored whatever the number of table entries.
+// Step k also reduces earlier steps' dots, in two levels, so that no
+// workgroup adds more than a few memory round trips to a step and only two
+// steps of partials are stored whatever the number of table entries:
+//  - the workgroup that runs entry e of an mv with (e - first entry) a
+//    multiple of kChunk adds step k - 1's partials (`prev`) of entries
+//    e .. e + kChunk - 1 in order (compensated) into chunk_out[e];
+//  - the workgroup that runs the mv's first entry adds step k - 2's chunk
+//    sums (`chunk_in`, written by the previous launch) in order into the
+//    mv's dots.
+// batched_final_reduce_kernel finishes the last two steps in the same order.
+constexpr int kChunk = 16;
+
 template <typename TA, typename TV, bool FIRST, int G>
 __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntryDev* __restrict__ entries,
                                                                 const BatchMvDev* __restrict__ mvs, int parity,
@@ -87,7 +94,9 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
                                                                 const double* __restrict__ prev,
                                                                 const int32_t* __restrict__ e0,
                                                                 const int32_t* __restrict__ e1,
-                                                                double* __restrict__ dots_prev) {
+                                                                double* __restrict__ chunk_out,
+                                                                const double* __restrict__ chunk_in,
+                                                                double* __restrict__ dots_prev2) {
     constexpr int N = Pack<TV>::N;
     __shared__ __align__(16) double smem[kWaves * 64 * 2 * N];
     const int lane = threadIdx.x & 63;
@@ -136,20 +145,35 @@ __global__ __launch_bounds__(kThreads) void batched_step_kernel(const BatchEntry
         for (int sl = 0; sl < nslots; ++sl) s += red[(sl * 2 + d) * ld + c];
         outp[t] = s;
     }
-    if (!FIRST && e == e0[E.mv]) {
-        // loads in groups of 16 (one memory round trip each), sums in order
-        const int width = 2 * ld, f1 = e1[E.mv];
-        for (int t = threadIdx.x; t < width; t += kThreads) {
-            double s = 0.0, c = 0.0;
-            for (int f = e; f < f1; f += 16) {
-                double x[16];
+    if (!FIRST) {
+        const int width = 2 * ld, ef = e0[E.mv], el = e1[E.mv];
+        if ((e - ef) % kChunk == 0) {  // one memory round trip
+            const int f1 = min(el, e + kChunk);
+            for (int t = threadIdx.x; t < width; t += kThreads) {
+                double x[kChunk];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = f + u < f1 ? prev[(int64_t)(f + u) * width + t] : 0.0;
+                for (int u = 0; u < kChunk; ++u) x[u] = e + u < f1 ? prev[(int64_t)(e + u) * width + t] : 0.0;
+                double s = 0.0, c = 0.0;
 #pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (f + u < f1) bneumaier(s, c, x[u]);
+                for (int u = 0; u < kChunk; ++u)
+                    if (e + u < f1) bneumaier(s, c, x[u]);
+                chunk_out[(int64_t)e * width + t] = s + c;
             }
-            dots_prev[(int64_t)E.mv * width + t] = s + c;
+        }
+        if (chunk_in && e == ef) {  // chunk sums loaded 16 per round trip
+            for (int t = threadIdx.x; t < width; t += kThreads) {
+                double s = 0.0, c = 0.0;
+                for (int f = ef; f < el; f += 16 * kChunk) {
+                    double x[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        x[u] = f + u * kChunk < el ? chunk_in[(int64_t)(f + u * kChunk) * width + t] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (f + u * kChunk < el) bneumaier(s, c, x[u]);
+                }
+                dots_prev2[(int64_t)E.mv * width + t] = s + c;
+            }
         }
     }
 }
@@ -485,19 +509,33 @@ __global__ void batched_fill_kernel(const BatchMvDev* __restrict__ mvs, int ld) 
         out[i * ld + j] = j < mv.ncols ? (T)rademacher_sign(mv.seed, (uint64_t)(mv.vec0 + j), (uint64_t)i) : (T)0;
 }
 
-// dots[k][mv][t] = sum over the mv's table entries of partial[k][e][t], in order
-// (launched for the last step only; the step kernels reduce the others).
-__global__ __launch_bounds__(64) void batched_reduce_kernel(const double* __restrict__ partial, int nentries,
-                                                            int width, const int32_t* __restrict__ e0,
-                                                            const int32_t* __restrict__ e1, int nmv,
-                                                            double* __restrict__ dots) {
+// The last two steps' dots, in the order of the step kernels' two levels:
+// dots_prev2 (step K - 2, when chunk_prev is given) adds the stored chunk
+// sums; dots_last (step K - 1) forms each chunk's sum of `partial` as a
+// chunk leader would and adds those.
+__global__ __launch_bounds__(64) void batched_final_reduce_kernel(const double* __restrict__ partial,
+                                                                  const double* __restrict__ chunk_prev,
+                                                                  int width, const int32_t* __restrict__ e0,
+                                                                  const int32_t* __restrict__ e1, int nmv,
+                                                                  double* __restrict__ dots_prev2,
+                                                                  double* __restrict__ dots_last) {
     const int t = blockIdx.x * 64 + threadIdx.x;
-    const int k = blockIdx.y, mv = blockIdx.z;
+    const int mv = blockIdx.z;
     if (t >= width) return;
+    const int ef = e0[mv], el = e1[mv];
+    if (chunk_prev) {
+        double s = 0.0, c = 0.0;
+        for (int f = ef; f < el; f += kChunk) bneumaier(s, c, chunk_prev[(int64_t)f * width + t]);
+        dots_prev2[(int64_t)mv * width + t] = s + c;
+    }
     double s = 0.0, c = 0.0;
-    const double* src = partial + (int64_t)k * nentries * width + t;
-    for (int e = e0[mv]; e < e1[mv]; ++e) bneumaier(s, c, src[(int64_t)e * width]);
-    dots[((int64_t)k * nmv + mv) * width + t] = s + c;
+    for (int f = ef; f < el; f += kChunk) {
+        const int f1 = min(el, f + kChunk);
+        double s1 = 0.0, c1 = 0.0;
+        for (int e = f; e < f1; ++e) bneumaier(s1, c1, partial[(int64_t)e * width + t]);
+        bneumaier(s, c, s1 + c1);
+    }
+    dots_last[(int64_t)mv * width + t] = s + c;
 }
 
 // zeta_norm[mat][vec0 + c][k] = zeta_k / n of probe vec0 + c.
@@ -583,6 +621,7 @@ struct BatchPlan {
     int32_t* d_e0 = nullptr;
     int32_t* d_e1 = nullptr;
     double* d_partial = nullptr;
+    double* d_chunk = nullptr;  // chunk sums of two steps, at their leaders' entries
     double* d_dots = nullptr;
     double* d_zeta = nullptr;
     double* d_mu = nullptr;
@@ -649,24 +688,29 @@ hipError_t enqueue_batched(hipStream_t s, const BatchPlan& P) {
     dim3 fill_grid(256, P.nmv);
     batched_fill_kernel<TV><<<fill_grid, 256, 0, s>>>(P.d_mvs, P.ld);
     const size_t width = 2 * (size_t)P.ld;
-    // partials of step k go to half k & 1; step k reduces step k - 1's half
+    // partials of step k go to half k & 1 and step k - 1's chunk sums to
+    // chunk half (k - 1) & 1; step k reads the other halves
+    const size_t half = (size_t)P.nentries * width;
     for (int k = 0; k < P.K; ++k) {
-        double* pk = P.d_partial + (size_t)(k & 1) * P.nentries * width;
+        double* pk = P.d_partial + (size_t)(k & 1) * half;
         if (k == 0)
             batched_step_kernel<TA, TV, true, 7><<<P.nentries, kThreads, 0, s>>>(
                 P.d_entries, P.d_mvs, 0, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk, nullptr, P.d_e0, P.d_e1,
-                nullptr);
+                nullptr, nullptr, nullptr);
         else
             batched_step_kernel<TA, TV, false, 7><<<P.nentries, kThreads, 0, s>>>(
                 P.d_entries, P.d_mvs, k & 1, P.ld, P.lpr, P.rpw, P.rows, P.stage, pk,
-                P.d_partial + (size_t)((k - 1) & 1) * P.nentries * width, P.d_e0, P.d_e1,
-                P.d_dots + (size_t)(k - 1) * P.nmv * width);
+                P.d_partial + (size_t)((k - 1) & 1) * half, P.d_e0, P.d_e1,
+                P.d_chunk + (size_t)((k - 1) & 1) * half, k >= 2 ? P.d_chunk + (size_t)(k & 1) * half : nullptr,
+                k >= 2 ? P.d_dots + (size_t)(k - 2) * P.nmv * width : nullptr);
     }
-    if (P.K > 0) {  // the last step's dots
+    if (P.K > 0) {  // the last two steps' dots
         dim3 rg((unsigned)((width + 63) / 64), 1, P.nmv);
-        batched_reduce_kernel<<<rg, 64, 0, s>>>(P.d_partial + (size_t)((P.K - 1) & 1) * P.nentries * width,
-                                                P.nentries, (int)width, P.d_e0, P.d_e1, P.nmv,
-                                                P.d_dots + (size_t)(P.K - 1) * P.nmv * width);
+        const bool two = P.K >= 2;
+        batched_final_reduce_kernel<<<rg, 64, 0, s>>>(
+            P.d_partial + (size_t)((P.K - 1) & 1) * half, two ? P.d_chunk + (size_t)((P.K - 2) & 1) * half : nullptr,
+            (int)width, P.d_e0, P.d_e1, P.nmv, two ? P.d_dots + (size_t)(P.K - 2) * P.nmv * width : nullptr,
+            P.d_dots + (size_t)(P.K - 1) * P.nmv * width);
     }
     dim3 ag((P.ld * (P.M + 1) + 255) / 256, P.nmv);
     batched_assemble_kernel<<<ag, 256, 0, s>>>(P.d_dots, P.d_mvs, P.nmv, P.ld, P.M, P.nvec, P.d_zeta);
@@ -931,7 +975,7 @@ kpm_status kpm_moments_batched_seeded(kpm_ctx* ctx, int nmat, const kpm_csr* A, 
         P.d_maxabs = (double*)(base + o_max);
         P.d_entries = nullptr;
         P.d_e0 = P.d_e1 = nullptr;
-        P.d_partial = P.d_dots = nullptr;
+        P.d_partial = P.d_chunk = P.d_dots = nullptr;
         P.nentries = 0;
         std::vector<SellMatDev> hm(nmat);
         for (int m = 0; m < nmat; ++m) {
@@ -1085,6 +1129,8 @@ kpm_status kpm_moments_batched_seeded(kpm_ctx* ctx, int nmat, const kpm_csr* A, 
         off += align256((size_t)P.nmv * 4);
         const size_t o_part = off;
         off += align256((size_t)std::min(std::max(P.K, 1), 2) * P.nentries * 2 * g.ld * 8);
+        const size_t o_chunk = off;
+        off += align256((size_t)2 * P.nentries * 2 * g.ld * 8);
         const size_t o_dots = off;
         off += align256((size_t)std::max(P.K, 1) * P.nmv * 2 * g.ld * 8);
         const size_t o_zeta = off;
@@ -1104,6 +1150,7 @@ kpm_status kpm_moments_batched_seeded(kpm_ctx* ctx, int nmat, const kpm_csr* A, 
         P.d_e0 = (int32_t*)(base + o_e0);
         P.d_e1 = (int32_t*)(base + o_e1);
         P.d_partial = (double*)(base + o_part);
+        P.d_chunk = (double*)(base + o_chunk);
         P.d_dots = (double*)(base + o_dots);
         P.d_zeta = (double*)(base + o_zeta);
         P.d_mu = (double*)(base + o_mu);

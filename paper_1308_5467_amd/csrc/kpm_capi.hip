@@ -990,10 +990,9 @@ extern "C" kpm_status kpm_dos_pipeline_batched(kpm_ctx* ctx, int nmat, const kpm
         // Escape recovery as in kpm_moments_robust, for the escaping matrices
         // only, each with its own probes (seed opts->seed + m): first their
         // bounds with margin 4x (one batched call) and their moments, as one
-        // sub-batch when enough of them escape and none is large (a
-        // sub-batch of a few large matrices spreads each over so many
-        // workgroups that it runs slower than the single-matrix path: one
-        // 91,125-row matrix took 7 ms longer that way), else one by one;
+        // sub-batch when enough of them escape and none is large (a few
+        // large matrices run faster on the single-matrix path), else one by
+        // one;
         // then, for any that still escape, the Gershgorin interval and the
         // single-matrix path.
         const double tol = o->precision == KPM_FP64 ? 1e-9 : 1e-4;
